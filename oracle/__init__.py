@@ -1,0 +1,285 @@
+"""Python access to the plain-C double-precision oracle.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is a slow, obviously-correct CPU model of
+the batched neural-heuristic search (domains, network forward pass, output
+rules, reduced-precision emulation, serial IDA* and Budgeted Tree Search,
+training gradients).  Only the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import it; the library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+STP3, STP4, RUBIK = 0, 1, 2
+STATE_LEN = {STP3: 9, STP4: 16, RUBIK: 54}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # noqa: F401
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class HSpec(C.Structure):
+    _fields_ = [("kind", C.c_int), ("table8", C.POINTER(C.c_int32)), ("pdb_k", C.c_int),
+                ("pdb", C.POINTER(C.c_uint8))]
+
+
+class Iter(C.Structure):
+    _fields_ = [("bound", C.c_int32), ("expanded", C.c_int64), ("generated", C.c_int64),
+                ("complete", C.c_int32), ("found", C.c_int32), ("limit", C.c_int64)]
+
+
+def _declare(L):
+    vp = C.c_void_p
+    L.orc_apply_seq_batch.argtypes = [C.c_int, vp, C.c_int64, C.c_int, vp]
+    L.orc_apply.argtypes = [C.c_int, vp, C.c_int, vp]
+    L.orc_manhattan_batch.argtypes = [C.c_int, vp, C.c_int64, vp]
+    L.orc_bfs8.argtypes = [vp]
+    L.orc_bfs8.restype = C.c_int64
+    L.orc_all8.argtypes = [vp]
+    L.orc_all8.restype = C.c_int64
+    L.orc_perm9_rank.argtypes = [vp]
+    L.orc_perm9_rank.restype = C.c_int64
+    L.orc_corner_pdb.argtypes = [C.c_int, vp]
+    L.orc_corner_pdb.restype = C.c_int64
+    L.orc_corner_k_size.argtypes = [C.c_int]
+    L.orc_corner_k_size.restype = C.c_int64
+    L.orc_corner_k_index_batch.argtypes = [vp, C.c_int64, C.c_int, vp]
+    L.orc_bf16_round_array.argtypes = [vp, C.c_int64, vp]
+    L.orc_e4m3_round_array.argtypes = [vp, C.c_int64, vp]
+    L.orc_e4m3_decode.argtypes = [C.c_int]
+    L.orc_e4m3_decode.restype = C.c_double
+    L.orc_e4m3_encode.argtypes = [C.c_double]
+    L.orc_e4m3_encode.restype = C.c_int
+    L.orc_net_load.argtypes = [C.c_char_p]
+    L.orc_net_load.restype = vp
+    L.orc_net_free.argtypes = [vp]
+    L.orc_net_info.argtypes = [vp, vp]
+    L.orc_net_n_act.argtypes = [vp]
+    L.orc_net_forward.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp, vp]
+    L.orc_net_calibrate.argtypes = [vp, vp, C.c_int64, vp]
+    L.orc_net_fp8_col_scales.argtypes = [vp, C.c_int, vp]
+    L.orc_h_batch.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp]
+    L.orc_ida.argtypes = [C.c_int, vp, C.POINTER(HSpec), C.c_int, C.c_int, C.c_int64,
+                          C.POINTER(Iter), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
+    L.orc_bts.argtypes = [C.c_int, vp, C.POINTER(HSpec), C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
+                          C.c_int64, C.POINTER(Iter), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp,
+                          C.POINTER(C.c_int)]
+    if hasattr(L, "orc_train_grad"):
+        L.orc_train_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_double, vp, vp]
+        L.orc_train_grad.restype = C.c_double
+        L.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int]
+
+
+# ----------------------------------------------------------------- domains
+def goal(domain):
+    if domain == RUBIK:
+        return np.repeat(np.arange(6, dtype=np.uint8), 9)
+    n = 3 if domain == STP3 else 4
+    return np.arange(n * n, dtype=np.uint8)
+
+
+def apply(domain, state, move):
+    s = np.ascontiguousarray(state, dtype=np.uint8)
+    out = np.zeros_like(s)
+    ok = lib().orc_apply(domain, s.ctypes.data, int(move), out.ctypes.data)
+    return out if ok else None
+
+
+def apply_moves(domain, moves):
+    """moves: int array [count, L] padded with -1 (applied to the goal)."""
+    m = np.ascontiguousarray(moves, dtype=np.int8)
+    if m.ndim == 1:
+        m = m[None, :]
+    out = np.zeros((m.shape[0], STATE_LEN[domain]), dtype=np.uint8)
+    ok = lib().orc_apply_seq_batch(domain, m.ctypes.data, m.shape[0], m.shape[1], out.ctypes.data)
+    if not ok:
+        raise ValueError("invalid move sequence")
+    return out
+
+
+def manhattan(domain, states):
+    s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, STATE_LEN[domain])
+    out = np.zeros(s.shape[0], dtype=np.int32)
+    lib().orc_manhattan_batch(domain, s.ctypes.data, s.shape[0], out.ctypes.data)
+    return out
+
+
+def bfs8():
+    d = np.zeros(362880, dtype=np.int8)
+    n = lib().orc_bfs8(d.ctypes.data)
+    return d, n
+
+
+def all8():
+    out = np.zeros((181440, 9), dtype=np.uint8)
+    n = lib().orc_all8(out.ctypes.data)
+    return out[:n]
+
+
+def perm9_rank(states):
+    s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 9)
+    return np.array([lib().orc_perm9_rank(s[i].ctypes.data) for i in range(s.shape[0])], dtype=np.int64)
+
+
+def corner_pdb(k):
+    size = lib().orc_corner_k_size(k)
+    t = np.zeros(size, dtype=np.uint8)
+    reached = lib().orc_corner_pdb(k, t.ctypes.data)
+    return t, reached
+
+
+def corner_index(states, k):
+    s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 54)
+    out = np.zeros(s.shape[0], dtype=np.int64)
+    if not lib().orc_corner_k_index_batch(s.ctypes.data, s.shape[0], k, out.ctypes.data):
+        raise ValueError("not a valid cube state")
+    return out
+
+
+# ------------------------------------------------------------- rounding
+def bf16_round(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_bf16_round_array(x.ctypes.data, x.size, out.ctypes.data)
+    return out
+
+
+def e4m3_round(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_e4m3_round_array(x.ctypes.data, x.size, out.ctypes.data)
+    return out
+
+
+def e4m3_decode(code):
+    return lib().orc_e4m3_decode(int(code))
+
+
+def e4m3_encode(x):
+    return lib().orc_e4m3_encode(float(x))
+
+
+# ---------------------------------------------------------------- network
+class Net:
+    """Double-precision network loaded from a weight file."""
+
+    def __init__(self, path):
+        self._h = lib().orc_net_load(path.encode())
+        if not self._h:
+            raise ValueError(f"cannot load weights {path}")
+        info = np.zeros(16, dtype=np.int32)
+        lib().orc_net_info(self._h, info.ctypes.data)
+        self.domain, self.n_in, self.n_dense, self.n_res, self.n_out, self.head_kind, self.nt = map(int, info[:7])
+        self.dims = [int(v) for v in info[7:7 + self.n_dense]]
+        self.n_act = lib().orc_net_n_act(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_net_free(self._h)
+            self._h = None
+
+    def forward(self, states, mode=0, act_scale=None, want_act_max=False):
+        s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, STATE_LEN[self.domain])
+        y = np.zeros((s.shape[0], self.n_out), dtype=np.float64)
+        sc = None if act_scale is None else np.ascontiguousarray(act_scale, dtype=np.float64)
+        am = np.zeros(self.n_act, dtype=np.float64) if want_act_max else None
+        lib().orc_net_forward(self._h, s.ctypes.data, s.shape[0], mode,
+                              None if sc is None else sc.ctypes.data, y.ctypes.data,
+                              None if am is None else am.ctypes.data)
+        return (y, am) if want_act_max else y
+
+    def calibrate(self, states):
+        s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, STATE_LEN[self.domain])
+        out = np.zeros(self.n_act, dtype=np.float64)
+        lib().orc_net_calibrate(self._h, s.ctypes.data, s.shape[0], out.ctypes.data)
+        return out
+
+    def fp8_col_scales(self, tensor_index):
+        cols = None
+        # tensor shapes follow the file order; column count from dims
+        out = np.zeros(4096, dtype=np.float32)
+        lib().orc_net_fp8_col_scales(self._h, tensor_index, out.ctypes.data)
+        return out if cols is None else out[:cols]
+
+    def h(self, y, mode=0, q=0.99, offset=0.0, classic=None):
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1, self.n_out)
+        out = np.zeros(y.shape[0], dtype=np.int32)
+        cl = None if classic is None else np.ascontiguousarray(classic, dtype=np.int32)
+        lib().orc_h_batch(self._h, y.ctypes.data, y.shape[0], mode, q, offset,
+                          None if cl is None else cl.ctypes.data, out.ctypes.data)
+        return out
+
+
+# ----------------------------------------------------------------- search
+H_ZERO, H_MD, H_TABLE8, H_PDB = 0, 1, 2, 3
+
+
+def _hspec(kind, table8=None, pdb=None, pdb_k=0):
+    hs = HSpec()
+    hs.kind = kind
+    keep = []
+    if table8 is not None:
+        t = np.ascontiguousarray(table8, dtype=np.int32)
+        keep.append(t)
+        hs.table8 = _p(t, C.c_int32)
+    if pdb is not None:
+        keep.append(pdb)
+        hs.pdb = _p(pdb, C.c_uint8)
+        hs.pdb_k = pdb_k
+    return hs, keep
+
+
+def _iters(arr, n):
+    return [dict(bound=arr[i].bound, expanded=arr[i].expanded, generated=arr[i].generated,
+                 complete=arr[i].complete, found=arr[i].found, limit=arr[i].limit) for i in range(n)]
+
+
+def ida(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, complete_final=False,
+        max_iters=200, node_limit=-1):
+    hs, keep = _hspec(hkind, table8, pdb, pdb_k)
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (Iter * max_iters)()
+    n = C.c_int(0)
+    cost = C.c_int32(-1)
+    path = np.zeros(512, dtype=np.int8)
+    plen = C.c_int(0)
+    rc = lib().orc_ida(domain, s.ctypes.data, C.byref(hs), int(complete_final), max_iters, node_limit,
+                       arr, C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    del keep
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters(arr, n.value))
+
+
+def bts(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, b0=10000, c1=2, c2=8, plus_one=True,
+        max_iters=400, max_total=-1):
+    hs, keep = _hspec(hkind, table8, pdb, pdb_k)
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (Iter * max_iters)()
+    n = C.c_int(0)
+    cost = C.c_int32(-1)
+    path = np.zeros(512, dtype=np.int8)
+    plen = C.c_int(0)
+    rc = lib().orc_bts(domain, s.ctypes.data, C.byref(hs), b0, c1, c2, int(plus_one), max_iters, max_total,
+                       arr, C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    del keep
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters(arr, n.value))

@@ -1,0 +1,184 @@
+"""Pins of the oracle's domain models against facts fixed by mathematics.
+
+Sliding tile: the 8-puzzle's reachable half of S_9 and its known diameter;
+Manhattan distance admissible and consistent; walk-parity of the state graph;
+level counts of the parent-pruned tree from a blank-position recurrence.
+Rubik's cube: group identities, centre and colour invariants, and the
+closed-form level counts of the canonically pruned tree.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+def test_bfs8_reaches_half_the_permutations_with_diameter_31():
+    d, n = O.bfs8()
+    assert n == 181440  # 9!/2: exactly the even-parity half
+    assert d.max() == 31  # known 8-puzzle diameter for a corner-blank goal
+    assert (d >= 0).sum() == 181440
+
+
+def test_manhattan_is_admissible_and_consistent_on_all_8puzzle_states():
+    d, _ = O.bfs8()
+    st = O.all8()
+    md = O.manhattan(O.STP3, st)
+    dist = d[O.perm9_rank(st[:2000])]
+    assert np.all(md[:2000] <= dist)
+    ranks = np.array([O.lib().orc_perm9_rank(s.ctypes.data) for s in st], dtype=np.int64)
+    assert np.all(md <= d[ranks])
+    assert np.all((md % 2) == (d[ranks] % 2))  # both change parity with every move
+    # consistency: |MD(s) - MD(s')| == 1 across every edge
+    for s in st[::97]:
+        for m in range(4):
+            c = O.apply(O.STP3, s, m)
+            if c is not None:
+                assert abs(int(O.manhattan(O.STP3, c)[0]) - int(O.manhattan(O.STP3, s)[0])) == 1
+
+
+def test_walk_parity_and_bound():
+    d, _ = O.bfs8()
+    st = synth.stp3_instances(100)
+    s = synth.Stream(1000)
+    for i in range(100):
+        L = 30 + synth.Stream(1000 + i).next() % 31
+        r = O.lib().orc_perm9_rank(np.ascontiguousarray(st[i]).ctypes.data)
+        assert d[r] <= L and d[r] % 2 == L % 2
+    del s
+
+
+def _stp_level_counts(n, depth, blank=0):
+    """Number of parent-pruned move sequences of each length from a state with
+    the blank at `blank`, by dynamic programming over (blank cell, previous move)."""
+    moves = {0: (-1, 0), 1: (0, -1), 2: (0, 1), 3: (1, 0)}
+    cnt = {(blank, -1): 1}
+    out = []
+    for _ in range(depth):
+        nxt = {}
+        for (b, prev), c in cnt.items():
+            r, col = divmod(b, n)
+            for m, (dr, dc) in moves.items():
+                if prev >= 0 and m == 3 - prev:
+                    continue
+                rr, cc = r + dr, col + dc
+                if 0 <= rr < n and 0 <= cc < n:
+                    key = (rr * n + cc, m)
+                    nxt[key] = nxt.get(key, 0) + c
+        cnt = nxt
+        out.append(sum(cnt.values()))
+    return out
+
+
+def test_stp_zero_heuristic_counts_match_level_recurrence():
+    st = synth.stp_walks(4, [777], lengths=40)[0]
+    r = O.ida(O.STP4, st, hkind=O.H_ZERO, max_iters=9)
+    lv = _stp_level_counts(4, 10, blank=int(np.argmin(st)))
+    for it in r["iters"]:
+        T = it["bound"]
+        assert it["expanded"] == 1 + sum(lv[:T])
+        assert it["generated"] == sum(lv[:T + 1])
+
+
+def _rc_level_counts(depth):
+    a, b = 9, 9
+    out = [18]
+    for _ in range(depth - 1):
+        a, b = 6 * (a + b), 9 * a + 6 * b
+        out.append(a + b)
+    return out
+
+
+def test_rc_level_recurrence_values():
+    assert _rc_level_counts(6) == [18, 243, 3240, 43254, 577368, 7706988]
+
+
+def test_rc_zero_heuristic_counts_match_closed_form():
+    mv = synth.rc_walk_moves([4242], lengths=12)
+    st = O.apply_moves(O.RUBIK, np.array(mv, dtype=np.int8))[0]
+    r = O.ida(O.RUBIK, st, hkind=O.H_ZERO, max_iters=4, node_limit=-1)
+    lv = _rc_level_counts(5)
+    assert [it["bound"] for it in r["iters"]] == [0, 1, 2, 3]
+    for it in r["iters"]:
+        T = it["bound"]
+        assert it["expanded"] == 1 + sum(lv[:T])
+        assert it["generated"] == sum(lv[:T + 1])
+
+
+def _seq(ms):
+    return O.apply_moves(O.RUBIK, np.array(ms, dtype=np.int8))[0]
+
+
+def test_rc_group_identities():
+    g = O.goal(O.RUBIK)
+    for f in range(6):
+        cw, ccw, half = 3 * f, 3 * f + 1, 3 * f + 2
+        assert not np.array_equal(_seq([cw]), g)
+        assert np.array_equal(_seq([cw] * 4), g)
+        assert np.array_equal(_seq([cw, ccw]), g)
+        assert np.array_equal(_seq([cw, cw]), _seq([half]))
+        assert np.array_equal(_seq([half, half]), g)
+    R, Rp, U, Up = 9, 10, 0, 1
+    assert np.array_equal(_seq([R, U, Rp, Up] * 6), g)
+    assert not np.array_equal(_seq([R, U, Rp, Up] * 3), g)
+    cur = g
+    order = None
+    for k in range(1, 200):
+        cur = O.apply(O.RUBIK, O.apply(O.RUBIK, cur, R), U)
+        if np.array_equal(cur, g):
+            order = k
+            break
+    assert order == 105
+    # opposite faces commute, adjacent ones do not
+    assert np.array_equal(_seq([0, 3]), _seq([3, 0]))
+    assert not np.array_equal(_seq([0, 9]), _seq([9, 0]))
+
+
+def test_rc_invariants_under_random_walks():
+    mv = synth.rc_walk_moves_array(synth.config_seeds(3, 200), length_base=14, length_span=5)
+    st = O.apply_moves(O.RUBIK, mv)
+    for s in st:
+        assert [s[9 * f + 4] for f in range(6)] == list(range(6))
+        assert np.all(np.bincount(s, minlength=6) == 9)
+
+
+def test_rc_u_turn_moves_front_top_row_to_left():
+    # Looking down at U, a clockwise turn carries the front face's top row to
+    # the left face (standard Singmaster convention).
+    s = _seq([0])
+    assert list(s[18:21]) == [4, 4, 4]  # L top row now shows F's colour
+    assert list(s[36:39]) == [3, 3, 3]  # F top row now shows R's colour
+
+
+def test_corner_pdb_size_admissible_consistent():
+    k = 4
+    tab, reached = O.corner_pdb(k)
+    assert reached == 8 * 7 * 6 * 5 * 3 ** 4  # every placement and twist is reachable
+    assert tab[O.corner_index(O.goal(O.RUBIK), k)[0]] == 0
+    mv = synth.rc_walk_moves_array(synth.config_seeds(7, 300), length_base=1, length_span=8)
+    st = O.apply_moves(O.RUBIK, mv)
+    h = tab[O.corner_index(st, k)]
+    lengths = (mv >= 0).sum(axis=1)
+    assert np.all(h <= lengths)  # walk length bounds the true distance
+    for s in st[:60]:
+        hs = int(tab[O.corner_index(s, k)[0]])
+        for m in range(18):
+            c = O.apply(O.RUBIK, s, m)
+            assert abs(int(tab[O.corner_index(c, k)[0]]) - hs) <= 1
+
+
+def test_apply_rejects_off_board_moves():
+    g = O.goal(O.STP4)
+    assert O.apply(O.STP4, g, 0) is None  # blank at the top-left corner
+    assert O.apply(O.STP4, g, 1) is None
+    assert O.apply(O.STP4, g, 2) is not None
+    assert O.apply(O.STP4, g, 3) is not None
+
+
+def test_permutation_rank_is_a_bijection_on_small_sample():
+    seen = set()
+    for p in itertools.islice(itertools.permutations(range(9)), 5000):
+        seen.add(O.lib().orc_perm9_rank(np.array(p, dtype=np.uint8).ctypes.data))
+    assert len(seen) == 5000 and max(seen) < 362880

@@ -1,0 +1,108 @@
+"""Pins of the oracle's serial IDA* and Budgeted Tree Search.
+
+Optimal costs against breadth-first distances (8-puzzle, exhaustive table) and
+against brute-force search with a zero heuristic (cube); path validity;
+admissibility of min(floor(net), Manhattan); the BTS growth property.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+@pytest.fixture(scope="module")
+def bfs():
+    d, _ = O.bfs8()
+    return d
+
+
+def _rank(s):
+    return O.lib().orc_perm9_rank(np.ascontiguousarray(s, dtype=np.uint8).ctypes.data)
+
+
+def _follow(domain, start, path):
+    s = np.array(start, dtype=np.uint8)
+    for m in path:
+        s = O.apply(domain, s, m)
+        assert s is not None
+    return s
+
+
+def test_ida_manhattan_costs_equal_bfs_distances(bfs):
+    st = synth.stp3_instances(100)
+    for s in st:
+        r = O.ida(O.STP3, s, hkind=O.H_MD)
+        assert r["status"] == 1
+        assert r["cost"] == bfs[_rank(s)]
+        assert len(r["path"]) == r["cost"]
+        assert np.array_equal(_follow(O.STP3, s, r["path"]), O.goal(O.STP3))
+
+
+def test_ida_with_net_min_manhattan_is_optimal(bfs, net_files):
+    net = O.Net(net_files["stp3_small"])
+    allst = O.all8()
+    y = net.forward(allst)
+    h = net.h(y, 0, classic=O.manhattan(O.STP3, allst))
+    ranks = np.array([_rank(s) for s in allst])
+    table = np.zeros(362880, dtype=np.int32)
+    table[ranks] = h
+    assert np.all(h <= bfs[ranks])  # admissible on every state
+    for s in synth.stp3_instances(100):
+        r = O.ida(O.STP3, s, hkind=O.H_TABLE8, table8=table)
+        assert r["cost"] == bfs[_rank(s)]
+
+
+def test_ida_iteration_bounds_increase_and_complete_final_counts_dominate(bfs):
+    for s in synth.stp3_instances(20):
+        a = O.ida(O.STP3, s, hkind=O.H_MD)
+        b = O.ida(O.STP3, s, hkind=O.H_MD, complete_final=True)
+        assert [i["bound"] for i in a["iters"]] == [i["bound"] for i in b["iters"]]
+        bounds = [i["bound"] for i in a["iters"]]
+        assert all(x < y for x, y in zip(bounds, bounds[1:]))
+        for x, y in zip(a["iters"][:-1], b["iters"][:-1]):
+            assert (x["expanded"], x["generated"]) == (y["expanded"], y["generated"])
+        assert a["iters"][-1]["expanded"] <= b["iters"][-1]["expanded"]
+        assert b["cost"] == a["cost"]
+
+
+def test_rc_corner_pdb_ida_matches_brute_force():
+    tab, _ = O.corner_pdb(4)
+    mv = synth.rc_walk_moves_array(synth.config_seeds(8, 12), length_base=2, length_span=4)
+    st = O.apply_moves(O.RUBIK, mv)
+    for s, m in zip(st, mv):
+        a = O.ida(O.RUBIK, s, hkind=O.H_PDB, pdb=tab, pdb_k=4)
+        b = O.ida(O.RUBIK, s, hkind=O.H_ZERO)
+        assert a["cost"] == b["cost"] <= (m >= 0).sum()
+        assert np.array_equal(_follow(O.RUBIK, s, a["path"]), O.goal(O.RUBIK))
+
+
+def test_stp4_walk_costs_respect_parity_and_length():
+    st = synth.stp_walks(4, range(10), lengths=30)
+    for s in st:
+        r = O.ida(O.STP4, s, hkind=O.H_MD)
+        assert r["status"] == 1 and r["cost"] <= 30 and r["cost"] % 2 == 0
+
+
+def test_bts_finds_optimal_costs(bfs):
+    for s in synth.stp3_instances(40):
+        for b0 in (1, 50, 10000):
+            r = O.bts(O.STP3, s, hkind=O.H_MD, b0=b0)
+            assert r["status"] == 1 and r["cost"] == bfs[_rank(s)]
+            assert np.array_equal(_follow(O.STP3, s, r["path"]), O.goal(O.STP3))
+
+
+def test_bts_accepted_iterations_grow_geometrically():
+    st = synth.stp_walks(4, range(6), lengths=44)
+    for s in st:
+        r = O.bts(O.STP4, s, hkind=O.H_MD, b0=1, c1=2, c2=8)
+        assert r["status"] == 1
+        it = r["iters"]
+        # every limited search respects its limit when it reports completion
+        for i in it:
+            if i["limit"] >= 0 and i["complete"]:
+                assert i["expanded"] <= i["limit"]
+            if not i["complete"]:
+                assert i["expanded"] == i["limit"]
+        ida = O.ida(O.STP4, s, hkind=O.H_MD)
+        assert r["cost"] == ida["cost"]
