@@ -1,0 +1,270 @@
+/* hb.h — C ABI of the batched neural-heuristic search library for MI355X (gfx950).
+ *
+ * The library implements the data-parallel hot path of parallel cost-bounded
+ * depth-first search (CB-DFS) with a neural heuristic, as described in
+ * "A Parallel CPU-GPU Framework for Batching Heuristic Operations in
+ * Depth-First Heuristic Search" (Futuhi & Sturtevant): CPU search threads park
+ * the states they generate in shared batches; a batch thread copies each batch
+ * to the GPU, evaluates the network h_M on it with hand-written HIP kernels and
+ * hands the heuristic values back (section "SingleGPU Batch CB-DFS").
+ *
+ * Conventions for every entry point:
+ *  - Every call returns hb_status (0 = HB_OK, negative = error) and never
+ *    throws across the ABI.  On error, hb_last_error() describes the cause.
+ *  - Sizes are int64_t element counts; n == 0 is valid and does nothing.
+ *  - "Host" pointers are ordinary CPU memory; "device" pointers are GPU memory
+ *    (for example a torch tensor's data_ptr()).  The caller owns every buffer
+ *    it passes in, unless stated otherwise.
+ *  - Streams are hipStream_t passed as void*; NULL means the default stream.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status */
+typedef enum {
+    HB_OK = 0,
+    HB_E_INVAL = -1,        /* bad argument or invalid state */
+    HB_E_NOMEM = -2,        /* host or device allocation failed */
+    HB_E_DEVICE = -3,       /* a HIP call or kernel launch failed */
+    HB_E_UNSUPPORTED = -4,  /* valid request that this build does not support */
+    HB_E_BUDGET = -5,       /* node or time limit reached; statistics are valid */
+    HB_E_NOSOLUTION = -6    /* the search space holds no solution */
+} hb_status;
+
+/* Description of the last error raised on the calling thread.  Valid until the
+ * thread's next hb_* call.  Never NULL. */
+const char* hb_last_error(void);
+
+/* ------------------------------------------------------------- domains */
+/* The paper's two domains (Experimental Setup) plus the 8-puzzle.
+ * Unit edge costs (the problem tuple {G, s, g, c, h} of the Background
+ * section with c = 1).
+ *  HB_STP3 / HB_STP4: n x n sliding tile.  State = n*n bytes, byte p = tile at
+ *    cell p (row-major), 0 = blank.  Goal: tile p at cell p.  Moves move the
+ *    blank: 0 up, 1 left, 2 right, 3 down; a move never undoes the previous one
+ *    (path information that stops the search returning to the parent).
+ *  HB_RUBIK3: 3x3x3 cube, 54 stickers, sticker p = 9*f + 3*r + c on face
+ *    f in (U, D, L, R, F, B); byte p = colour 0..5 (the face index of the
+ *    colour's home face).  Face frames (x: L->R, y: D->U, z: B->F): row r and
+ *    column c of face f run along v and u with U (u=+x, v=+z), D (+x, -z),
+ *    L (+z, -y), R (-z, -y), F (+x, -y), B (-x, -y).  Move m turns face m/3
+ *    clockwise (seen from outside), counter-clockwise or by a half turn for
+ *    m%3 = 0, 1, 2.  Canonical pruning: never the same face twice in a row and
+ *    never U, L or F directly after D, R or B.                               */
+typedef enum { HB_STP3 = 0, HB_STP4 = 1, HB_RUBIK3 = 2 } hb_domain;
+
+int hb_state_bytes(hb_domain d);   /* 9, 16, 54; -1 for an unknown domain */
+int hb_packed_bytes(hb_domain d);  /* 8, 8, 24;  -1 for an unknown domain */
+
+/* TensorRepresentation of a state (Subtree expansion algorithm): the packed
+ * record that is parked in a batch and decoded on the GPU into the one-hot
+ * network input.  Sliding tile: 4 bits per cell, cell p in bits 4p..4p+3 of one
+ * little-endian uint64.  Cube: the 48 non-centre stickers in increasing index
+ * order, 3 bits each, sticker q in bits 3*(q%16) of uint64 word q/16 (3 words).
+ * states: host, n * hb_state_bytes; packed_out: host, n * hb_packed_bytes.
+ * Each state is validated (a permutation of the tiles / nine stickers of each
+ * colour with the centres in place); the first bad index is reported through
+ * HB_E_INVAL and hb_last_error, and nothing after it is written. */
+hb_status hb_encode(hb_domain d, const uint8_t* states, int64_t n, uint8_t* packed_out);
+/* Inverse of hb_encode (host buffers). */
+hb_status hb_decode(hb_domain d, const uint8_t* packed, int64_t n, uint8_t* states_out);
+
+/* env.ApplyAction of the subtree-expansion algorithm, for building inputs:
+ * applies rows of `len` moves (a negative move ends a row) to the goal state.
+ * moves: host int8 [count][len]; states_out: host [count][hb_state_bytes].
+ * HB_E_INVAL if a move is out of range or pushes the blank off the board. */
+hb_status hb_apply_moves(hb_domain d, const int8_t* moves, int64_t count, int32_t len, uint8_t* states_out);
+
+/* Manhattan distance of sliding-tile states (host in, host int32 out). */
+hb_status hb_manhattan(hb_domain d, const uint8_t* states, int64_t n, int32_t* out);
+
+/* ---------------------------------------------------- pattern databases */
+/* Corner pattern database of the cube (the paper's classic heuristic for the
+ * cube is an 8-corner PDB, Experimental Setup): the breadth-first distance of
+ * the placement and twist of the first k corner cubies, 1 <= k <= 8.  Built on
+ * the host with `threads` threads (<= 0: all cores).  Owned by the library. */
+typedef struct hb_pdb hb_pdb;
+hb_status hb_pdb_build_corner(int k, int threads, hb_pdb** out);
+hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out); /* host */
+void hb_pdb_free(hb_pdb* pdb); /* NULL-safe */
+
+/* --------------------------------------------------------------- model */
+/* Operand precision of the matrix layers; accumulation is always FP32.
+ *  HB_FP32: float32 weights and activations.
+ *  HB_BF16: bfloat16 (round to nearest even) weights and activations.
+ *  HB_FP8_E4M3: OCP e4m3 dense/residual weights with one FP32 scale per output
+ *    column (max|W[:,n]| / 448) and e4m3 activations with one static
+ *    power-of-two scale per tensor (hb_model_calibrate); layer 1 and head
+ *    weights in bfloat16. */
+typedef enum { HB_FP32 = 0, HB_BF16 = 1, HB_FP8_E4M3 = 2 } hb_precision;
+
+/* Output rule applied in the kernel epilogue.
+ *  Regression (one output y): v = y - offset; FLOOR: h = floor(v); ROUND:
+ *  round half to even; REAL: h = floor(v) and raw_out = v.  h is clamped at 0
+ *  and, with combine_md, replaced by min(h, Manhattan distance).
+ *  Classifier (n_out classes): QUANTILE: the smallest class whose cumulative
+ *  softmax probability is >= q (the last class if none); ARGMAX: the highest
+ *  logit, lowest index on ties.  Softmax, sums and comparisons in FP32.
+ *  A non-finite network output yields h = Manhattan distance with combine_md,
+ *  else 0. */
+typedef enum {
+    HB_OUT_REG_FLOOR = 0, HB_OUT_REG_ROUND = 1, HB_OUT_REG_REAL = 2,
+    HB_OUT_CLS_QUANTILE = 3, HB_OUT_CLS_ARGMAX = 4
+} hb_out_mode;
+
+typedef struct {
+    hb_precision prec;
+    int device;          /* HIP device ordinal */
+    hb_out_mode out;
+    float q;             /* classifier quantile, e.g. 0.99 */
+    float offset;        /* regression offset, e.g. 2.2 */
+    int combine_md;      /* sliding tile: h = min(h, Manhattan distance) */
+    int max_batch;       /* largest n per launch; larger calls are split (0: 16384) */
+} hb_model_opts;
+
+typedef struct hb_model hb_model;
+
+/* Load a weight file and upload it to `device`.
+ * File (little-endian): u32 magic "HBW1", u32 version 1, u32 domain, u32 n_in,
+ * u32 n_dense, u32 dims[n_dense], u32 n_res, u32 n_out, u32 head_kind (0
+ * regression, 1 classifier), then float32 tensors: for each dense layer W
+ * [in][out] row-major and b[out]; for each residual block W_a, b_a, W_b, b_b;
+ * then the head W, b.  Layer 1 is the one-hot layer (n_in = cells * symbols,
+ * input index p*S + s[p]); every hidden layer is followed by ReLU; a residual
+ * block computes x <- ReLU(x + W_b ReLU(W_a x + b_a) + b_b).
+ * opts NULL = {FP32, device 0, FLOOR, 0.99, 0, 0, 16384}. */
+hb_status hb_model_load(const char* weights_path, const hb_model_opts* opts, hb_model** out);
+void hb_model_free(hb_model* m); /* NULL-safe; synchronises the model's device work first */
+
+typedef struct {
+    int domain, n_in, n_dense, n_res, n_out, head_kind, n_act, prec;
+    int dims[8];
+    int64_t weight_bytes;   /* device bytes of the weights in the model's precision */
+    double flops_per_eval;  /* algorithmic FLOPs per state: 2*K*N per matrix layer plus one add per gathered row element */
+} hb_model_info;
+hb_status hb_model_get_info(const hb_model* m, hb_model_info* out);
+
+/* FP8 only: derive the static activation scales from a calibration batch.
+ * Runs the FP32 network on d_packed (device, n packed states) and sets, per
+ * stored activation tensor, the smallest power of two a with max|x| / a <= 448.
+ * Synchronous.  Must be called before hb_eval_batch on an FP8 model. */
+hb_status hb_model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n);
+/* Read or set the activation scales (n_act floats, host). */
+hb_status hb_model_get_act_scales(const hb_model* m, float* out, int cap);
+hb_status hb_model_set_act_scales(hb_model* m, const float* scales, int n);
+
+/* Batched heuristic evaluation (ProcessBatch step 2 of SingleGPU Batch CB-DFS).
+ * d_packed: device, n * hb_packed_bytes (hb_encode layout).
+ * d_h_out:  device int32[n], the heuristic per state.
+ * d_raw_out: device float[n * n_out] or NULL: the network output (regression
+ *   value minus offset, or the logits).
+ * Asynchronous on `stream`; the caller keeps the buffers alive until the stream
+ * is synchronised.  Calls on distinct streams may run concurrently: each
+ * stream gets its own activation workspace. */
+hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
+                        float* d_raw_out, void* stream);
+
+/* Persistent, capture-friendly variant: the state count is read on the device
+ * from *d_n (int32, 0 <= *d_n <= max_n) so one launch shape (sized for max_n)
+ * serves every batch size; suitable for hipGraph capture. */
+hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_t* d_n, int64_t max_n,
+                              int32_t* d_h_out, float* d_raw_out, void* stream);
+
+/* Select the GEMM tile shape (0 = automatic) used by later evaluations on this
+ * model; see hb_model_tune. */
+hb_status hb_model_set_tile(hb_model* m, int tile_id);
+/* Autotuner: times every tile shape on n seeded states and keeps the fastest
+ * for batches of about that size.  Results (tile id, microseconds) are written
+ * to `report` (host, cap entries) if non-NULL. */
+hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
+
+/* -------------------------------------------------------------- search */
+typedef enum { HB_IDA = 0, HB_BTS = 1 } hb_algo;
+
+/* How the search obtains h for pruning:
+ *  HB_H_NN:          the network's h (model output rule, GPU batches).
+ *  HB_H_MIN_NN_CLASSIC: min(network h, classic h).
+ *  HB_H_FIXED_TREE:  the network is evaluated on every generated state (GPU
+ *                    batches) but pruning uses the classic h, so the tree is the
+ *                    classic heuristic's (Fixed-Tree Evaluation).
+ *  HB_H_CLASSIC:     classic h only, computed at generation (no network).
+ *  HB_H_CLASSIC_BATCHED: classic h computed by the batch thread on the host,
+ *                    through the same batching machinery (no GPU needed). */
+typedef enum {
+    HB_H_NN = 0, HB_H_MIN_NN_CLASSIC = 1, HB_H_FIXED_TREE = 2, HB_H_CLASSIC = 3, HB_H_CLASSIC_BATCHED = 4
+} hb_combine;
+
+typedef enum { HB_CLASSIC_ZERO = 0, HB_CLASSIC_MD = 1, HB_CLASSIC_PDB = 2 } hb_classic;
+
+typedef struct {
+    hb_model* model;       /* required unless combine is CLASSIC or CLASSIC_BATCHED */
+    hb_combine combine;
+    hb_classic classic;
+    const hb_pdb* pdb;     /* for HB_CLASSIC_PDB */
+} hb_heuristic;
+
+typedef struct {
+    int batch_size;        /* states per batch (default 8000) */
+    int work_num;          /* subtrees per search thread, workNum (default 8) */
+    int d_init;            /* depth of the initial partitioning tree (default: chosen from threads*work_num) */
+    int timeout_us;        /* partial-batch flush timeout (default 4000, the paper's 4 ms) */
+    int n_slabs;           /* batch buffers kept in host memory (default 4) */
+    int flush_when_idle;   /* also flush as soon as every search thread waits on h (default 1) */
+    int64_t node_limit;    /* total expansions (<= 0: none) */
+    double time_limit_s;   /* wall limit (<= 0: none) */
+    int64_t bts_b0;        /* BTS first budget (default 10000) */
+    int bts_c1, bts_c2;    /* BTS growth window (defaults 2 and 8) */
+    int bts_root_plus_one; /* BTS first bound h(root)+1 (default 1) */
+    int dedup_frontier;    /* remove duplicate frontier states after partitioning (default 0) */
+    int complete_final_iter; /* finish the final iteration (default 0) */
+    int32_t start_bound;   /* resume from this bound (< 0: h(start)) */
+    int max_iters;         /* safety cap on iterations (default 1000) */
+} cbdfs_params;
+
+/* Fill p with the defaults listed above. */
+void cbdfs_params_default(cbdfs_params* p);
+
+typedef struct {
+    int32_t bound;
+    int64_t limit;         /* expansion limit of this search (< 0: none) */
+    int64_t expanded, generated;
+    int32_t complete;      /* 1: the iteration ran to completion */
+    int32_t found;
+} cbdfs_iter;
+
+typedef struct {
+    int32_t cost;          /* -1 if none */
+    int32_t path_len;
+    int8_t* path;          /* library-owned: moves from start to goal */
+    int32_t n_iter;
+    cbdfs_iter* iters;     /* library-owned */
+    int64_t evals;         /* heuristic evaluations (network or batched classic) */
+    int64_t batches;
+    double mean_batch;
+    double wall_s, gpu_busy_s;
+    int64_t expanded, generated; /* totals over every iteration */
+    int32_t frontier;      /* work units after the initial partitioning */
+    int64_t peak_nodes;    /* most node records live at once */
+} cbdfs_result;
+
+/* Batch IDA* (Batch IDA* algorithm) or Batch BTS (Batch BTS enhancements) over
+ * parallel CB-DFS (Parallel CB-DFS and Subtree expansion algorithms) with
+ * `threads` search threads and one batch thread.  start: host state
+ * (hb_state_bytes).  Invalid or unsolvable starts -> HB_E_INVAL before any
+ * thread starts; limits -> HB_E_BUDGET with statistics; a device failure ->
+ * HB_E_DEVICE after every thread has joined.  Release out with
+ * cbdfs_result_free. */
+hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, hb_algo algo, int threads,
+                      const cbdfs_params* p, cbdfs_result* out);
+void cbdfs_result_free(cbdfs_result* r); /* NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HB_H */

@@ -1,0 +1,205 @@
+// C ABI entry points (include/hb.h): argument checks, error text, dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+#include "domain.hpp"
+#include "hb.h"
+#include "kernels.hpp"
+#include "model.hpp"
+
+namespace hb {
+
+static thread_local std::string g_err = "no error";
+
+hb_status fail(hb_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err = "no error"; }
+
+}  // namespace hb
+
+using namespace hb;
+
+extern "C" {
+
+const char* hb_last_error(void) { return g_err.c_str(); }
+
+int hb_state_bytes(hb_domain d) {
+    const Domain* D = domain_of(d);
+    return D ? D->state_bytes : -1;
+}
+
+int hb_packed_bytes(hb_domain d) {
+    const Domain* D = domain_of(d);
+    return D ? D->packed_bytes : -1;
+}
+
+hb_status hb_encode(hb_domain d, const uint8_t* states, int64_t n, uint8_t* packed_out) {
+    const Domain* D = domain_of(d);
+    if (!D) return fail(HB_E_INVAL, "unknown domain %d", (int)d);
+    if (n < 0 || (n > 0 && (!states || !packed_out))) return fail(HB_E_INVAL, "bad buffers or count");
+    for (int64_t i = 0; i < n; i++) {
+        const char* why = "";
+        if (!valid_state(*D, states + i * D->state_bytes, &why))
+            return fail(HB_E_INVAL, "state %lld: %s", (long long)i, why);
+        encode(*D, states + i * D->state_bytes, packed_out + i * D->packed_bytes);
+    }
+    return HB_OK;
+}
+
+hb_status hb_decode(hb_domain d, const uint8_t* packed, int64_t n, uint8_t* states_out) {
+    const Domain* D = domain_of(d);
+    if (!D) return fail(HB_E_INVAL, "unknown domain %d", (int)d);
+    if (n < 0 || (n > 0 && (!packed || !states_out))) return fail(HB_E_INVAL, "bad buffers or count");
+    for (int64_t i = 0; i < n; i++) decode(*D, packed + i * D->packed_bytes, states_out + i * D->state_bytes);
+    return HB_OK;
+}
+
+hb_status hb_apply_moves(hb_domain d, const int8_t* moves, int64_t count, int32_t len, uint8_t* states_out) {
+    const Domain* D = domain_of(d);
+    if (!D) return fail(HB_E_INVAL, "unknown domain %d", (int)d);
+    if (count < 0 || len < 0 || (count > 0 && (!states_out || (len > 0 && !moves))))
+        return fail(HB_E_INVAL, "bad buffers or count");
+    uint8_t cur[kMaxStateBytes], nxt[kMaxStateBytes];
+    for (int64_t i = 0; i < count; i++) {
+        goal_state(*D, cur);
+        for (int j = 0; j < len; j++) {
+            const int m = moves[i * len + j];
+            if (m < 0) break;
+            if (!apply_move(*D, cur, m, nxt))
+                return fail(HB_E_INVAL, "row %lld move %d (%d) is not applicable", (long long)i, j, m);
+            std::memcpy(cur, nxt, (size_t)D->state_bytes);
+        }
+        std::memcpy(states_out + i * D->state_bytes, cur, (size_t)D->state_bytes);
+    }
+    return HB_OK;
+}
+
+hb_status hb_manhattan(hb_domain d, const uint8_t* states, int64_t n, int32_t* out) {
+    const Domain* D = domain_of(d);
+    if (!D || D->id == HB_RUBIK3) return fail(HB_E_INVAL, "Manhattan distance needs a sliding-tile domain");
+    if (n < 0 || (n > 0 && (!states || !out))) return fail(HB_E_INVAL, "bad buffers or count");
+    for (int64_t i = 0; i < n; i++) out[i] = manhattan(*D, states + i * D->state_bytes);
+    return HB_OK;
+}
+
+hb_status hb_pdb_build_corner(int k, int threads, hb_pdb** out) {
+    if (!out) return fail(HB_E_INVAL, "null output");
+    if (k < 1 || k > 8) return fail(HB_E_INVAL, "k must be in 1..8");
+    hb_pdb* p = new (std::nothrow) hb_pdb;
+    if (!p) return fail(HB_E_NOMEM, "pdb");
+    try {
+        if (!corner_pdb_build(k, threads, &p->corner)) { delete p; return fail(HB_E_INVAL, "bad k"); }
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(HB_E_NOMEM, "pattern database table");
+    }
+    *out = p;
+    return HB_OK;
+}
+
+hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out) {
+    if (!pdb) return fail(HB_E_INVAL, "null pdb");
+    if (n < 0 || (n > 0 && (!states || !out))) return fail(HB_E_INVAL, "bad buffers or count");
+    const Domain* D = domain_of(HB_RUBIK3);
+    for (int64_t i = 0; i < n; i++) {
+        const char* why = "";
+        if (!valid_state(*D, states + i * 54, &why)) return fail(HB_E_INVAL, "state %lld: %s", (long long)i, why);
+        out[i] = pdb->corner.lookup(states + i * 54);
+    }
+    return HB_OK;
+}
+
+void hb_pdb_free(hb_pdb* pdb) { delete pdb; }
+
+hb_status hb_model_load(const char* weights_path, const hb_model_opts* opts, hb_model** out) {
+    if (!weights_path || !out) return fail(HB_E_INVAL, "null path or output");
+    hb_model_opts o{HB_FP32, 0, HB_OUT_REG_FLOOR, 0.99f, 0.f, 0, 16384};
+    if (opts) o = *opts;
+    if (o.max_batch < 0 || o.max_batch > (1 << 22)) return fail(HB_E_INVAL, "max_batch out of range");
+    try {
+        return model_load(weights_path, o, out);
+    } catch (const std::bad_alloc&) {
+        return fail(HB_E_NOMEM, "host allocation while loading the model");
+    }
+}
+
+void hb_model_free(hb_model* m) { model_free(m); }
+
+hb_status hb_model_get_info(const hb_model* m, hb_model_info* out) {
+    if (!m || !out) return fail(HB_E_INVAL, "null argument");
+    std::memset(out, 0, sizeof *out);
+    out->domain = m->spec.domain;
+    out->n_in = m->spec.n_in;
+    out->n_dense = (int)m->spec.dims.size();
+    out->n_res = m->spec.n_res;
+    out->n_out = m->spec.n_out;
+    out->head_kind = m->spec.head_kind;
+    out->n_act = m->n_act;
+    out->prec = (int)m->opts.prec;
+    for (int i = 0; i < out->n_dense && i < 8; i++) out->dims[i] = m->spec.dims[i];
+    out->weight_bytes = m->weight_bytes;
+    out->flops_per_eval = m->flops;
+    return HB_OK;
+}
+
+hb_status hb_model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n) {
+    if (!m || (n > 0 && !d_packed)) return fail(HB_E_INVAL, "null argument");
+    return model_calibrate(m, d_packed, n);
+}
+
+hb_status hb_model_get_act_scales(const hb_model* m, float* out, int cap) {
+    if (!m || !out || cap < m->n_act) return fail(HB_E_INVAL, "need room for %d scales", m ? m->n_act : 0);
+    for (int a = 0; a < m->n_act; a++) out[a] = m->act_scale[a];
+    return HB_OK;
+}
+
+hb_status hb_model_set_act_scales(hb_model* m, const float* scales, int n) {
+    if (!m || !scales || n != m->n_act) return fail(HB_E_INVAL, "expected %d scales", m ? m->n_act : 0);
+    for (int a = 0; a < n; a++)
+        if (!(scales[a] > 0.f) || !std::isfinite(scales[a])) return fail(HB_E_INVAL, "scale %d is not positive", a);
+    for (int a = 0; a < n; a++) m->act_scale[a] = scales[a];
+    m->calibrated = true;
+    return HB_OK;
+}
+
+hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out, float* d_raw_out,
+                        void* stream) {
+    if (!m) return fail(HB_E_INVAL, "null model");
+    if (n < 0) return fail(HB_E_INVAL, "negative count");
+    if (n == 0) return HB_OK;
+    if (!d_packed || !d_h_out) return fail(HB_E_INVAL, "null device buffer");
+    return model_eval(m, d_packed, n, nullptr, 0, d_h_out, d_raw_out, (hipStream_t)stream, nullptr);
+}
+
+hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_t* d_n, int64_t max_n,
+                              int32_t* d_h_out, float* d_raw_out, void* stream) {
+    if (!m || !d_n || !d_packed || !d_h_out) return fail(HB_E_INVAL, "null argument");
+    if (max_n < 0) return fail(HB_E_INVAL, "negative max_n");
+    return model_eval(m, d_packed, 0, d_n, max_n, d_h_out, d_raw_out, (hipStream_t)stream, nullptr);
+}
+
+hb_status hb_model_set_tile(hb_model* m, int tile_id) {
+    if (!m || tile_id < 0 || tile_id > gemm_tile_count()) return fail(HB_E_INVAL, "tile id out of range");
+    m->tile = tile_id;
+    return HB_OK;
+}
+
+hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap) {
+    if (!m || !d_packed) return fail(HB_E_INVAL, "null argument");
+    return model_tune(m, d_packed, n, report, cap);
+}
+
+}  // extern "C"

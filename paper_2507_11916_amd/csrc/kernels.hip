@@ -1,0 +1,549 @@
+// HIP kernels of the heuristic network for gfx950 (CDNA4).
+//
+// Forward pass of h_M over a batch of packed states (ProcessBatch step 2 of
+// SingleGPU Batch CB-DFS):
+//   gather_l1   decode packed states, layer 1 as a gather-sum of weight rows
+//               (the one-hot input is never materialised), bias, ReLU, cast;
+//   gemm        dense / residual layers on MFMA with LDS-staged tiles and a
+//               fused epilogue (column scale, bias, residual, ReLU, cast);
+//   head        output layer and the output rule (floor / round / real,
+//               Manhattan minimum; softmax-quantile / arg-max).
+// Every kernel computes each row independently and in a fixed order, so a
+// state's heuristic does not depend on the batch it is evaluated in.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace hb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------ conversions
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// OCP e4m3, round to nearest even, saturating at +-448.  The hardware
+// conversion rounds to nearest even but maps overflow to NaN, so the value is
+// clamped first.
+__device__ __forceinline__ uint32_t f32x2_to_fp8x2(float a, float b) {
+    a = fminf(fmaxf(a, -448.f), 448.f);
+    b = fminf(fmaxf(b, -448.f), 448.f);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
+}
+
+__device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)byte, 0);
+}
+
+// ------------------------------------------------------------ decoding
+// Symbol of cell/sticker row g of the folded layer-1 table.  Sliding tile:
+// P cells, symbol = tile; row = p * S + tile.  Cube: 48 non-centre stickers,
+// row = q * 6 + colour (the centres are folded into the bias).
+template <int DOM>
+struct Dec;
+// Symbols are clamped to S - 1 so that a corrupt record cannot index past the
+// table (hb_encode never produces one).
+template <>
+struct Dec<0> {  // 3x3
+    static constexpr int P = 9, S = 9, WORDS = 1;
+    __device__ static int row(const uint64_t* w, int p) { return p * S + min((int)((w[0] >> (4 * p)) & 15), S - 1); }
+};
+template <>
+struct Dec<1> {  // 4x4
+    static constexpr int P = 16, S = 16, WORDS = 1;
+    __device__ static int row(const uint64_t* w, int p) { return p * S + (int)((w[0] >> (4 * p)) & 15); }
+};
+template <>
+struct Dec<2> {  // cube
+    static constexpr int P = 48, S = 6, WORDS = 3;
+    __device__ static int row(const uint64_t* w, int q) {
+        return q * S + min((int)((w[q >> 4] >> (3 * (q & 15))) & 7), S - 1);
+    }
+};
+
+// ------------------------------------------------------------ layer 1
+// One block of 256 threads handles ROWS states; thread t owns four
+// consecutive columns per 1024-column slab.  Rows >= n are written as zeros.
+template <int DOM, int WT /*0 f32, 1 bf16 table*/, int OUT /*0 f32, 1 bf16, 2 fp8*/>
+__global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restrict__ packed, const int32_t* n_dev,
+                                                        int n_host, int m_rows, const void* __restrict__ table,
+                                                        const float* __restrict__ bias, int N, int ld_out,
+                                                        void* __restrict__ out, float out_inv_scale) {
+    using D = Dec<DOM>;
+    constexpr int ROWS = 8;
+    const int n = min(n_dev ? *n_dev : n_host, m_rows);
+    const int r0 = blockIdx.x * ROWS;
+    for (int rr = 0; rr < ROWS; rr++) {
+        const int r = r0 + rr;
+        if (r >= m_rows) return;
+        uint64_t w[D::WORDS];
+        const bool live = r < n;
+        if (live)
+            for (int i = 0; i < D::WORDS; i++) w[i] = packed[(size_t)r * D::WORDS + i];
+        for (int c = threadIdx.x * 4; c < N; c += 1024) {
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            if (live) {
+                const float4 b = *reinterpret_cast<const float4*>(bias + c);
+                acc[0] = b.x; acc[1] = b.y; acc[2] = b.z; acc[3] = b.w;
+                for (int p = 0; p < D::P; p++) {
+                    const size_t g = (size_t)D::row(w, p) * N + c;
+                    if (WT == 0) {
+                        const float4 v = *reinterpret_cast<const float4*>((const float*)table + g);
+                        acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
+                    } else {
+                        const uint2 v = *reinterpret_cast<const uint2*>((const uint16_t*)table + g);
+                        acc[0] += bf16_to_f32((uint16_t)(v.x & 0xFFFF));
+                        acc[1] += bf16_to_f32((uint16_t)(v.x >> 16));
+                        acc[2] += bf16_to_f32((uint16_t)(v.y & 0xFFFF));
+                        acc[3] += bf16_to_f32((uint16_t)(v.y >> 16));
+                    }
+                }
+                for (int i = 0; i < 4; i++) acc[i] = fmaxf(acc[i], 0.f);
+            }
+            const size_t o = (size_t)r * ld_out + c;
+            if (OUT == 0) {
+                *reinterpret_cast<float4*>((float*)out + o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else if (OUT == 1) {
+                uint2 v;
+                v.x = (uint32_t)f32_to_bf16(acc[0]) | ((uint32_t)f32_to_bf16(acc[1]) << 16);
+                v.y = (uint32_t)f32_to_bf16(acc[2]) | ((uint32_t)f32_to_bf16(acc[3]) << 16);
+                *reinterpret_cast<uint2*>((uint16_t*)out + o) = v;
+            } else {
+                const uint32_t lo = f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale);
+                const uint32_t hi = f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale);
+                *reinterpret_cast<uint32_t*>((uint8_t*)out + o) = lo | (hi << 16);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ GEMM
+// C[M][N] = epi(A[M][K] * B[K][N]) with A row-major (activations) and B given
+// transposed, Bt[N][K] (weights, K contiguous).  Block tile BM x BN, 4 waves in
+// a 2 x 2 grid, each wave (BM/2) x (BN/2) built from 32x32 MFMA tiles.  Each
+// K stage moves 128 bytes of every A and Bt row through LDS (double-buffered);
+// 16-byte chunks are XOR-swizzled by row so that both the global->LDS stores
+// and the MFMA operand reads are free of bank conflicts.
+//   PREC 0: fp32, v_mfma_f32_32x32x2_f32 (a lane reads 4 K values, one per MFMA);
+//   PREC 1: bf16, v_mfma_f32_32x32x16_bf16 (8 K values per lane);
+//   PREC 2: fp8,  v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales
+//           (32 K values per lane; column/tensor scales in the epilogue).
+// A and Bt use the same per-lane K assignment, so every K index is paired
+// once with itself.
+struct GemmArgs {
+    const uint8_t* A;
+    const uint8_t* Bt;
+    uint8_t* C;
+    const uint8_t* R;        // residual (same type and layout as C) or null
+    const float* bias;       // [N]
+    const float* colscale;   // [N] fp8 weight scales or null
+    const int32_t* m_dev;    // device row count or null
+    int m_host;              // row count when m_dev is null
+    int m_tiles_cap;         // tiles available in M (grid shape)
+    int N, K;                // N and K elements (padded)
+    int lda, ldb, ldc;       // elements
+    float a_scale;           // fp8: scale of A
+    float r_scale;           // fp8: scale of R
+    float out_inv_scale;     // fp8: 1 / scale of C
+    int relu;
+    int persistent;          // loop over tiles with a grid stride
+};
+
+template <int PREC>
+struct Ty {
+    static constexpr int EB = PREC == 0 ? 4 : PREC == 1 ? 2 : 1;  // bytes per element
+};
+
+__device__ __forceinline__ int swz(int row, int chunk) { return row * 128 + ((chunk ^ (row & 7)) << 4); }
+
+template <int PREC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    constexpr int EB = Ty<PREC>::EB;
+    constexpr int TI = BM / 64, TJ = BN / 64;  // MFMA tiles per wave
+    constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
+    constexpr int A_LD = BM * 8 / 256, B_LD = BN * 8 / 256;  // 16-byte chunks per thread per stage
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int STAGE = A_BYTES + B_BYTES;
+#define SA(buf) (smem + (buf) * STAGE)
+#define SB(buf) (smem + (buf) * STAGE + A_BYTES)
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + BM - 1) / BM, g.m_tiles_cap);  // never past the launch's row capacity
+    const int n_tiles = g.N / BN;
+    const int total = m_tiles * n_tiles;
+    const int kb = g.K * EB;  // bytes of K
+    const int ktiles = kb / 128;
+
+    // Tile order: consecutive blocks of one XCD (blocks are dealt to the 8
+    // XCDs round-robin) take consecutive tiles, so the N tiles of one M row
+    // block share that XCD's L2.
+    const int grid = gridDim.x;
+    const int grid8 = grid & ~7;
+    int first = blockIdx.x;
+    if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
+
+    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+        const int tm = t / n_tiles, tn = t % n_tiles;
+        const int m0 = tm * BM, n0 = tn * BN;
+        const uint8_t* Ag = g.A + (size_t)m0 * g.lda * EB;
+        const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
+
+        floatx16 acc[TI][TJ];
+        for (int i = 0; i < TI; i++)
+            for (int j = 0; j < TJ; j++)
+                for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
+
+        uint4 ra[A_LD], rb[B_LD];
+        auto gload = [&](int kt) {
+            const int kbyte = kt * 128;
+            for (int i = 0; i < A_LD; i++) {
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
+                ra[i] = *reinterpret_cast<const uint4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16);
+            }
+            for (int i = 0; i < B_LD; i++) {
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
+                rb[i] = *reinterpret_cast<const uint4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16);
+            }
+        };
+        auto sstore = [&](int buf) {
+            for (int i = 0; i < A_LD; i++) {
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
+                *reinterpret_cast<uint4*>(SA(buf) + swz(row, ch)) = ra[i];
+            }
+            for (int i = 0; i < B_LD; i++) {
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
+                *reinterpret_cast<uint4*>(SB(buf) + swz(row, ch)) = rb[i];
+            }
+        };
+
+        gload(0);
+        __syncthreads();  // previous tile's readers of buffer 0 are done
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt < ktiles; kt++) {
+            const int cur = kt & 1;
+            if (kt + 1 < ktiles) gload(kt + 1);
+            const uint8_t* a_s = SA(cur);
+            const uint8_t* b_s = SB(cur);
+            const int half = lane >> 5, r32 = lane & 31;
+            if (PREC == 2) {
+                for (int kg = 0; kg < 2; kg++) {
+                    intx8 af[TI], bfr[TJ];
+                    for (int i = 0; i < TI; i++) {
+                        const int row = wm * (BM / 2) + i * 32 + r32;
+                        const uint4 lo = *reinterpret_cast<const uint4*>(a_s + swz(row, 4 * kg + 2 * half));
+                        const uint4 hi = *reinterpret_cast<const uint4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
+                        af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                    }
+                    for (int j = 0; j < TJ; j++) {
+                        const int row = wn * (BN / 2) + j * 32 + r32;
+                        const uint4 lo = *reinterpret_cast<const uint4*>(b_s + swz(row, 4 * kg + 2 * half));
+                        const uint4 hi = *reinterpret_cast<const uint4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
+                        bfr[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                    }
+                    for (int i = 0; i < TI; i++)
+                        for (int j = 0; j < TJ; j++)
+                            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[i], bfr[j], acc[i][j], 0, 0, 0,
+                                                                                       127, 0, 127);
+                }
+            } else {
+                for (int kg = 0; kg < 4; kg++) {
+                    uint4 af[TI], bfr[TJ];
+                    for (int i = 0; i < TI; i++) {
+                        const int row = wm * (BM / 2) + i * 32 + r32;
+                        af[i] = *reinterpret_cast<const uint4*>(a_s + swz(row, 2 * kg + half));
+                    }
+                    for (int j = 0; j < TJ; j++) {
+                        const int row = wn * (BN / 2) + j * 32 + r32;
+                        bfr[j] = *reinterpret_cast<const uint4*>(b_s + swz(row, 2 * kg + half));
+                    }
+                    if (PREC == 1) {
+                        for (int i = 0; i < TI; i++)
+                            for (int j = 0; j < TJ; j++)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j], 0, 0, 0);
+                    } else {
+                        for (int e = 0; e < 4; e++)
+                            for (int i = 0; i < TI; i++)
+                                for (int j = 0; j < TJ; j++) {
+                                    const uint32_t ai = e == 0 ? af[i].x : e == 1 ? af[i].y : e == 2 ? af[i].z : af[i].w;
+                                    const uint32_t bj = e == 0 ? bfr[j].x : e == 1 ? bfr[j].y : e == 2 ? bfr[j].z : bfr[j].w;
+                                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj),
+                                                                                     acc[i][j], 0, 0, 0);
+                                }
+                    }
+                }
+            }
+            if (kt + 1 < ktiles) sstore(cur ^ 1);
+            __syncthreads();
+        }
+
+        // Epilogue.  Lane holds, for MFMA tile (i, j), column j*32 + lane%32 and
+        // rows i*32 + 8a + 4*(lane/32) + b for a, b in 0..3 (value 4a + b).
+        const int half = lane >> 5, c32 = lane & 31;
+        for (int j = 0; j < TJ; j++) {
+            const int n = n0 + wn * (BN / 2) + j * 32 + c32;
+            const float bn = g.bias[n];
+            const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+            for (int i = 0; i < TI; i++) {
+                for (int a = 0; a < 4; a++)
+                    for (int b = 0; b < 4; b++) {
+                        const int m = m0 + wm * (BM / 2) + i * 32 + 8 * a + 4 * half + b;
+                        float v = acc[i][j][4 * a + b] * sn + bn;
+                        const size_t o = (size_t)m * g.ldc + n;
+                        if (g.R) {
+                            if (PREC == 0) v += reinterpret_cast<const float*>(g.R)[o];
+                            else if (PREC == 1) v += bf16_to_f32(reinterpret_cast<const uint16_t*>(g.R)[o]);
+                            else v += fp8_to_f32(g.R[o]) * g.r_scale;
+                        }
+                        if (g.relu) v = fmaxf(v, 0.f);
+                        if (PREC == 0) reinterpret_cast<float*>(g.C)[o] = v;
+                        else if (PREC == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
+                        else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+                    }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ head
+// One wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o] for o < n_out,
+// lanes own K slices of 4; wave-wide butterfly sums; lane 0 applies the
+// output rule.
+template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/, int NOUT>
+__global__ __launch_bounds__(256) void head_kernel(HeadArgs h) {
+    const int lane = threadIdx.x & 63;
+    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    float y[NOUT];
+    for (int o = 0; o < NOUT; o++) y[o] = 0.f;
+    for (int k = lane * 4; k < h.K; k += 256) {
+        float x[4];
+        const size_t xo = (size_t)r * h.ldx + k;
+        if (IN == 0) {
+            const float4 v = *reinterpret_cast<const float4*>((const float*)h.X + xo);
+            x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+        } else if (IN == 1) {
+            const uint2 v = *reinterpret_cast<const uint2*>((const uint16_t*)h.X + xo);
+            x[0] = bf16_to_f32(v.x & 0xFFFF); x[1] = bf16_to_f32(v.x >> 16);
+            x[2] = bf16_to_f32(v.y & 0xFFFF); x[3] = bf16_to_f32(v.y >> 16);
+        } else {
+            const uint32_t v = *reinterpret_cast<const uint32_t*>((const uint8_t*)h.X + xo);
+            for (int i = 0; i < 4; i++) x[i] = fp8_to_f32((v >> (8 * i)) & 0xFF) * h.x_scale;
+        }
+        for (int o = 0; o < NOUT; o++) {
+            if (o >= h.n_out) break;
+            const size_t wo = (size_t)o * h.K + k;
+            float w[4];
+            if (HW == 0) {
+                const float4 v = *reinterpret_cast<const float4*>((const float*)h.W + wo);
+                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            } else {
+                const uint2 v = *reinterpret_cast<const uint2*>((const uint16_t*)h.W + wo);
+                w[0] = bf16_to_f32(v.x & 0xFFFF); w[1] = bf16_to_f32(v.x >> 16);
+                w[2] = bf16_to_f32(v.y & 0xFFFF); w[3] = bf16_to_f32(v.y >> 16);
+            }
+            y[o] += x[0] * w[0] + x[1] * w[1] + x[2] * w[2] + x[3] * w[3];
+        }
+    }
+    for (int o = 0; o < NOUT; o++) {
+        if (o >= h.n_out) break;
+        float v = y[o];
+        for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+        y[o] = v + h.b[o];
+    }
+    if (lane != 0) return;
+    int md = -1;
+    if (h.combine_md && h.domain < 2) {
+        const uint64_t w = reinterpret_cast<const uint64_t*>(h.packed)[r];
+        const int side = h.domain == 0 ? 3 : 4;
+        md = 0;
+        for (int p = 0; p < side * side; p++) {
+            const int t = (int)((w >> (4 * p)) & 15);
+            if (t) md += abs(p / side - t / side) + abs(p % side - t % side);
+        }
+    }
+    int hv;
+    if (h.mode >= 3) {
+        if (h.mode == 4) {
+            int best = 0;
+            for (int o = 1; o < NOUT; o++)
+                if (o < h.n_out && y[o] > y[best]) best = o;
+            hv = best;
+        } else {
+            float mx = y[0];
+            for (int o = 1; o < NOUT; o++)
+                if (o < h.n_out) mx = fmaxf(mx, y[o]);
+            float e[NOUT], sum = 0.f;
+            for (int o = 0; o < NOUT; o++)
+                if (o < h.n_out) { e[o] = expf(y[o] - mx); sum += e[o]; }
+            float cdf = 0.f;
+            hv = h.n_out - 1;
+            for (int o = 0; o < NOUT; o++) {
+                if (o >= h.n_out) break;
+                cdf += e[o] / sum;
+                if (cdf >= h.q) { hv = o; break; }
+            }
+            if (!(sum > 0.f) || !isfinite(mx)) hv = md >= 0 ? md : 0;
+        }
+        if (h.raw) for (int o = 0; o < NOUT; o++) if (o < h.n_out) h.raw[(size_t)r * h.n_out + o] = y[o];
+    } else {
+        const float v = y[0] - h.offset;
+        if (!isfinite(v)) {
+            hv = md >= 0 ? md : 0;
+        } else {
+            const float f = h.mode == 1 ? rintf(v) : floorf(v);
+            hv = f < 0.f ? 0 : f > 1e9f ? 1000000000 : (int)f;
+            if (md >= 0 && md < hv) hv = md;
+        }
+        if (h.raw) h.raw[r] = v;
+    }
+    h.h_out[r] = hv;
+}
+
+// ------------------------------------------------------------ calibration
+// Largest value of rows < n, columns < N of a float32 activation tensor,
+// accumulated with an atomic max on the (non-negative) float bits.
+__global__ void absmax_kernel(const float* __restrict__ x, int n, int N, int ld, unsigned* out) {
+    float m = 0.f;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * N; i += gridDim.x * blockDim.x) {
+        const int r = i / N, c = i % N;
+        m = fmaxf(m, fabsf(x[(size_t)r * ld + c]));
+    }
+    for (int s = 32; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// ------------------------------------------------------------ launchers
+template <int DOM, int WT, int OUT>
+static void launch_gather_t(const GatherLaunch& L, hipStream_t s) {
+    const int blocks = (L.m_rows + 7) / 8;
+    hipLaunchKernelGGL((gather_l1_kernel<DOM, WT, OUT>), dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const uint64_t*>(L.packed), L.n_dev, L.n_host, L.m_rows, L.table, L.bias, L.N,
+                       L.ld_out, L.out, L.out_inv_scale);
+}
+
+template <int DOM>
+static bool launch_gather_d(const GatherLaunch& L, hipStream_t s) {
+    if (L.prec == 0) launch_gather_t<DOM, 0, 0>(L, s);
+    else if (L.prec == 1) launch_gather_t<DOM, 1, 1>(L, s);
+    else launch_gather_t<DOM, 1, 2>(L, s);
+    return true;
+}
+
+bool launch_gather(const GatherLaunch& L, hipStream_t s) {
+    switch (L.domain) {
+        case 0: return launch_gather_d<0>(L, s);
+        case 1: return launch_gather_d<1>(L, s);
+        case 2: return launch_gather_d<2>(L, s);
+    }
+    return false;
+}
+
+template <int PREC, int BM, int BN>
+static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    const int m_tiles = (L.m_cap + BM - 1) / BM;
+    const int tiles = m_tiles * (L.N / BN);
+    g.m_tiles_cap = m_tiles;
+    int grid = tiles;
+    g.persistent = 0;
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.m_dev) g.persistent = 1;  // tile count known only on the device: stride over the cap
+    const size_t lds = 2 * (size_t)(BM + BN) * 128;
+    hipLaunchKernelGGL((gemm_kernel<PREC, BM, BN>), dim3(grid), dim3(256), lds, s, g);
+}
+
+int gemm_tile_count() { return 3; }
+void gemm_tile_shape(int id, int* bm, int* bn) {
+    static const int T[3][2] = {{128, 128}, {128, 256}, {64, 128}};
+    *bm = T[id][0];
+    *bn = T[id][1];
+}
+
+template <int PREC>
+static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
+    switch (L.tile) {
+        case 0: launch_gemm_t<PREC, 128, 128>(L, s); return true;
+        case 1: launch_gemm_t<PREC, 128, 256>(L, s); return true;
+        case 2: launch_gemm_t<PREC, 64, 128>(L, s); return true;
+    }
+    return false;
+}
+
+bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
+    switch (L.prec) {
+        case 0: return launch_gemm_p<0>(L, s);
+        case 1: return launch_gemm_p<1>(L, s);
+        case 2: return launch_gemm_p<2>(L, s);
+    }
+    return false;
+}
+
+template <int IN, int HW>
+static bool launch_head_t(HeadArgs H, int m_cap, hipStream_t s) {
+    H.m_cap = m_cap;
+    const int blocks = (m_cap + 3) / 4;
+    if (H.n_out == 1)
+        hipLaunchKernelGGL((head_kernel<IN, HW, 1>), dim3(blocks), dim3(256), 0, s, H);
+    else if (H.n_out <= 32)
+        hipLaunchKernelGGL((head_kernel<IN, HW, 32>), dim3(blocks), dim3(256), 0, s, H);
+    else
+        return false;
+    return true;
+}
+
+bool launch_head(const HeadArgs& H, int prec, int m_cap, hipStream_t s) {
+    if (prec == 0) return launch_head_t<0, 0>(H, m_cap, s);
+    if (prec == 1) return launch_head_t<1, 1>(H, m_cap, s);
+    return launch_head_t<2, 1>(H, m_cap, s);
+}
+
+template <int PREC, int BM, int BN>
+static hipError_t set_lds_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<PREC, BM, BN>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (BM + BN) * 128);
+}
+
+template <int PREC>
+static hipError_t set_lds_attr_p() {
+    hipError_t e = set_lds_attr<PREC, 128, 128>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, 128, 256>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, 64, 128>();
+    return e;
+}
+
+// Blocks of the larger tiles use more than 64 KiB of LDS (gfx950 has 160 KiB).
+hipError_t gemm_prepare_attributes() {
+    hipError_t e = set_lds_attr_p<0>();
+    if (e == hipSuccess) e = set_lds_attr_p<1>();
+    if (e == hipSuccess) e = set_lds_attr_p<2>();
+    return e;
+}
+
+void launch_absmax(const float* x, int n, int N, int ld, unsigned* out, hipStream_t s) {
+    int blocks = (int)((int64_t)n * N / 256 + 1);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(absmax_kernel, dim3(blocks), dim3(256), 0, s, x, n, N, ld, out);
+}
+
+}  // namespace hb

@@ -1,0 +1,69 @@
+// Launch descriptors of the network kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hb {
+
+struct GatherLaunch {
+    int domain;             // 0 3x3, 1 4x4, 2 cube
+    int prec;               // 0 fp32 table -> fp32, 1 bf16 -> bf16, 2 bf16 -> fp8
+    const void* packed;     // device, packed states
+    const int32_t* n_dev;   // device state count or null
+    int n_host;
+    int m_rows;             // rows written (>= n, padded rows are zero)
+    const void* table;      // [rows][N] layer-1 table (fp32 or bf16)
+    const float* bias;      // [N]
+    int N;                  // padded width (multiple of 4)
+    int ld_out;             // elements
+    void* out;
+    float out_inv_scale;    // fp8 output
+};
+
+struct GemmLaunch {
+    int prec;               // 0 fp32, 1 bf16, 2 fp8
+    int tile;               // index into the tile table
+    const void* A;
+    const void* Bt;
+    void* C;
+    const void* R;
+    const float* bias;
+    const float* colscale;
+    const int32_t* m_dev;
+    int m_host;
+    int m_cap;              // largest M (grid shape)
+    int N, K, lda, ldb, ldc;
+    float a_scale, r_scale, out_inv_scale;
+    int relu;
+    int persistent_grid;    // > 0: at most this many blocks, striding over tiles
+};
+
+struct HeadArgs {
+    const void* X;          // [n][ldx] final activation
+    int ldx, K;
+    const void* W;          // [n_out][K]
+    const float* b;         // [n_out]
+    int n_out;
+    float x_scale;          // fp8 activation scale
+    const int32_t* n_dev;
+    int n_host;
+    int m_cap;              // rows the launch covers (clamps *n_dev)
+    const void* packed;     // for the Manhattan minimum
+    int domain;
+    int mode;               // hb_out_mode
+    float q, offset;
+    int combine_md;
+    int32_t* h_out;
+    float* raw;             // nullable
+};
+
+bool launch_gather(const GatherLaunch& L, hipStream_t s);
+bool launch_gemm(const GemmLaunch& L, hipStream_t s);
+bool launch_head(const HeadArgs& H, int prec, int m_cap, hipStream_t s);
+void launch_absmax(const float* x, int n, int N, int ld, unsigned* out, hipStream_t s);
+int gemm_tile_count();
+void gemm_tile_shape(int id, int* bm, int* bn);
+hipError_t gemm_prepare_attributes();
+
+}  // namespace hb

@@ -1,0 +1,493 @@
+// Model loading (weight file -> device operands in the chosen precision),
+// workspace management and the forward pass: gather layer 1, a chain of MFMA
+// GEMMs, head with the output rule.
+#include "model.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <fstream>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace hb {
+
+static int dom_P(int d) { return d == 0 ? 9 : d == 1 ? 16 : 54; }
+static int dom_S(int d) { return d == 0 ? 9 : d == 1 ? 16 : 6; }
+
+bool read_weight_file(const char* path, NetSpec* out, const char** why) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) { *why = "cannot open weight file"; return false; }
+    auto rd = [&](uint32_t* v, size_t cnt) { return (bool)f.read(reinterpret_cast<char*>(v), (std::streamsize)(cnt * 4)); };
+    uint32_t h[5];
+    if (!rd(h, 5) || h[0] != 0x31574248u) { *why = "bad weight-file magic"; return false; }
+    if (h[1] != 1) { *why = "unsupported weight-file version"; return false; }
+    if (h[2] > 2 || h[4] < 1 || h[4] > 8) { *why = "bad weight-file header"; return false; }
+    out->domain = (int)h[2];
+    out->n_in = (int)h[3];
+    std::vector<uint32_t> d(h[4]);
+    if (!rd(d.data(), d.size())) { *why = "truncated header"; return false; }
+    out->dims.assign(d.begin(), d.end());
+    uint32_t t3[3];
+    if (!rd(t3, 3)) { *why = "truncated header"; return false; }
+    out->n_res = (int)t3[0];
+    out->n_out = (int)t3[1];
+    out->head_kind = (int)t3[2];
+    if (out->n_in != dom_P(out->domain) * dom_S(out->domain)) { *why = "n_in does not match the domain"; return false; }
+    if (out->n_out < 1 || out->n_out > 32 || out->n_res > 64) { *why = "unsupported output width or depth"; return false; }
+    for (int v : out->dims)
+        if (v < 1 || v > 8192) { *why = "unsupported layer width"; return false; }
+    std::vector<std::pair<int, int>> shp;
+    int prev = out->n_in;
+    for (int v : out->dims) { shp.push_back({prev, v}); shp.push_back({1, v}); prev = v; }
+    for (int r = 0; r < out->n_res; r++)
+        for (int j = 0; j < 2; j++) { shp.push_back({prev, prev}); shp.push_back({1, prev}); }
+    shp.push_back({prev, out->n_out});
+    shp.push_back({1, out->n_out});
+    out->tensors.clear();
+    for (auto& s : shp) {
+        std::vector<float> t((size_t)s.first * s.second);
+        if (!f.read(reinterpret_cast<char*>(t.data()), (std::streamsize)(t.size() * 4))) { *why = "truncated tensors"; return false; }
+        out->tensors.push_back(std::move(t));
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------- rounding
+static uint16_t bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static float bf16_val(float f) {
+    uint32_t u = (uint32_t)bf16_bits(f) << 16;
+    float o;
+    std::memcpy(&o, &u, 4);
+    return o;
+}
+
+// OCP e4m3: 4 exponent bits (bias 7), 3 mantissa bits, max 448, round to
+// nearest even, saturating.
+static uint8_t e4m3_bits(float x) {
+    uint8_t sign = std::signbit(x) ? 0x80 : 0;
+    float a = std::fabs(x);
+    if (std::isnan(x)) return 0x7F;
+    if (a >= 448.f) return sign | 0x7E;
+    if (a < 0.015625f) {  // below 2^-6: subnormal step 2^-9
+        const int m = (int)std::nearbyint(a * 512.f);
+        return sign | (uint8_t)m;  // m == 8 is the smallest normal, same bits
+    }
+    int e;
+    const float fr = std::frexp(a, &e);  // a = fr * 2^e, fr in [0.5, 1)
+    int E = e - 1;                        // a = (2 fr) * 2^E
+    int m = (int)std::nearbyint((2.f * fr - 1.f) * 8.f);
+    if (m == 8) { m = 0; E++; }
+    int code = ((E + 7) << 3) | m;
+    if (code > 0x7E) code = 0x7E;
+    return sign | (uint8_t)code;
+}
+
+// --------------------------------------------------------------- loading
+static hb_status dev_upload(hb_model* m, const void* host, size_t bytes, void** dst) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(HB_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    m->allocs.push_back(p);
+    HB_HIP(hipMemcpy(p, host, bytes, hipMemcpyHostToDevice));
+    *dst = p;
+    return HB_OK;
+}
+
+int choose_tile(const hb_model* m, int64_t M, int N_pad) {
+    if (m->tile > 0) {
+        int bm, bn;
+        gemm_tile_shape(m->tile - 1, &bm, &bn);
+        if (N_pad % bn == 0) return m->tile - 1;
+    }
+    int bucket = 0;
+    while ((1LL << (bucket + 1)) <= M) bucket++;
+    auto it = m->tuned.find(bucket);
+    if (it != m->tuned.end()) {
+        int bm, bn;
+        gemm_tile_shape(it->second, &bm, &bn);
+        if (N_pad % bn == 0) return it->second;
+    }
+    // Prefer the biggest tile that still gives every compute unit a block.
+    const int order[3] = {1, 0, 2};
+    for (int id : order) {
+        int bm, bn;
+        gemm_tile_shape(id, &bm, &bn);
+        if (N_pad % bn) continue;
+        const int64_t tiles = ((M + bm - 1) / bm) * (N_pad / bn);
+        if (tiles >= 240) return id;
+    }
+    return N_pad % 128 == 0 ? 2 : 0;
+}
+
+hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
+    NetSpec spec;
+    const char* why = "";
+    if (!read_weight_file(path, &spec, &why)) return fail(HB_E_INVAL, "%s: %s", path, why);
+    if (o.prec < HB_FP32 || o.prec > HB_FP8_E4M3) return fail(HB_E_INVAL, "unknown precision %d", (int)o.prec);
+    if (o.out < HB_OUT_REG_FLOOR || o.out > HB_OUT_CLS_ARGMAX) return fail(HB_E_INVAL, "unknown output mode");
+    const bool cls_mode = o.out >= HB_OUT_CLS_QUANTILE;
+    if (cls_mode != (spec.head_kind == 1)) return fail(HB_E_INVAL, "output mode does not match the network head");
+    if (!cls_mode && spec.n_out != 1) return fail(HB_E_INVAL, "a regression head has one output");
+    if (o.combine_md && spec.domain == 2) return fail(HB_E_INVAL, "Manhattan distance applies to sliding tiles only");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(HB_E_DEVICE, "no HIP device available");
+    if (o.device < 0 || o.device >= ndev) return fail(HB_E_INVAL, "device %d out of range", o.device);
+    HB_HIP(hipSetDevice(o.device));
+    static bool attrs = false;
+    if (!attrs) { HB_HIP(gemm_prepare_attributes()); attrs = true; }
+
+    auto m = std::make_unique<hb_model>();
+    m->device = o.device;
+    m->opts = o;
+    if (m->opts.max_batch <= 0) m->opts.max_batch = 16384;
+    m->spec = spec;
+    m->path = path;
+    const int prec = (int)o.prec;
+    const int eb = prec == 0 ? 4 : prec == 1 ? 2 : 1;
+    const auto& T = spec.tensors;
+    auto pad = [](int v) { return (int)round_up(v, 128); };
+
+    // Layer 1: table of gathered rows (cube: non-centre stickers only, the
+    // constant centre rows folded into the bias).
+    m->P = dom_P(spec.domain);
+    m->S = dom_S(spec.domain);
+    m->N1 = spec.dims[0];
+    m->N1_pad = pad(m->N1);
+    const int P_eff = spec.domain == 2 ? 48 : m->P;
+    m->table_rows = P_eff * m->S;
+    auto wq = [&](float v) { return prec == 0 ? v : bf16_val(v); };  // layer-1 / head weight rounding
+    std::vector<float> bias1(m->N1_pad, 0.f);
+    for (int j = 0; j < m->N1; j++) bias1[j] = T[1][j];
+    std::vector<float> tab((size_t)m->table_rows * m->N1_pad, 0.f);
+    for (int q = 0; q < P_eff; q++) {
+        const int p = spec.domain == 2 ? q + q / 8 + (q % 8 >= 4 ? 1 : 0) : q;
+        for (int s = 0; s < m->S; s++)
+            for (int j = 0; j < m->N1; j++) tab[((size_t)q * m->S + s) * m->N1_pad + j] = wq(T[0][((size_t)p * m->S + s) * m->N1 + j]);
+    }
+    if (spec.domain == 2)
+        for (int f = 0; f < 6; f++) {
+            const int p = 9 * f + 4;
+            for (int j = 0; j < m->N1; j++) bias1[j] += wq(T[0][((size_t)p * 6 + f) * m->N1 + j]);
+        }
+    hb_status st;
+    if (prec == 0) {
+        st = dev_upload(m.get(), tab.data(), tab.size() * 4, &m->l1_table);
+    } else {
+        std::vector<uint16_t> tb(tab.size());
+        for (size_t i = 0; i < tab.size(); i++) tb[i] = bf16_bits(tab[i]);
+        st = dev_upload(m.get(), tb.data(), tb.size() * 2, &m->l1_table);
+    }
+    if (st != HB_OK) return st;
+    if ((st = dev_upload(m.get(), bias1.data(), bias1.size() * 4, (void**)&m->l1_bias)) != HB_OK) return st;
+    m->weight_bytes += (int64_t)tab.size() * (prec == 0 ? 4 : 2);
+    m->flops = (double)P_eff * m->N1;  // gathered adds
+
+    // Matrix layers: dense layers 2..n_dense, then residual pairs.
+    const int n_dense = (int)spec.dims.size();
+    m->n_act = n_dense + 2 * spec.n_res;
+    int ti = 2, act = 0;
+    int width_cap = m->N1_pad;
+    auto add_layer = [&](const std::vector<float>& W, const std::vector<float>& b, int K, int N, int in_act, int out_act,
+                         int res_act) -> hb_status {
+        MatLayer L;
+        L.K = K; L.N = N; L.K_pad = pad(K); L.N_pad = pad(N);
+        L.in_act = in_act; L.out_act = out_act; L.res_act = res_act;
+        std::vector<float> bp(L.N_pad, 0.f);
+        for (int j = 0; j < N; j++) bp[j] = b[j];
+        hb_status s2 = dev_upload(m.get(), bp.data(), bp.size() * 4, (void**)&L.bias);
+        if (s2 != HB_OK) return s2;
+        const size_t cnt = (size_t)L.N_pad * L.K_pad;
+        if (prec == 0) {
+            std::vector<float> wt(cnt, 0.f);
+            for (int k = 0; k < K; k++)
+                for (int n = 0; n < N; n++) wt[(size_t)n * L.K_pad + k] = W[(size_t)k * N + n];
+            s2 = dev_upload(m.get(), wt.data(), cnt * 4, &L.Wt);
+        } else if (prec == 1) {
+            std::vector<uint16_t> wt(cnt, 0);
+            for (int k = 0; k < K; k++)
+                for (int n = 0; n < N; n++) wt[(size_t)n * L.K_pad + k] = bf16_bits(W[(size_t)k * N + n]);
+            s2 = dev_upload(m.get(), wt.data(), cnt * 2, &L.Wt);
+        } else {
+            std::vector<uint8_t> wt(cnt, 0);
+            std::vector<float> cs(L.N_pad, 0.f);
+            for (int n = 0; n < N; n++) {
+                float mx = 0.f;
+                for (int k = 0; k < K; k++) mx = std::max(mx, std::fabs(W[(size_t)k * N + n]));
+                const float s = mx / 448.f;
+                cs[n] = s;
+                if (s > 0.f)
+                    for (int k = 0; k < K; k++) wt[(size_t)n * L.K_pad + k] = e4m3_bits(W[(size_t)k * N + n] / s);
+            }
+            s2 = dev_upload(m.get(), wt.data(), cnt, &L.Wt);
+            if (s2 == HB_OK) s2 = dev_upload(m.get(), cs.data(), cs.size() * 4, (void**)&L.colscale);
+        }
+        if (s2 != HB_OK) return s2;
+        m->weight_bytes += (int64_t)cnt * eb;
+        m->flops += 2.0 * K * N;
+        width_cap = std::max(width_cap, std::max(L.K_pad, L.N_pad));
+        m->layers.push_back(L);
+        return HB_OK;
+    };
+    for (int i = 1; i < n_dense; i++) {
+        if ((st = add_layer(T[ti], T[ti + 1], spec.dims[i - 1], spec.dims[i], act, act + 1, -1)) != HB_OK) return st;
+        ti += 2;
+        act++;
+    }
+    const int H = spec.dims.back();
+    for (int r = 0; r < spec.n_res; r++) {
+        const int x_act = act;
+        if ((st = add_layer(T[ti], T[ti + 1], H, H, x_act, n_dense + 2 * r, -1)) != HB_OK) return st;
+        if ((st = add_layer(T[ti + 2], T[ti + 3], H, H, n_dense + 2 * r, n_dense + 2 * r + 1, x_act)) != HB_OK) return st;
+        m->layers.back().res_in_place = true;
+        ti += 4;
+        act = n_dense + 2 * r + 1;
+    }
+    // Head: [n_out][K_pad], float32 or bfloat16.
+    m->K_last_pad = pad(H);
+    std::vector<float> hw((size_t)spec.n_out * m->K_last_pad, 0.f);
+    for (int k = 0; k < H; k++)
+        for (int oo = 0; oo < spec.n_out; oo++) hw[(size_t)oo * m->K_last_pad + k] = wq(T[ti][(size_t)k * spec.n_out + oo]);
+    if (prec == 0) {
+        st = dev_upload(m.get(), hw.data(), hw.size() * 4, &m->head_W);
+    } else {
+        std::vector<uint16_t> hb16(hw.size());
+        for (size_t i = 0; i < hw.size(); i++) hb16[i] = bf16_bits(hw[i]);
+        st = dev_upload(m.get(), hb16.data(), hb16.size() * 2, &m->head_W);
+    }
+    if (st != HB_OK) return st;
+    if ((st = dev_upload(m.get(), T[ti + 1].data(), T[ti + 1].size() * 4, (void**)&m->head_b)) != HB_OK) return st;
+    m->weight_bytes += (int64_t)hw.size() * (prec == 0 ? 4 : 2);
+    m->flops += 2.0 * H * spec.n_out;
+    m->width_cap = width_cap;
+    m->act_scale.assign(m->n_act, 1.f);
+    m->calibrated = prec != 2;
+    *out = m.release();
+    return HB_OK;
+}
+
+void model_free(hb_model* m) {
+    if (!m) return;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : m->ws) {
+        (void)hipFree(kv.second.x);
+        (void)hipFree(kv.second.t);
+        (void)hipFree(kv.second.absmax);
+    }
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+}
+
+static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
+    std::lock_guard<std::mutex> lk(m->mu);
+    auto it = m->ws.find(s);
+    if (it != m->ws.end()) { *out = &it->second; return HB_OK; }
+    Workspace w;
+    const int eb = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
+    w.rows_cap = (int)round_up(m->opts.max_batch, 256);
+    const size_t bytes = (size_t)w.rows_cap * m->width_cap * eb;
+    if (hipMalloc(&w.x, bytes) != hipSuccess || hipMalloc(&w.t, bytes) != hipSuccess ||
+        hipMalloc((void**)&w.absmax, 64 * sizeof(unsigned)) != hipSuccess) {
+        (void)hipFree(w.x);
+        (void)hipFree(w.t);
+        return fail(HB_E_NOMEM, "workspace allocation of 2 x %zu bytes failed", bytes);
+    }
+    auto r = m->ws.emplace(s, w);
+    *out = &r.first->second;
+    return HB_OK;
+}
+
+// Forward pass over one chunk of at most max_batch states.
+static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
+                            int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile) {
+    const int prec = (int)m->opts.prec;
+    if (cap && prec != 0) return fail(HB_E_INVAL, "calibration runs on a float32 model");
+    const int rows = (int)round_up(m_cap, 128);
+    void* X = w->x;
+    void* Tb = w->t;
+    if (cap) HB_HIP(hipMemsetAsync(w->absmax, 0, 64 * sizeof(unsigned), s));
+    GatherLaunch G{};
+    G.domain = m->spec.domain;
+    G.prec = prec;
+    G.packed = d_packed;
+    G.n_dev = d_n;
+    G.n_host = n;
+    G.m_rows = rows;
+    G.table = m->l1_table;
+    G.bias = m->l1_bias;
+    G.N = m->N1_pad;
+    G.ld_out = m->width_cap;
+    G.out = X;
+    G.out_inv_scale = 1.f / m->act_scale[0];
+    if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "no layer-1 kernel for this domain/precision");
+    HB_HIP(hipGetLastError());
+    if (cap) launch_absmax((const float*)X, n, m->N1, m->width_cap, w->absmax + 0, s);
+    // X holds the running activation x, Tb is scratch.  A dense layer writes
+    // Tb and the two swap roles; the first layer of a residual block writes
+    // t into Tb and keeps x in X; the second reads t, adds x and overwrites x
+    // in place (each element of x is read and written by the same lane).
+    const int n_dense = (int)m->spec.dims.size();
+    for (const MatLayer& L : m->layers) {
+        const bool res_first = !L.res_in_place && L.out_act >= n_dense;
+        GemmLaunch g{};
+        g.prec = prec;
+        g.tile = force_tile >= 0 ? force_tile : choose_tile(m, m_cap, L.N_pad);
+        g.Bt = L.Wt;
+        if (L.res_in_place) { g.A = Tb; g.R = X; g.C = X; }
+        else { g.A = X; g.R = nullptr; g.C = Tb; }
+        g.bias = L.bias;
+        g.colscale = L.colscale;
+        g.m_dev = d_n;
+        g.m_host = n;
+        g.m_cap = m_cap;
+        g.N = L.N_pad;
+        g.K = L.K_pad;
+        g.lda = m->width_cap;
+        g.ldb = L.K_pad;
+        g.ldc = m->width_cap;
+        g.a_scale = m->act_scale[L.in_act];
+        g.r_scale = L.res_act >= 0 ? m->act_scale[L.res_act] : 1.f;
+        g.out_inv_scale = 1.f / m->act_scale[L.out_act];
+        g.relu = 1;
+        if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
+        HB_HIP(hipGetLastError());
+        if (cap) launch_absmax((const float*)g.C, n, L.N, m->width_cap, w->absmax + L.out_act, s);
+        if (!L.res_in_place && !res_first) std::swap(X, Tb);
+    }
+    HeadArgs H{};
+    H.X = X;
+    H.ldx = m->width_cap;
+    H.K = m->K_last_pad;
+    H.W = m->head_W;
+    H.b = m->head_b;
+    H.n_out = m->spec.n_out;
+    H.x_scale = m->act_scale[m->n_act - 1];
+    H.n_dev = d_n;
+    H.n_host = n;
+    H.packed = d_packed;
+    H.domain = m->spec.domain;
+    H.mode = (int)m->opts.out;
+    H.q = m->opts.q;
+    H.offset = m->opts.offset;
+    H.combine_md = m->opts.combine_md;
+    H.h_out = d_h;
+    H.raw = d_raw;
+    if (!launch_head(H, prec, m_cap, s)) return fail(HB_E_UNSUPPORTED, "no head kernel for %d outputs", H.n_out);
+    HB_HIP(hipGetLastError());
+    if (cap) {
+        std::vector<unsigned> bits(m->n_act);
+        HB_HIP(hipMemcpyAsync(bits.data(), w->absmax, m->n_act * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HB_HIP(hipStreamSynchronize(s));
+        cap->act_max->resize(m->n_act);
+        for (int a = 0; a < m->n_act; a++) {
+            float v;
+            std::memcpy(&v, &bits[a], 4);
+            (*cap->act_max)[a] = std::max((*cap->act_max)[a], v);
+        }
+    }
+    return HB_OK;
+}
+
+hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n, int32_t* d_h,
+                     float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile) {
+    if (!m) return fail(HB_E_INVAL, "null model");
+    if (!m->calibrated) return fail(HB_E_INVAL, "FP8 model has no activation scales: call hb_model_calibrate first");
+    HB_HIP(hipSetDevice(m->device));
+    Workspace* w = nullptr;
+    hb_status st = get_ws(m, s, &w);
+    if (st != HB_OK) return st;
+    const int pb = m->spec.domain == 2 ? 24 : 8;
+    if (d_n) {
+        if (max_n > m->opts.max_batch) return fail(HB_E_INVAL, "max_n %lld exceeds the model's max_batch %d", (long long)max_n, m->opts.max_batch);
+        if (max_n <= 0) return HB_OK;
+        return eval_chunk(m, w, d_packed, 0, d_n, (int)max_n, d_h, d_raw, s, cap, force_tile);
+    }
+    for (int64_t off = 0; off < n; off += m->opts.max_batch) {
+        const int c = (int)std::min<int64_t>(m->opts.max_batch, n - off);
+        st = eval_chunk(m, w, d_packed + off * pb, c, nullptr, c, d_h + off,
+                        d_raw ? d_raw + off * m->spec.n_out : nullptr, s, cap, force_tile);
+        if (st != HB_OK) return st;
+    }
+    return HB_OK;
+}
+
+hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n) {
+    if (m->opts.prec != HB_FP8_E4M3) return fail(HB_E_INVAL, "calibration applies to FP8 models");
+    if (n <= 0) return fail(HB_E_INVAL, "calibration needs at least one state");
+    hb_model_opts o = m->opts;
+    o.prec = HB_FP32;
+    hb_model* f = nullptr;
+    hb_status st = model_load(m->path.c_str(), o, &f);
+    if (st != HB_OK) return st;
+    std::vector<float> mx(f->n_act, 0.f);
+    CalibCapture cap{&mx};
+    int32_t* d_h = nullptr;
+    if (hipMalloc((void**)&d_h, (size_t)std::min<int64_t>(n, f->opts.max_batch) * 4) != hipSuccess) {
+        model_free(f);
+        return fail(HB_E_NOMEM, "calibration buffer");
+    }
+    st = model_eval(f, d_packed, n, nullptr, 0, d_h, nullptr, nullptr, &cap);
+    (void)hipFree(d_h);
+    model_free(f);
+    if (st != HB_OK) return st;
+    for (int a = 0; a < m->n_act; a++) {
+        const double v = mx[a];
+        if (!(v > 0)) { m->act_scale[a] = 1.f; continue; }
+        int e = 0;
+        while (448.0 * std::ldexp(1.0, e) < v) e++;
+        while (448.0 * std::ldexp(1.0, e - 1) >= v) e--;
+        m->act_scale[a] = (float)std::ldexp(1.0, e);
+    }
+    m->calibrated = true;
+    return HB_OK;
+}
+
+hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap) {
+    if (n <= 0 || n > m->opts.max_batch) return fail(HB_E_INVAL, "tuning batch must be in 1..max_batch");
+    int32_t* d_h = nullptr;
+    if (hipMalloc((void**)&d_h, (size_t)n * 4) != hipSuccess) return fail(HB_E_NOMEM, "tuning buffer");
+    hipStream_t s = nullptr;
+    hipEvent_t e0, e1;
+    HB_HIP(hipEventCreate(&e0));
+    HB_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    int best_id = -1, nrep = 0;
+    for (int id = 0; id < gemm_tile_count(); id++) {
+        int bm, bn;
+        gemm_tile_shape(id, &bm, &bn);
+        bool ok = true;
+        for (const MatLayer& L : m->layers) ok &= (L.N_pad % bn == 0);
+        if (!ok) continue;
+        hb_status st = HB_OK;
+        for (int w = 0; w < 3 && st == HB_OK; w++) st = model_eval(m, d_packed, n, nullptr, 0, d_h, nullptr, s, nullptr, id);
+        if (st != HB_OK) { (void)hipFree(d_h); return st; }
+        const int reps = 10;
+        HB_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; r++) model_eval(m, d_packed, n, nullptr, 0, d_h, nullptr, s, nullptr, id);
+        HB_HIP(hipEventRecord(e1, s));
+        HB_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1000.0 * ms / reps;
+        if (report && 2 * nrep + 1 < cap) { report[2 * nrep] = id; report[2 * nrep + 1] = us; }
+        nrep++;
+        if (us < best) { best = us; best_id = id; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_h);
+    int bucket = 0;
+    while ((1LL << (bucket + 1)) <= n) bucket++;
+    if (best_id >= 0) m->tuned[bucket] = best_id;
+    return HB_OK;
+}
+
+}  // namespace hb

@@ -1,0 +1,80 @@
+// Device-resident heuristic network (hb_model) and its forward pass.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "hb.h"
+
+namespace hb {
+
+struct NetSpec {
+    int domain = 0, n_in = 0, n_res = 0, n_out = 0, head_kind = 0;
+    std::vector<int> dims;
+    std::vector<std::vector<float>> tensors;  // file order, float32
+};
+
+bool read_weight_file(const char* path, NetSpec* out, const char** why);
+
+struct MatLayer {
+    void* Wt = nullptr;         // [N_pad][K_pad] in the operand type
+    float* bias = nullptr;      // [N_pad]
+    float* colscale = nullptr;  // [N_pad] fp8 only
+    int K = 0, N = 0, K_pad = 0, N_pad = 0;
+    int in_act = 0, out_act = 0, res_act = -1;  // activation tensor ids
+    bool res_in_place = false;
+};
+
+struct Workspace {
+    void* x = nullptr;  // activation buffers: rows_cap x width_cap elements
+    void* t = nullptr;
+    int rows_cap = 0;
+    unsigned* absmax = nullptr;  // calibration scratch (n_act entries)
+};
+
+struct CalibCapture {
+    std::vector<float>* act_max;  // filled per activation tensor
+};
+
+}  // namespace hb
+
+struct hb_model {
+    int device = 0;
+    hb_model_opts opts{};
+    hb::NetSpec spec;
+    std::string path;
+    int P = 0, S = 0, table_rows = 0;
+    void* l1_table = nullptr;
+    float* l1_bias = nullptr;
+    int N1 = 0, N1_pad = 0;
+    std::vector<hb::MatLayer> layers;
+    void* head_W = nullptr;
+    float* head_b = nullptr;
+    int K_last_pad = 0;
+    int width_cap = 0;
+    int n_act = 0;
+    std::vector<float> act_scale;
+    bool calibrated = false;
+    int tile = 0;                       // 0 automatic, else tile id + 1
+    std::map<int, int> tuned;           // batch bucket (log2) -> tile id
+    int64_t weight_bytes = 0;
+    double flops = 0;
+    std::mutex mu;
+    std::map<hipStream_t, hb::Workspace> ws;
+    std::vector<void*> allocs;
+};
+
+namespace hb {
+
+hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out);
+void model_free(hb_model* m);
+hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n,
+                     int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile = -1);
+hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n);
+hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
+int choose_tile(const hb_model* m, int64_t M, int N_pad);
+
+}  // namespace hb

@@ -1,0 +1,199 @@
+"""GPU parity of hb_eval_batch against the double-precision oracle.
+
+Inputs are seeded (synth); both sides compute independently; the library is
+called through its C ABI.  Tolerances (derived in the design notes):
+  raw output y: |y_gpu - y_ref| <= TOL[prec] * max(1, |y_ref|), where y_ref is
+  the oracle with the same operand rounding (bf16 / e4m3) and double
+  accumulation.  FP32 1e-4, BF16 2e-3, FP8 2e-2: float32 accumulation error
+  plus rare one-ulp flips of stored activations.
+  integer h: equal wherever the oracle's value is farther than the tolerance
+  from a decision boundary (an integer for floor, q for the quantile); the rest
+  are counted as ambiguous and must be few.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2507_11916_amd as hb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {hb.HB_FP32: 1e-4, hb.HB_BF16: 2e-3, hb.HB_FP8_E4M3: 2e-2}
+
+
+def _dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda") if dtype is None else t.to("cuda", dtype)
+
+
+def _eval(model, packed, n_out):
+    d_p = _dev(packed)
+    d_h = torch.zeros(packed.shape[0], dtype=torch.int32, device="cuda")
+    d_y = torch.zeros(packed.shape[0] * n_out, dtype=torch.float32, device="cuda")
+    model.eval_batch(d_p, d_h, d_y)
+    torch.cuda.synchronize()
+    return d_h.cpu().numpy(), d_y.cpu().numpy().reshape(-1, n_out)
+
+
+def _cube_states(count, seed_base=9009, lo=20, span=11):
+    mv = synth.rc_walk_moves_array(synth.throughput_seeds(count, seed_base), length_base=lo, length_span=span)
+    return hb.hb_apply_moves(2, mv)
+
+
+def _floor_ambiguous(y, tol):
+    fr = y - np.floor(y)
+    return np.minimum(fr, 1 - fr) <= tol * np.maximum(1, np.abs(y))
+
+
+def test_8puzzle_all_states_fp32(net_files):
+    st = O.all8()
+    net = O.Net(net_files["stp3_small"])
+    y_ref = net.forward(st)[:, 0]
+    md = O.manhattan(0, st)
+    h_ref = net.h(y_ref, 0, classic=md)
+    m = hb.Model(net_files["stp3_small"], prec=hb.HB_FP32, combine_md=True)
+    h, y = _eval(m, hb.hb_encode(0, st), 1)
+    err = np.abs(y[:, 0] - y_ref) / np.maximum(1, np.abs(y_ref))
+    print("8-puzzle fp32 max rel err", err.max())
+    assert err.max() <= TOL[hb.HB_FP32]
+    amb = _floor_ambiguous(y_ref, TOL[hb.HB_FP32]) & (np.floor(y_ref) < md)
+    mism = (h != h_ref) & ~amb
+    print("ambiguous", amb.sum(), "mismatch", (h != h_ref).sum())
+    assert mism.sum() == 0
+    assert amb.sum() <= 20
+
+
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
+def test_stp4_residual_net_parity(net_files, prec):
+    n = 300  # three 128-row tiles with a ragged tail
+    st = synth.stp_walks(4, synth.throughput_seeds(n), lengths=200)
+    path = net_files["stp4_res"]
+    net = O.Net(path)
+    m = hb.Model(path, prec=prec, combine_md=True)
+    packed = hb.hb_encode(1, st)
+    scales = None
+    if prec == hb.HB_FP8_E4M3:
+        calib = synth.stp_walks(4, synth.throughput_seeds(1024, 4242), lengths=200)
+        m.calibrate(_dev(hb.hb_encode(1, calib)))
+        scales = net.calibrate(calib)
+        np.testing.assert_array_equal(m.act_scales(), scales.astype(np.float32))
+    h, y = _eval(m, packed, 1)
+    y_ref = net.forward(st, mode=int(prec), act_scale=scales)[:, 0]
+    err = np.abs(y[:, 0] - y_ref) / np.maximum(1, np.abs(y_ref))
+    print("stp4 prec", prec, "max rel err", err.max(), "mean", err.mean())
+    assert err.max() <= TOL[prec]
+    md = O.manhattan(1, st)
+    h_ref = net.h(y_ref, 0, classic=md)
+    amb = _floor_ambiguous(y_ref, TOL[prec])
+    assert np.all((h == h_ref) | amb)
+
+
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
+def test_cube_classifier_parity(net_files, prec):
+    n = 200
+    st = _cube_states(n)
+    path = net_files["rc_cls"]
+    net = O.Net(path)
+    m = hb.Model(path, prec=prec, out=hb.HB_OUT_CLS_QUANTILE, q=0.99)
+    scales = None
+    if prec == hb.HB_FP8_E4M3:
+        calib = _cube_states(512, 777)
+        m.calibrate(_dev(hb.hb_encode(2, calib)))
+        scales = net.calibrate(calib)
+        np.testing.assert_array_equal(m.act_scales(), scales.astype(np.float32))
+    h, z = _eval(m, hb.hb_encode(2, st), 21)
+    z_ref = net.forward(st, mode=int(prec), act_scale=scales)
+    scale = np.maximum(1, np.abs(z_ref).max(axis=1, keepdims=True))
+    err = np.abs(z - z_ref) / scale
+    print("cube prec", prec, "max rel err", err.max())
+    assert err.max() <= TOL[prec]
+    h_ref = net.h(z_ref, 3, q=0.99)
+    # decision margin: distance of the cumulative probability from q at every class
+    p = np.exp(z_ref - z_ref.max(axis=1, keepdims=True))
+    cdf = np.cumsum(p / p.sum(axis=1, keepdims=True), axis=1)
+    margin = np.abs(cdf - 0.99).min(axis=1)
+    amb = margin < 50 * TOL[prec]
+    assert np.all((h == h_ref) | amb)
+    assert amb.sum() <= n // 10
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 127, 129, 1000])
+def test_batch_sizes_and_position_independence(net_files, n):
+    path = net_files["stp4_res"]
+    m = hb.Model(path, prec=hb.HB_BF16)
+    st = synth.stp_walks(4, synth.throughput_seeds(1000), lengths=200)
+    packed = hb.hb_encode(1, st)
+    h_all, y_all = _eval(m, packed, 1)
+    if n == 0:
+        d_h = torch.zeros(1, dtype=torch.int32, device="cuda")
+        m.eval_batch(_dev(packed[:1]), d_h, n=0)
+        return
+    h, y = _eval(m, packed[1000 - n:], 1)
+    # a state's output does not depend on the batch around it
+    np.testing.assert_array_equal(y[:, 0], y_all[1000 - n:, 0])
+    np.testing.assert_array_equal(h, h_all[1000 - n:])
+
+
+def test_tile_shapes_give_identical_results(net_files):
+    path = net_files["stp4_res"]
+    st = synth.stp_walks(4, synth.throughput_seeds(700), lengths=200)
+    packed = hb.hb_encode(1, st)
+    outs = []
+    for tile in (1, 2, 3):
+        m = hb.Model(path, prec=hb.HB_BF16)
+        m.set_tile(tile)
+        outs.append(_eval(m, packed, 1)[1])
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_chunking_beyond_max_batch(net_files):
+    path = net_files["stp4_res"]
+    st = synth.stp_walks(4, synth.throughput_seeds(700), lengths=200)
+    packed = hb.hb_encode(1, st)
+    a = _eval(hb.Model(path, prec=hb.HB_BF16, max_batch=256), packed, 1)
+    b = _eval(hb.Model(path, prec=hb.HB_BF16), packed, 1)
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_device_count_variant_matches(net_files):
+    path = net_files["rc_cls"]
+    m = hb.Model(path, prec=hb.HB_BF16, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4096)
+    st = _cube_states(333)
+    packed = hb.hb_encode(2, st)
+    h0, z0 = _eval(m, packed, 21)
+    d_p = _dev(packed)
+    d_n = torch.tensor([333], dtype=torch.int32, device="cuda")
+    d_h = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    d_z = torch.zeros(4096 * 21, dtype=torch.float32, device="cuda")
+    buf = torch.zeros((4096, 24), dtype=torch.uint8, device="cuda")
+    buf[:333] = d_p
+    m.eval_batch_dev_n(buf, d_n, 4096, d_h, d_z)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d_h[:333].cpu().numpy(), h0)
+    np.testing.assert_array_equal(d_z[:333 * 21].cpu().numpy().reshape(-1, 21), z0)
+    assert int(d_h[333:].abs().sum()) == 0  # rows past n untouched (zero-initialised)
+
+
+def test_full_size_sampled_rows(net_files):
+    """B = 16384 (the largest batch) in the benchmark's launch shape; 48 sampled
+    rows against the oracle."""
+    path = net_files["stp4_res"]
+    B = 16384
+    st = synth.stp_walks(4, synth.throughput_seeds(B, 31337), lengths=200)
+    m = hb.Model(path, prec=hb.HB_FP32, combine_md=True)
+    h, y = _eval(m, hb.hb_encode(1, st), 1)
+    idx = np.random.default_rng(0).choice(B, 48, replace=False)
+    net = O.Net(path)
+    y_ref = net.forward(st[idx])[:, 0]
+    err = np.abs(y[idx, 0] - y_ref) / np.maximum(1, np.abs(y_ref))
+    assert err.max() <= TOL[hb.HB_FP32]
+
+
+def test_fp8_requires_calibration(net_files):
+    m = hb.Model(net_files["stp4_res"], prec=hb.HB_FP8_E4M3)
+    st = synth.stp_walks(4, [1, 2], lengths=10)
+    with pytest.raises(hb.HBError, match="calibrate"):
+        _eval(m, hb.hb_encode(1, st), 1)

@@ -1,0 +1,135 @@
+"""Host-side library checks that need no GPU: the C ABI loads and exports every
+declared symbol; the library's domain code agrees with the oracle's
+independent models; packing round-trips; input validation rejects bad states."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2507_11916_amd as hb
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(hb_[a-z0-9_]+|cbdfs_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    hb.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", hb.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [s for s in _declared_symbols() if s not in exported]
+    assert not missing, missing
+    assert len(_declared_symbols()) >= 20
+
+
+def test_sizes():
+    assert [hb.state_bytes(d) for d in (0, 1, 2)] == [9, 16, 54]
+    assert [hb.packed_bytes(d) for d in (0, 1, 2)] == [8, 8, 24]
+    assert hb.state_bytes(7) == -1
+
+
+@pytest.mark.parametrize("domain", [0, 1])
+def test_stp_moves_and_manhattan_agree_with_oracle(domain):
+    n = 3 if domain == 0 else 4
+    st = synth.stp_walks(n, range(500), lengths=80)
+    np.testing.assert_array_equal(hb.hb_manhattan(domain, st), O.manhattan(domain, st))
+
+
+def test_cube_moves_agree_with_oracle_on_10000_sequences():
+    mv = synth.rc_walk_moves_array(range(10000), length_base=1, length_span=30)
+    a = hb.hb_apply_moves(2, mv)
+    b = O.apply_moves(2, mv)
+    np.testing.assert_array_equal(a, b)
+    # every single move too, including the ones canonical pruning never draws
+    for m in range(18):
+        np.testing.assert_array_equal(hb.hb_apply_moves(2, [m]), O.apply_moves(2, np.array([m], dtype=np.int8)))
+
+
+def test_stp_move_sequences_agree_with_oracle():
+    rng = np.random.default_rng(9)
+    for n, dom in ((3, 0), (4, 1)):
+        # random legal move sequences built by walking the blank
+        seqs = []
+        for _ in range(300):
+            b, seq = 0, []
+            for _ in range(int(rng.integers(0, 60))):
+                r, c = divmod(b, n)
+                opts = [m for m, ok in enumerate([r > 0, c > 0, c < n - 1, r < n - 1]) if ok]
+                m = int(rng.choice(opts))
+                seq.append(m)
+                b += [-n, -1, 1, n][m]
+            seqs.append(seq + [-1] * (60 - len(seq)))
+        mv = np.array(seqs, dtype=np.int8)
+        np.testing.assert_array_equal(hb.hb_apply_moves(dom, mv), O.apply_moves(dom, mv))
+
+
+def test_apply_moves_rejects_off_board():
+    with pytest.raises(hb.HBError):
+        hb.hb_apply_moves(1, [0])
+
+
+@pytest.mark.parametrize("domain", [0, 1, 2])
+def test_encode_decode_round_trip(domain):
+    if domain == 2:
+        st = O.apply_moves(2, synth.rc_walk_moves_array(range(300), length_base=0, length_span=25))
+    else:
+        st = synth.stp_walks(3 if domain == 0 else 4, range(300), lengths=100)
+    p = hb.hb_encode(domain, st)
+    assert p.shape == (300, hb.packed_bytes(domain))
+    np.testing.assert_array_equal(hb.hb_decode(domain, p), st)
+
+
+def test_encode_layout_is_documented_bit_layout():
+    st = synth.stp_walks(4, [5], lengths=50)
+    w = int.from_bytes(hb.hb_encode(1, st)[0].tobytes(), "little")
+    assert [(w >> (4 * p)) & 15 for p in range(16)] == list(st[0])
+    cube = O.apply_moves(2, np.array([[0, 9, 14]], dtype=np.int8))[0]
+    words = np.frombuffer(hb.hb_encode(2, cube)[0].tobytes(), dtype="<u8")
+    nc = [p for p in range(54) if p % 9 != 4]
+    for q, p in enumerate(nc):
+        assert (int(words[q // 16]) >> (3 * (q % 16))) & 7 == cube[p]
+
+
+def test_encode_rejects_invalid_states():
+    bad = np.arange(16, dtype=np.uint8)
+    bad[3] = 2
+    with pytest.raises(hb.HBError, match="state 1"):
+        hb.hb_encode(1, np.stack([np.arange(16, dtype=np.uint8), bad]))
+    cube = O.goal(2).copy()
+    cube[4] = 1
+    with pytest.raises(hb.HBError):
+        hb.hb_encode(2, cube)
+    assert hb.hb_encode(1, np.zeros((0, 16), dtype=np.uint8)).shape == (0, 8)
+
+
+def test_corner_pdb_agrees_with_oracle():
+    k = 4
+    ours = hb.Pdb(k, threads=4)
+    tab, _ = O.corner_pdb(k)
+    st = O.apply_moves(2, synth.rc_walk_moves_array(range(2000), length_base=0, length_span=20))
+    np.testing.assert_array_equal(ours.lookup(st), tab[O.corner_index(st, k)])
+
+
+def test_model_load_without_gpu_reports_device_error(net_files):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(hb.HBError) as e:
+        hb.Model(net_files["stp3_small"])
+    assert e.value.status in (hb.HB_E_DEVICE, hb.HB_E_INVAL)
+
+
+def test_model_load_rejects_bad_files(tmp_path):
+    p = tmp_path / "bad.hbw"
+    p.write_bytes(b"XXXX" + bytes(40))
+    with pytest.raises(hb.HBError, match="magic"):
+        hb.Model(str(p))
