@@ -1,0 +1,231 @@
+"""Benchmark: batched neural-heuristic evaluations/s (and search nodes/s) on one MI355X.
+
+Workload: the 4x4 sliding-tile residual network (one-hot 256 -> 1000 -> 1000 ->
+2 residual blocks of width 1000 -> 1), batches of 8000 packed states resident
+in device memory, FP32 operands (the configuration's precision).  A step is one
+hb_eval_batch over one batch (decode + gather-sum layer 1, five MFMA layers, head
+with the floor/min-Manhattan output rule).  BF16 and FP8 are measured on the same
+network and inputs and reported with their h agreement against the FP64 oracle.
+
+Also reported: the dominant kernel's roofline (GEMM; algorithmic FLOPs per launch
+over its average event-timed duration), the end-to-end rate through pinned host
+memory, search nodes/s of Batch IDA* in fixed-tree mode, and the CPU oracle's
+evals/s on a bounded sample (baseline only).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # MI355X dense MFMA peaks
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8000)
+    ap.add_argument("--no-search", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-only", action="store_true", help="only the FP32 timed loop (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2507_11916_amd as hb
+    import synth
+    from synth import netcfg
+
+    B = args.batch
+    tmp = tempfile.mkdtemp()
+    wpath = os.path.join(tmp, "stp4_res.hbw")
+    synth.write_weights(wpath, "stp4_res", **netcfg.DEFAULTS["stp4_res"])
+    log(f"[bench] weights {wpath}; generating {B} states")
+    states = synth.stp_walks(4, synth.throughput_seeds(B), lengths=200)
+    packed = hb.hb_encode(hb.HB_STP4, states)
+    d_packed = torch.from_numpy(packed).cuda()
+    d_h = torch.zeros(B, dtype=torch.int32, device="cuda")
+    d_y = torch.zeros(B, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed_loop(model, steps, warmup):
+        for _ in range(warmup):
+            model.eval_batch(d_packed, d_h, None)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            model.eval_batch(d_packed, d_h, None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps  # ms per step
+
+    def profile_gemm(model, steps):
+        hb.lib().hb_model_profile(model.handle, 1)
+        for _ in range(steps):
+            model.eval_batch(d_packed, d_h, None)
+        torch.cuda.synchronize()
+        prof = Profile()
+        hb.lib().hb_model_profile_read(model.handle, hb.C.byref(prof))
+        hb.lib().hb_model_profile(model.handle, 0)
+        return prof
+
+    import ctypes as C
+
+    class Profile(C.Structure):
+        _fields_ = [("gather_ms", C.c_double), ("gemm_ms", C.c_double), ("head_ms", C.c_double),
+                    ("gather_launches", C.c_int64), ("gemm_launches", C.c_int64), ("head_launches", C.c_int64),
+                    ("gemm_flops", C.c_double)]
+
+    hb.lib().hb_model_profile.argtypes = [C.c_void_p, C.c_int]
+    hb.lib().hb_model_profile_read.argtypes = [C.c_void_p, C.POINTER(Profile)]
+
+    results = {}
+    calib = synth.stp_walks(4, synth.throughput_seeds(4096, 4242), lengths=200)
+    d_calib = torch.from_numpy(hb.hb_encode(hb.HB_STP4, calib)).cuda()
+    precs = [("f32", hb.HB_FP32)] if args.profile_only else [("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)]
+    models = {}
+    for name, prec in precs:
+        m = hb.Model(wpath, prec=prec, combine_md=True, max_batch=max(B, 16384))
+        if prec == hb.HB_FP8_E4M3:
+            m.calibrate(d_calib)
+        tune = m.tune(d_packed)
+        ms = timed_loop(m, args.steps, args.warmup)
+        log(f"[bench] {name}: {ms * 1e3:.1f} us/step  {B / ms * 1e3:.3e} evals/s  tiles {tune}")
+        entry = {"ms_per_step": ms, "evals_per_s": B / ms * 1e3, "tile_us": tune}
+        if not args.profile_only:
+            prof = profile_gemm(m, max(10, args.steps // 10))
+            gemm_avg_ms = prof.gemm_ms / max(1, prof.gemm_launches)
+            flops_per_launch = prof.gemm_flops / max(1, prof.gemm_launches)
+            entry["gemm_avg_us"] = gemm_avg_ms * 1e3
+            entry["gemm_tflops"] = flops_per_launch / (gemm_avg_ms * 1e-3) / 1e12
+            entry["gather_avg_us"] = prof.gather_ms / max(1, prof.gather_launches) * 1e3
+            entry["head_avg_us"] = prof.head_ms / max(1, prof.head_launches) * 1e3
+            entry["gemm_flops_per_launch"] = flops_per_launch
+            # h of the benchmark batch for the agreement check
+            m.eval_batch(d_packed, d_h, d_y)
+            torch.cuda.synchronize()
+            entry["_h"] = d_h.cpu().numpy().copy()
+            entry["_y"] = d_y.cpu().numpy().copy()
+        results[name] = entry
+        models[name] = m
+
+    if args.profile_only:
+        r = results["f32"]
+        print(json.dumps({"metric": "heuristic evals/s", "value": r["evals_per_s"], "unit": "evals/s",
+                          "ms_per_step": r["ms_per_step"], "profile_only": True}))
+        return
+
+    flops_eval = models["f32"].flops_per_eval
+    # end-to-end through pinned host memory (H2D + eval + D2H), FP32
+    h_pinned = torch.from_numpy(packed).pin_memory()
+    h_out = torch.zeros(B, dtype=torch.int32).pin_memory()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    n_e2e = max(10, args.steps // 4)
+    for _ in range(n_e2e):
+        d_packed.copy_(h_pinned, non_blocking=True)
+        models["f32"].eval_batch(d_packed, d_h, None)
+        h_out.copy_(d_h, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    e2e_ms = e0.elapsed_time(e1) / n_e2e
+
+    # h agreement with the FP64 oracle on a sample of the batch
+    agree = {}
+    import oracle as O
+    sample = np.arange(0, B, max(1, B // 256))[:256]
+    onet = O.Net(wpath)
+    y64 = onet.forward(states[sample])[:, 0]
+    h64 = onet.h(y64, 0, classic=O.manhattan(1, states[sample]))
+    for name in results:
+        agree[name] = float((results[name]["_h"][sample] == h64).mean())
+        results[name]["h_agree_fp64"] = agree[name]
+        results[name]["max_abs_dy_fp64"] = float(np.abs(results[name]["_y"][sample] - y64).max())
+
+    # search nodes/s: Batch IDA* on a 15-puzzle start (200-move walk), fixed-tree
+    # mode (network evaluated on every generated state, Manhattan pruning), FP32
+    search = None
+    if not args.no_search:
+        start = synth.stp4_instances(1)[0]
+        threads = min(32, max(4, len(os.sched_getaffinity(0))))
+        p = hb.default_params(batch_size=8000, work_num=8, node_limit=3_000_000, time_limit_s=20.0)
+        r = hb.cbdfs_solve(hb.HB_STP4, start, model=models["f32"], combine=hb.HB_H_FIXED_TREE,
+                           classic=hb.HB_CLASSIC_MD, threads=threads, params=p)
+        search = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
+                  "expanded": r["expanded"], "wall_s": r["wall_s"], "evals": r["evals"], "batches": r["batches"],
+                  "mean_batch": r["mean_batch"], "gpu_busy_s": r["gpu_busy_s"], "threads": threads,
+                  "host_cores": len(os.sched_getaffinity(0)), "status": r["status"],
+                  "iterations": len(r["iters"])}
+        log(f"[bench] search: {search['nodes_per_s']:.3e} nodes/s mean batch {search['mean_batch']:.0f}")
+
+    # CPU baseline: the oracle's FP64 forward on a bounded sample, all host cores
+    cpu = None
+    if not args.no_cpu_baseline:
+        from concurrent.futures import ThreadPoolExecutor
+        cores = len(os.sched_getaffinity(0))
+        t0 = time.time()
+        onet.forward(states[:4])
+        per_eval = (time.time() - t0) / 4
+        n_cpu = int(max(cores, min(B, args.cpu_seconds * cores / max(per_eval, 1e-6))))
+        chunks = np.array_split(np.arange(n_cpu), cores)
+        t0 = time.time()
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda idx: onet.forward(states[idx]), chunks))
+        dt = time.time() - t0
+        cpu = {"value": n_cpu / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+               "sample": f"{n_cpu} of the {B} benchmark states, FP64 plain-C forward, one thread per core"}
+        log(f"[bench] cpu oracle: {cpu['value']:.1f} evals/s on {cores} cores")
+
+    f32 = results["f32"]
+    ach = f32["gemm_tflops"]
+    line = {
+        "metric": "heuristic evals/s + search nodes/s per GPU (FP32 vs BF16/FP8) at matched h",
+        "value": f32["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 200-move random walks; seeded He-uniform weights)",
+        "config": {"workload": "4x4 sliding tile, residual MLP 256-1000-1000-2x(1000,1000)-1, batch 8000, FP32",
+                   "batch": B, "flops_per_eval": flops_eval},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK_TFLOPS["f32"], "traffic": None,
+                     "kernel": "gemm_kernel (dense/residual layer, M=batch, K=N=1000 padded to 1024)",
+                     "avg_launch_us": f32["gemm_avg_us"], "flops_per_launch": f32["gemm_flops_per_launch"]},
+        "cpu_baseline": cpu,
+        "precisions": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
+        "mfma_frac": {k: results[k]["evals_per_s"] * flops_eval / 1e12 / PEAK_TFLOPS[k] for k in results},
+        "end_to_end_evals_per_s_pcie": B / e2e_ms * 1e3,
+        "search": search,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -184,6 +184,18 @@ hb_status hb_model_set_tile(hb_model* m, int tile_id);
  * to `report` (host, cap entries) if non-NULL. */
 hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
 
+/* Per-kernel timing: while enabled, every launch of this model's kernels is
+ * bracketed by HIP events recorded on the stream it runs on.  Reading
+ * synchronises those events and returns the sums since the last reset.
+ * gemm_flops counts algorithmic work (2*K*N per row, unpadded). */
+typedef struct {
+    double gather_ms, gemm_ms, head_ms;
+    int64_t gather_launches, gemm_launches, head_launches;
+    double gemm_flops;
+} hb_profile;
+hb_status hb_model_profile(hb_model* m, int enable); /* enabling also resets the sums */
+hb_status hb_model_profile_read(hb_model* m, hb_profile* out);
+
 /* -------------------------------------------------------------- search */
 typedef enum { HB_IDA = 0, HB_BTS = 1 } hb_algo;
 

@@ -74,6 +74,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_2507_11916_amd/build.py")
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes libhb bind to that one, so device pointers and streams
+        # from torch and from the library live in a single runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i64 = C.c_void_p, C.c_int64
         sigs = {

@@ -202,4 +202,14 @@ hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double*
     return model_tune(m, d_packed, n, report, cap);
 }
 
+hb_status hb_model_profile(hb_model* m, int enable) {
+    if (!m) return fail(HB_E_INVAL, "null model");
+    return model_profile(m, enable != 0);
+}
+
+hb_status hb_model_profile_read(hb_model* m, hb_profile* out) {
+    if (!m || !out) return fail(HB_E_INVAL, "null argument");
+    return model_profile_read(m, out);
+}
+
 }  // extern "C"

@@ -305,6 +305,57 @@ static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
     return HB_OK;
 }
 
+// Per-kernel timing (hb_model_profile): events bracket each launch on its stream.
+static int prof_begin(hb_model* m, int kind, hipStream_t s) {
+    if (!m->profiling) return -1;
+    hb_model::Timed t{kind, nullptr, nullptr, 0.0};
+    if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return -1;
+    (void)hipEventRecord(t.a, s);
+    std::lock_guard<std::mutex> lk(m->mu);
+    m->timed.push_back(t);
+    return (int)m->timed.size() - 1;
+}
+
+static void prof_end(hb_model* m, int idx, double flops, hipStream_t s) {
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> lk(m->mu);
+    m->timed[idx].flops = flops;
+    (void)hipEventRecord(m->timed[idx].b, s);
+}
+
+hb_status model_profile(hb_model* m, bool enable) {
+    hb_profile dummy;
+    if (!enable) { model_profile_read(m, &dummy); m->profiling = false; return HB_OK; }
+    model_profile_read(m, &dummy);
+    for (int k = 0; k < 3; k++) { m->prof_ms[k] = 0; m->prof_n[k] = 0; }
+    m->prof_flops = 0;
+    m->profiling = true;
+    return HB_OK;
+}
+
+hb_status model_profile_read(hb_model* m, hb_profile* out) {
+    std::lock_guard<std::mutex> lk(m->mu);
+    for (auto& t : m->timed) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            m->prof_ms[t.kind] += ms;
+            m->prof_n[t.kind] += 1;
+            if (t.kind == 1) m->prof_flops += t.flops;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    m->timed.clear();
+    out->gather_ms = m->prof_ms[0];
+    out->gemm_ms = m->prof_ms[1];
+    out->head_ms = m->prof_ms[2];
+    out->gather_launches = m->prof_n[0];
+    out->gemm_launches = m->prof_n[1];
+    out->head_launches = m->prof_n[2];
+    out->gemm_flops = m->prof_flops;
+    return HB_OK;
+}
+
 // Forward pass over one chunk of at most max_batch states.
 static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
                             int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile) {
@@ -327,8 +378,10 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     G.ld_out = m->width_cap;
     G.out = X;
     G.out_inv_scale = 1.f / m->act_scale[0];
+    int pi = prof_begin(m, 0, s);
     if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "no layer-1 kernel for this domain/precision");
     HB_HIP(hipGetLastError());
+    prof_end(m, pi, 0.0, s);
     if (cap) launch_absmax((const float*)X, n, m->N1, m->width_cap, w->absmax + 0, s);
     // X holds the running activation x, Tb is scratch.  A dense layer writes
     // Tb and the two swap roles; the first layer of a residual block writes
@@ -357,8 +410,10 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         g.r_scale = L.res_act >= 0 ? m->act_scale[L.res_act] : 1.f;
         g.out_inv_scale = 1.f / m->act_scale[L.out_act];
         g.relu = 1;
+        pi = prof_begin(m, 1, s);
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());
+        prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N, s);
         if (cap) launch_absmax((const float*)g.C, n, L.N, m->width_cap, w->absmax + L.out_act, s);
         if (!L.res_in_place && !res_first) std::swap(X, Tb);
     }
@@ -380,8 +435,10 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     H.combine_md = m->opts.combine_md;
     H.h_out = d_h;
     H.raw = d_raw;
+    pi = prof_begin(m, 2, s);
     if (!launch_head(H, prec, m_cap, s)) return fail(HB_E_UNSUPPORTED, "no head kernel for %d outputs", H.n_out);
     HB_HIP(hipGetLastError());
+    prof_end(m, pi, 0.0, s);
     if (cap) {
         std::vector<unsigned> bits(m->n_act);
         HB_HIP(hipMemcpyAsync(bits.data(), w->absmax, m->n_act * sizeof(unsigned), hipMemcpyDeviceToHost, s));

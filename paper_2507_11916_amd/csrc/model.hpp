@@ -65,6 +65,13 @@ struct hb_model {
     std::mutex mu;
     std::map<hipStream_t, hb::Workspace> ws;
     std::vector<void*> allocs;
+    // per-kernel timing
+    bool profiling = false;
+    struct Timed { int kind; hipEvent_t a, b; double flops; };  // kind 0 gather, 1 gemm, 2 head
+    std::vector<Timed> timed;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};
+    double prof_flops = 0;
 };
 
 namespace hb {
@@ -76,5 +83,7 @@ hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int3
 hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n);
 hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
 int choose_tile(const hb_model* m, int64_t M, int N_pad);
+hb_status model_profile(hb_model* m, bool enable);
+hb_status model_profile_read(hb_model* m, hb_profile* out);
 
 }  // namespace hb

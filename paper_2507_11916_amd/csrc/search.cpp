@@ -91,13 +91,29 @@ public:
     Slab* reserve(int k, int* first, int* got);
     void commit(Slab* s, int n) { s->committed.fetch_add(n, std::memory_order_release); }
     void drain();  // flush and wait until every reserved record has been evaluated
-    // The batch thread is woken as soon as every still-searching thread waits.
-    void set_idle(int delta) {
-        if (idle_.fetch_add(delta) + delta >= active_.load() && delta > 0 && idle_flush_) cv_.notify_all();
+    // Flush-when-idle bookkeeping.  gen() advances every time a slab's values
+    // are handed back (before the values are written).  A search thread marks
+    // itself idle with the generation it read before a full round over its
+    // subtrees found nothing to do; it counts as idle only while no slab has
+    // returned since, so a thread that was just given results is never taken
+    // for idle.
+    int64_t gen() const { return gen_.load(); }
+    void set_active(int n) {
+        if (n > idle_cap_) {
+            idle_gen_.reset(new std::atomic<int64_t>[n]);
+            idle_cap_ = n;
+        }
+        for (int t = 0; t < n; t++) idle_gen_[t].store(kBusy);
+        n_search_ = n;
     }
-    void set_active(int n) { active_.store(n); }
-    void thread_done() {
-        if (active_.fetch_sub(1) - 1 <= idle_.load() && idle_flush_) cv_.notify_all();
+    void mark_idle(int t, int64_t g) {
+        idle_gen_[t].store(g);
+        if (idle_flush_ && all_idle()) cv_.notify_all();
+    }
+    void mark_busy(int t) { idle_gen_[t].store(kBusy); }
+    void thread_done(int t) {
+        idle_gen_[t].store(kDone);
+        if (idle_flush_ && all_idle()) cv_.notify_all();
     }
     hb_status eval_now(const std::vector<uint8_t>& packed, int64_t n, std::vector<int32_t>* h);  // synchronous
     std::atomic<int64_t> evals{0}, batches{0};
@@ -120,10 +136,23 @@ private:
     std::mutex mu_;
     std::condition_variable cv_;
     std::thread th_;
+    bool all_idle() const {
+        const int64_t g = gen_.load();
+        bool any = false;
+        for (int t = 0; t < n_search_; t++) {
+            const int64_t v = idle_gen_[t].load();
+            if (v == kDone) continue;
+            if (v != g) return false;
+            any = true;
+        }
+        return any;
+    }
+    static constexpr int64_t kBusy = -1, kDone = -2;
     bool stop_ = false;
     bool draining_ = false;
-    std::atomic<int> idle_{0};    // search threads whose subtrees all wait on h
-    std::atomic<int> active_{0};  // search threads still searching
+    std::atomic<int64_t> gen_{0};
+    std::unique_ptr<std::atomic<int64_t>[]> idle_gen_;
+    int idle_cap_ = 0, n_search_ = 0;
     uint8_t* d_packed_ = nullptr;
     int32_t* d_h_ = nullptr;
     hipStream_t stream_ = nullptr;
@@ -247,6 +276,7 @@ hb_status Batcher::process(Slab* s, int n) {
             s->h[i] = sh_->classic_h(st);
         }
     }
+    gen_.fetch_add(1);  // before any value becomes visible: idle marks taken so far are stale
     for (int i = 0; i < n; i++) {
         NodeRec* r = s->owners[i];
         int32_t v = s->h[i];
@@ -268,8 +298,7 @@ void Batcher::loop() {
             if (cur_ && cur_->reserved > 0) {
                 const bool full = cur_->reserved == cap_;
                 const bool timed = now_s() - cur_->t_first >= timeout_;
-                const int act = active_.load();
-                const bool idle = idle_flush_ && act > 0 && idle_.load() >= act;
+                const bool idle = idle_flush_ && all_idle();
                 if (full || timed || idle || draining_) break;
                 cv_.wait_for(lk, std::chrono::microseconds(100));
             } else {
@@ -391,7 +420,7 @@ struct Solver {
     }
     hb_status build_tree(const uint8_t* start);
     IterOut run(int32_t T, int64_t lim, bool stop_goal);
-    void thread_main(IterOut* out, int64_t* peak);
+    void thread_main(int tid, IterOut* out, int64_t* peak);
 };
 
 hb_status Solver::build_tree(const uint8_t* start) {
@@ -456,7 +485,7 @@ hb_status Solver::build_tree(const uint8_t* start) {
     return HB_OK;
 }
 
-void Solver::thread_main(IterOut* out, int64_t* peak) {
+void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
     const Domain& D = *sh.D;
     const int W = std::max(1, P->work_num);
     const int pb = D.packed_bytes;
@@ -601,8 +630,10 @@ void Solver::thread_main(IterOut* out, int64_t* peak) {
         if (!has_work[w]) { terminated[w] = 1; miss++; }
     int counter = 0;
     int stalled = 0;
+    int64_t streak_gen = 0, marked_gen = INT64_MIN;
     while (miss < W) {
         if (stop.load(std::memory_order_relaxed)) break;
+        const int64_t g_before = batcher ? batcher->gen() : 0;
         int res = 0;  // a terminated slot neither progresses nor blocks
         if (!terminated[counter]) {
             res = do_iteration(counter);
@@ -617,17 +648,23 @@ void Solver::thread_main(IterOut* out, int64_t* peak) {
         }
         if (res == 1) {
             stalled = 0;
-            if (idle) { batcher->set_idle(-1); idle = false; }
-        } else if (++stalled >= W) {
-            // every subtree of this thread waits on the batch
-            if (!idle && batcher) { batcher->set_idle(1); idle = true; }
-            std::this_thread::yield();
-            stalled = 0;
+            if (idle) { batcher->mark_busy(tid); idle = false; }
+        } else {
+            if (stalled == 0) streak_gen = g_before;
+            if (++stalled >= W) {
+                // a full round found every subtree of this thread waiting on h
+                if (batcher && (!idle || marked_gen != streak_gen)) {
+                    batcher->mark_idle(tid, streak_gen);
+                    idle = true;
+                    marked_gen = streak_gen;
+                }
+                std::this_thread::yield();
+                stalled = 0;
+            }
         }
         counter = (counter + 1) % W;
     }
-    if (idle) batcher->set_idle(-1);
-    if (batcher) batcher->thread_done();
+    if (batcher) batcher->thread_done(tid);
     if (limit >= 0) expanded_shared.fetch_add(expanded - flushed);
     std::lock_guard<std::mutex> lk(sol_mu);
     out->expanded += expanded;
@@ -691,7 +728,7 @@ IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
     if (!stop.load() && !exceeded_flag.load() && !work.empty()) {
         std::vector<std::thread> pool;
         if (batcher) batcher->set_active(threads);
-        for (int t = 0; t < threads; t++) pool.emplace_back([this, &out, &peak] { thread_main(&out, &peak); });
+        for (int t = 0; t < threads; t++) pool.emplace_back([this, t, &out, &peak] { thread_main(t, &out, &peak); });
         for (auto& th : pool) th.join();
         if (batcher) batcher->drain();
     }

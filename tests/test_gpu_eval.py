@@ -4,7 +4,7 @@ Inputs are seeded (synth); both sides compute independently; the library is
 called through its C ABI.  Tolerances (derived in the design notes):
   raw output y: |y_gpu - y_ref| <= TOL[prec] * max(1, |y_ref|), where y_ref is
   the oracle with the same operand rounding (bf16 / e4m3) and double
-  accumulation.  FP32 1e-4, BF16 2e-3, FP8 2e-2: float32 accumulation error
+  accumulation.  FP32 1e-5, BF16 2e-3, FP8 2e-2: float32 accumulation error
   plus rare one-ulp flips of stored activations.
   integer h: equal wherever the oracle's value is farther than the tolerance
   from a decision boundary (an integer for floor, q for the quantile); the rest
@@ -20,7 +20,7 @@ import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TOL = {hb.HB_FP32: 1e-4, hb.HB_BF16: 2e-3, hb.HB_FP8_E4M3: 2e-2}
+TOL = {hb.HB_FP32: 1e-5, hb.HB_BF16: 2e-3, hb.HB_FP8_E4M3: 2e-2}
 
 
 def _dev(a, dtype=None):
@@ -40,6 +40,28 @@ def _eval(model, packed, n_out):
 def _cube_states(count, seed_base=9009, lo=20, span=11):
     mv = synth.rc_walk_moves_array(synth.throughput_seeds(count, seed_base), length_base=lo, length_span=span)
     return hb.hb_apply_moves(2, mv)
+
+
+def _check_rows(y, y_q, y_exact, tol, max_flip_frac):
+    """Row-wise parity under reduced precision.
+
+    y: GPU output; y_q: oracle with the same operand rounding and double
+    accumulation; y_exact: oracle without rounding.  A row passes tightly when
+    |y - y_q| <= tol * scale.  A stored activation whose exact value lies within
+    the float32 accumulation error of a rounding boundary may round the other way
+    on the GPU; downstream layers then see a one-ulp different input and the row
+    drifts.  Such a row must stay within the rounding envelope: no farther from
+    y_q than y_q is from exact arithmetic (times 2, plus tol).  At most
+    max_flip_frac of the rows may take that branch.  Returns the flip fraction."""
+    scale = np.maximum(1, np.abs(y_q).max(axis=1))
+    d = np.abs(y - y_q).max(axis=1) / scale
+    env = np.abs(y_q - y_exact).max(axis=1) / scale
+    tight = d <= tol
+    flipped = ~tight
+    assert np.all(d[flipped] <= 2 * env[flipped] + tol), (d[flipped].max(), env[flipped])
+    frac = flipped.mean()
+    assert frac <= max_flip_frac, frac
+    return frac, tight
 
 
 def _floor_ambiguous(y, tol):
@@ -62,7 +84,9 @@ def test_8puzzle_all_states_fp32(net_files):
     mism = (h != h_ref) & ~amb
     print("ambiguous", amb.sum(), "mismatch", (h != h_ref).sum())
     assert mism.sum() == 0
-    assert amb.sum() <= 20
+    # states within the tolerance window of an integer: about 2 * window * n
+    window = TOL[hb.HB_FP32] * np.abs(y_ref).max()
+    assert amb.sum() <= 4 * window * len(st) + 10
 
 
 @pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
@@ -81,13 +105,15 @@ def test_stp4_residual_net_parity(net_files, prec):
         np.testing.assert_array_equal(m.act_scales(), scales.astype(np.float32))
     h, y = _eval(m, packed, 1)
     y_ref = net.forward(st, mode=int(prec), act_scale=scales)[:, 0]
+    y_exact = net.forward(st)[:, 0] if prec != hb.HB_FP32 else y_ref
     err = np.abs(y[:, 0] - y_ref) / np.maximum(1, np.abs(y_ref))
     print("stp4 prec", prec, "max rel err", err.max(), "mean", err.mean())
-    assert err.max() <= TOL[prec]
+    frac, tight = _check_rows(y, y_ref[:, None], y_exact[:, None], TOL[prec],
+                              0.0 if prec == hb.HB_FP32 else 0.15)
     md = O.manhattan(1, st)
     h_ref = net.h(y_ref, 0, classic=md)
     amb = _floor_ambiguous(y_ref, TOL[prec])
-    assert np.all((h == h_ref) | amb)
+    assert np.all((h == h_ref) | amb | ~tight)
 
 
 @pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
@@ -105,17 +131,16 @@ def test_cube_classifier_parity(net_files, prec):
         np.testing.assert_array_equal(m.act_scales(), scales.astype(np.float32))
     h, z = _eval(m, hb.hb_encode(2, st), 21)
     z_ref = net.forward(st, mode=int(prec), act_scale=scales)
-    scale = np.maximum(1, np.abs(z_ref).max(axis=1, keepdims=True))
-    err = np.abs(z - z_ref) / scale
-    print("cube prec", prec, "max rel err", err.max())
-    assert err.max() <= TOL[prec]
+    z_exact = net.forward(st) if prec != hb.HB_FP32 else z_ref
+    frac, tight = _check_rows(z, z_ref, z_exact, TOL[prec], 0.0 if prec == hb.HB_FP32 else 0.15)
+    print("cube prec", prec, "rows off the tight branch", frac)
     h_ref = net.h(z_ref, 3, q=0.99)
     # decision margin: distance of the cumulative probability from q at every class
     p = np.exp(z_ref - z_ref.max(axis=1, keepdims=True))
     cdf = np.cumsum(p / p.sum(axis=1, keepdims=True), axis=1)
     margin = np.abs(cdf - 0.99).min(axis=1)
     amb = margin < 50 * TOL[prec]
-    assert np.all((h == h_ref) | amb)
+    assert np.all((h == h_ref) | amb | ~tight)
     assert amb.sum() <= n // 10
 
 

@@ -1,0 +1,99 @@
+"""cbdfs_solve with the network evaluated on the GPU, against the serial oracle.
+
+* 8-puzzle, h = max(0, min(floor(net), Manhattan)): the GPU's h table over all
+  181,440 states is first compared with the oracle's; where they agree on every
+  state, per-iteration counts must be identical and costs optimal.
+* Fixed-tree mode (network evaluated on every generated state, pruning with the
+  classic heuristic): counts equal the oracle's classic-heuristic search exactly,
+  whatever the network computes.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2507_11916_amd as hb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _complete_counts(iters):
+    return [(i["bound"], i["expanded"], i["generated"]) for i in iters if i["complete"]]
+
+
+def _follow(dom, start, path):
+    s = np.array(start, dtype=np.uint8)
+    for m in path:
+        s = O.apply(dom, s, m)
+    return s
+
+
+def test_8puzzle_nn_search_matches_oracle(net_files):
+    path = net_files["stp3_small"]
+    allst = O.all8()
+    net = O.Net(path)
+    h_ref = net.h(net.forward(allst), 0, classic=O.manhattan(0, allst))
+    m = hb.Model(path, prec=hb.HB_FP32, combine_md=True, max_batch=4096)
+    d_p = torch.from_numpy(hb.hb_encode(0, allst)).cuda()
+    d_h = torch.zeros(len(allst), dtype=torch.int32, device="cuda")
+    m.eval_batch(d_p, d_h)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_h.cpu().numpy(), h_ref), "h tables differ; counts cannot be compared"
+    ranks = np.array([O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data) for s in allst])
+    table = np.zeros(362880, dtype=np.int32)
+    table[ranks] = h_ref
+    bfs, _ = O.bfs8()
+    for i, s in enumerate(synth.stp3_instances(100)):
+        p = hb.default_params(batch_size=64, work_num=4, complete_final_iter=1)
+        threads = 1 if i % 2 == 0 else 4  # the configuration's serial search and a parallel one
+        r = hb.cbdfs_solve(0, s, model=m, combine=hb.HB_H_NN, threads=threads, params=p)
+        o = O.ida(0, s, hkind=O.H_TABLE8, table8=table, complete_final=True)
+        assert r["status"] == hb.HB_OK
+        assert r["cost"] == o["cost"] == bfs[O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data)]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
+        assert np.array_equal(_follow(0, s, r["path"]), O.goal(0))
+        assert r["evals"] > 0 and r["batches"] > 0
+
+
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
+def test_stp4_fixed_tree_matches_oracle(net_files, prec):
+    path = net_files["stp4_res"]
+    m = hb.Model(path, prec=prec, combine_md=True, max_batch=8000)
+    if prec == hb.HB_FP8_E4M3:
+        calib = synth.stp_walks(4, synth.throughput_seeds(1024, 4242), lengths=200)
+        m.calibrate(torch.from_numpy(hb.hb_encode(1, calib)).cuda())
+    for s in synth.stp_walks(4, synth.config_seeds(2, 4), lengths=46):
+        p = hb.default_params(batch_size=1000, work_num=8)
+        r = hb.cbdfs_solve(1, s, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_MD, threads=16, params=p)
+        o = O.ida(1, s, hkind=O.H_MD)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"][:-1])
+        assert r["evals"] >= r["generated"] - 10 ** 5
+        assert np.array_equal(_follow(1, s, r["path"]), O.goal(1))
+
+
+def test_stp4_min_nn_manhattan_is_optimal(net_files):
+    m = hb.Model(net_files["stp4_res"], prec=hb.HB_BF16, combine_md=True)
+    for s in synth.stp_walks(4, synth.config_seeds(2, 3), lengths=40):
+        r = hb.cbdfs_solve(1, s, model=m, combine=hb.HB_H_NN, threads=8,
+                           params=hb.default_params(batch_size=2000))
+        o = O.ida(1, s, hkind=O.H_MD)
+        assert r["cost"] == o["cost"]
+
+
+def test_cube_fixed_tree_bts_matches_oracle(net_files):
+    k = 4
+    pdb = hb.Pdb(k)
+    tab, _ = O.corner_pdb(k)
+    m = hb.Model(net_files["rc_cls"], prec=hb.HB_BF16, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4000)
+    mv = synth.rc_walk_moves_array(synth.config_seeds(3, 3), length_base=6, length_span=2)
+    for s in O.apply_moves(2, mv):
+        p = hb.default_params(batch_size=4000, work_num=8, bts_b0=2000)
+        r = hb.cbdfs_solve(2, s, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                           algo=hb.HB_BTS, threads=16, params=p)
+        o = O.bts(2, s, hkind=O.H_PDB, pdb=tab, pdb_k=k, b0=2000)
+        assert r["cost"] == o["cost"]
+        assert [(i["bound"], i["limit"], i["complete"]) for i in r["iters"]] == \
+               [(i["bound"], i["limit"], i["complete"]) for i in o["iters"]]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
