@@ -82,11 +82,13 @@ def _declare(L):
     L.orc_bts.argtypes = [C.c_int, vp, C.POINTER(HSpec), C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                           C.c_int64, C.POINTER(Iter), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp,
                           C.POINTER(C.c_int)]
-    if hasattr(L, "orc_train_grad"):
-        L.orc_train_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_double, vp, vp]
-        L.orc_train_grad.restype = C.c_double
-        L.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double,
-                                    C.c_double, C.c_int]
+    L.orc_train_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_double, vp, vp]
+    L.orc_train_grad.restype = C.c_double
+    L.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.c_int]
+    L.orc_net_param_count.argtypes = [vp]
+    L.orc_net_get_params.argtypes = [vp, vp]
+    L.orc_net_set_params.argtypes = [vp, vp]
 
 
 # ----------------------------------------------------------------- domains
@@ -220,6 +222,30 @@ class Net:
         lib().orc_net_fp8_col_scales(self._h, tensor_index, out.ctypes.data)
         return out if cols is None else out[:cols]
 
+    # ------------------------------------------------------------ training
+    def n_params(self):
+        return lib().orc_net_param_count(self._h)
+
+    def params(self):
+        out = np.zeros(self.n_params(), dtype=np.float64)
+        lib().orc_net_get_params(self._h, out.ctypes.data)
+        return out
+
+    def set_params(self, flat):
+        f = np.ascontiguousarray(flat, dtype=np.float64)
+        assert f.size == self.n_params()
+        lib().orc_net_set_params(self._h, f.ctypes.data)
+
+    def loss_grad(self, states, labels, asym=False, alpha=1.0):
+        """(loss, flat gradient in file order, y) of the squared-error loss."""
+        s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, STATE_LEN[self.domain])
+        t = np.ascontiguousarray(labels, dtype=np.float64)
+        g = np.zeros(self.n_params(), dtype=np.float64)
+        y = np.zeros(s.shape[0], dtype=np.float64)
+        loss = lib().orc_train_grad(self._h, s.ctypes.data, s.shape[0], t.ctypes.data, int(asym), alpha,
+                                    g.ctypes.data, y.ctypes.data)
+        return loss, g, y
+
     def h(self, y, mode=0, q=0.99, offset=0.0, classic=None):
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1, self.n_out)
         out = np.zeros(y.shape[0], dtype=np.int32)
@@ -227,6 +253,13 @@ class Net:
         lib().orc_h_batch(self._h, y.ctypes.data, y.shape[0], mode, q, offset,
                           None if cl is None else cl.ctypes.data, out.ctypes.data)
         return out
+
+
+def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (w, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam_step(w.ctypes.data, g.ctypes.data, m.ctypes.data, v.ctypes.data, w.size, lr, b1, b2, eps, t)
 
 
 # ----------------------------------------------------------------- search

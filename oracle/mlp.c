@@ -32,14 +32,7 @@
 #include <string.h>
 #include "orc.h"
 
-#define MAXT 64
-
-typedef struct {
-    int domain, n_in, n_dense, dims[8], n_res, n_out, head_kind;
-    int P, S, nt;
-    int rows[MAXT], cols[MAXT];
-    double* T[MAXT]; /* tensors in file order */
-} orc_net;
+#define MAXT ORC_MAXT
 
 /* ----------------------------------------------------------- rounding */
 double orc_bf16_round(double x) {

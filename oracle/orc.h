@@ -23,6 +23,13 @@ int64_t orc_perm9_rank(const uint8_t* s);
 int orc_corner_k_index(const uint8_t* s, int k, int64_t* idx);
 
 /* mlp.c */
+#define ORC_MAXT 64
+typedef struct {
+    int domain, n_in, n_dense, dims[8], n_res, n_out, head_kind;
+    int P, S, nt;
+    int rows[ORC_MAXT], cols[ORC_MAXT];
+    double* T[ORC_MAXT]; /* tensors in file order */
+} orc_net;
 double orc_bf16_round(double x);
 double orc_e4m3_round(double x);
 
