@@ -179,6 +179,35 @@ def main():
                   "iterations": len(r["iters"])}
         log(f"[bench] search: {search['nodes_per_s']:.3e} nodes/s mean batch {search['mean_batch']:.0f}")
 
+    # training step of the learned heuristic: same network shape, BF16 operands,
+    # FP32 master weights and Adam, batch 8192 (labels: walk lengths)
+    training = None
+    if not args.no_search:
+        TB = 8192
+        tst = synth.stp_walks(4, synth.throughput_seeds(TB, 5005), length_base=0, length_span=201)
+        tlab = np.array([synth.Stream((5005 << 32) + i).next() % 201 for i in range(TB)], dtype=np.float32)
+        tr = hb.Trainer(wpath, prec=hb.HB_BF16, max_batch=TB)
+        d_tp = torch.from_numpy(hb.hb_encode(hb.HB_STP4, tst)).cuda()
+        d_tl = torch.from_numpy(tlab).cuda()
+        l0 = tr.step(d_tp, d_tl)
+        for _ in range(3):
+            tr.step(d_tp, d_tl, want_loss=False)
+        torch.cuda.synchronize()
+        n_tr = 20
+        e0.record(stream)
+        for _ in range(n_tr):
+            tr.step(d_tp, d_tl, want_loss=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tms = e0.elapsed_time(e1) / n_tr
+        l1 = tr.step(d_tp, d_tl)
+        tflops = 3 * flops_eval * TB / (tms * 1e-3) / 1e12
+        training = {"ms_per_step": tms, "samples_per_s": TB / tms * 1e3, "batch": TB, "prec": "bf16",
+                    "tflops_algorithmic": tflops, "mfma_frac_bf16": tflops / PEAK_TFLOPS["bf16"],
+                    "loss_first": l0, "loss_after_25_steps": l1}
+        log(f"[bench] training: {tms:.2f} ms/step, {tflops:.1f} TFLOP/s")
+        tr.close()
+
     # CPU baseline: the oracle's FP64 forward on a bounded sample, all host cores
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +252,7 @@ def main():
         "mfma_frac": {k: results[k]["evals_per_s"] * flops_eval / 1e12 / PEAK_TFLOPS[k] for k in results},
         "end_to_end_evals_per_s_pcie": B / e2e_ms * 1e3,
         "search": search,
+        "training": training,
     }
     print(json.dumps(line))
 

@@ -107,7 +107,8 @@ typedef enum { HB_FP32 = 0, HB_BF16 = 1, HB_FP8_E4M3 = 2 } hb_precision;
 /* Output rule applied in the kernel epilogue.
  *  Regression (one output y): v = y - offset; FLOOR: h = floor(v); ROUND:
  *  round half to even; REAL: h = floor(v) and raw_out = v.  h is clamped at 0
- *  and, with combine_md, replaced by min(h, Manhattan distance).
+ *  and, with combine_md, replaced by min(h, MD) (1) or max(h, MD) (2), MD the
+ *  Manhattan distance of the state.
  *  Classifier (n_out classes): QUANTILE: the smallest class whose cumulative
  *  softmax probability is >= q (the last class if none); ARGMAX: the highest
  *  logit, lowest index on ties.  Softmax, sums and comparisons in FP32.
@@ -124,7 +125,8 @@ typedef struct {
     hb_out_mode out;
     float q;             /* classifier quantile, e.g. 0.99 */
     float offset;        /* regression offset, e.g. 2.2 */
-    int combine_md;      /* sliding tile: h = min(h, Manhattan distance) */
+    int combine_md;      /* sliding tile: 1 h = min(h, Manhattan) (guard for untrained nets);
+                            2 h = max(h, Manhattan) (learned heuristic with Manhattan fallback) */
     int max_batch;       /* largest n per launch; larger calls are split (0: 16384) */
 } hb_model_opts;
 
@@ -195,6 +197,44 @@ typedef struct {
 } hb_profile;
 hb_status hb_model_profile(hb_model* m, int enable); /* enabling also resets the sums */
 hb_status hb_model_profile_read(hb_model* m, hb_profile* out);
+
+/* ------------------------------------------------------------ training */
+/* On-GPU training of a sliding-tile regression network (the learned
+ * heuristic; design objective of the appendix: large mean h with h_M <= h*).
+ * Loss over a batch of n labelled states:
+ *   L = (1/n) sum_b w_b (y_b - t_b)^2,  w_b = alpha if asym and y_b > t_b else 1.
+ * Gradients by the chain rule on the GPU (weight gradients in FP32; the
+ * layer-1 gradient is the scatter-add of the pre-activation gradient rows that
+ * the one-hot input selects); Adam (Kingma & Ba) on FP32 master weights, after
+ * which the working copies (BF16 or FP32) are re-cast.  ReLU'(z) = [z > 0]. */
+typedef struct {
+    hb_precision prec;   /* HB_BF16 (BF16 operands, FP32 master) or HB_FP32 */
+    int device;
+    int max_batch;       /* largest n per step (default 8192) */
+    float lr, beta1, beta2, eps; /* defaults 1e-3, 0.9, 0.999, 1e-8 */
+    int asym;            /* asymmetric loss */
+    float alpha;         /* over-estimate weight (default 4) */
+} hb_train_opts;
+
+typedef struct hb_trainer hb_trainer;
+/* opts NULL = defaults.  The weight file must be a regression network of a
+ * sliding-tile domain whose hidden widths are at most 1024. */
+hb_status hb_trainer_create(const char* weights_path, const hb_train_opts* opts, hb_trainer** out);
+void hb_trainer_free(hb_trainer* t); /* NULL-safe */
+int64_t hb_trainer_n_params(const hb_trainer* t);
+/* One optimisation step on n <= max_batch states (device, packed) with float32
+ * labels (device).  loss_out (host, nullable): the batch loss before the step
+ * (synchronises the stream).  Asynchronous otherwise. */
+hb_status hb_train_step(hb_trainer* t, const uint8_t* d_packed, const float* d_labels, int64_t n, float* loss_out,
+                        void* stream);
+/* Loss and gradient without an update: d_grads (device, float32,
+ * hb_trainer_n_params entries) in weight-file order.  Synchronous. */
+hb_status hb_train_grad(hb_trainer* t, const uint8_t* d_packed, const float* d_labels, int64_t n, float* d_grads,
+                        float* loss_out);
+/* FP32 master weights: copy out (host, n_params floats, weight-file order) or
+ * write a weight file that hb_model_load accepts. */
+hb_status hb_trainer_get_params(hb_trainer* t, float* out);
+hb_status hb_trainer_save(hb_trainer* t, const char* path);
 
 /* -------------------------------------------------------------- search */
 typedef enum { HB_IDA = 0, HB_BTS = 1 } hb_algo;

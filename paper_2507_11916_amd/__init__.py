@@ -43,6 +43,12 @@ class ModelInfo(C.Structure):
                 ("dims", C.c_int * 8), ("weight_bytes", C.c_int64), ("flops_per_eval", C.c_double)]
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("device", C.c_int), ("max_batch", C.c_int), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("asym", C.c_int),
+                ("alpha", C.c_float)]
+
+
 class Heuristic(C.Structure):
     _fields_ = [("model", C.c_void_p), ("combine", C.c_int), ("classic", C.c_int), ("pdb", C.c_void_p)]
 
@@ -104,6 +110,15 @@ def lib():
             "hb_eval_batch_dev_n": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
             "hb_model_set_tile": ([vp, C.c_int], C.c_int),
             "hb_model_tune": ([vp, vp, i64, vp, C.c_int], C.c_int),
+            "hb_model_profile": ([vp, C.c_int], C.c_int),
+            "hb_model_profile_read": ([vp, vp], C.c_int),
+            "hb_trainer_create": ([C.c_char_p, C.POINTER(TrainOpts), C.POINTER(vp)], C.c_int),
+            "hb_trainer_free": ([vp], None),
+            "hb_trainer_n_params": ([vp], i64),
+            "hb_train_step": ([vp, vp, vp, i64, vp, vp], C.c_int),
+            "hb_train_grad": ([vp, vp, vp, i64, vp, vp], C.c_int),
+            "hb_trainer_get_params": ([vp, vp], C.c_int),
+            "hb_trainer_save": ([vp, C.c_char_p], C.c_int),
             "cbdfs_params_default": ([C.POINTER(Params)], None),
             "cbdfs_solve": ([C.c_int, vp, C.POINTER(Heuristic), C.c_int, C.c_int, C.POINTER(Params),
                              C.POINTER(Result)], C.c_int),
@@ -257,6 +272,49 @@ class Model:
         rep = np.zeros(32, dtype=np.float64)
         _check(lib().hb_model_tune(self.handle, C.c_void_p(d_packed.data_ptr()), n, _np_ptr(rep), 32))
         return [(int(rep[2 * i]), float(rep[2 * i + 1])) for i in range(16) if rep[2 * i + 1] > 0]
+
+
+# --------------------------------------------------------------- training
+class Trainer:
+    """On-GPU training of a sliding-tile regression network (hb_trainer)."""
+
+    def __init__(self, path, prec=HB_BF16, max_batch=8192, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 asym=False, alpha=4.0, device=0):
+        o = TrainOpts(prec, device, max_batch, lr, beta1, beta2, eps, int(asym), alpha)
+        h = C.c_void_p()
+        _check(lib().hb_trainer_create(path.encode(), C.byref(o), C.byref(h)))
+        self.handle = h
+        self.n_params = lib().hb_trainer_n_params(h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hb_trainer_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, d_packed, d_labels, n=None, want_loss=True, stream=None):
+        n = d_packed.shape[0] if n is None else n
+        loss = C.c_float(0.0)
+        _check(lib().hb_train_step(self.handle, C.c_void_p(d_packed.data_ptr()), C.c_void_p(d_labels.data_ptr()), n,
+                                   C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def grad(self, d_packed, d_labels, d_grads, n=None):
+        n = d_packed.shape[0] if n is None else n
+        loss = C.c_float(0.0)
+        _check(lib().hb_train_grad(self.handle, C.c_void_p(d_packed.data_ptr()), C.c_void_p(d_labels.data_ptr()), n,
+                                   C.c_void_p(d_grads.data_ptr()), C.byref(loss)))
+        return loss.value
+
+    def params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().hb_trainer_get_params(self.handle, _np_ptr(out)))
+        return out
+
+    def save(self, path):
+        _check(lib().hb_trainer_save(self.handle, path.encode()))
 
 
 # ----------------------------------------------------------------- search

@@ -159,6 +159,7 @@ struct GemmArgs {
     float out_inv_scale;     // fp8: 1 / scale of C
     int relu;
     int persistent;          // loop over tiles with a grid stride
+    const uint8_t* Mk;       // mask (C's type and layout) or null: zero where Mk <= 0
 };
 
 template <int PREC>
@@ -168,7 +169,16 @@ struct Ty {
 
 __device__ __forceinline__ int swz(int row, int chunk) { return row * 128 + ((chunk ^ (row & 7)) << 4); }
 
-template <int PREC, int BM, int BN>
+// OUTT is the type of C, R and Mk (0 f32, 1 bf16, 2 fp8): equal to PREC for the
+// forward and input-gradient products, float32 for weight gradients.
+template <int OUTT>
+__device__ __forceinline__ float load_out_t(const uint8_t* p, size_t o, float fp8_scale) {
+    if (OUTT == 0) return reinterpret_cast<const float*>(p)[o];
+    if (OUTT == 1) return bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[o]);
+    return fp8_to_f32(p[o]) * fp8_scale;
+}
+
+template <int PREC, int OUTT, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int EB = Ty<PREC>::EB;
     constexpr int TI = BM / 64, TJ = BN / 64;  // MFMA tiles per wave
@@ -297,7 +307,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         const int half = lane >> 5, c32 = lane & 31;
         for (int j = 0; j < TJ; j++) {
             const int n = n0 + wn * (BN / 2) + j * 32 + c32;
-            const float bn = g.bias[n];
+            const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
             for (int i = 0; i < TI; i++) {
                 for (int a = 0; a < 4; a++)
@@ -306,13 +316,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         float v = acc[i][j][4 * a + b] * sn + bn;
                         const size_t o = (size_t)m * g.ldc + n;
                         if (g.R) {
-                            if (PREC == 0) v += reinterpret_cast<const float*>(g.R)[o];
-                            else if (PREC == 1) v += bf16_to_f32(reinterpret_cast<const uint16_t*>(g.R)[o]);
-                            else v += fp8_to_f32(g.R[o]) * g.r_scale;
+                            v += load_out_t<OUTT>(g.R, o, g.r_scale);
                         }
                         if (g.relu) v = fmaxf(v, 0.f);
-                        if (PREC == 0) reinterpret_cast<float*>(g.C)[o] = v;
-                        else if (PREC == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
+                        if (g.Mk && !(load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f)) v = 0.f;
+                        if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
+                        else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
                         else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
                     }
             }
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs h) {
         } else {
             const float f = h.mode == 1 ? rintf(v) : floorf(v);
             hv = f < 0.f ? 0 : f > 1e9f ? 1000000000 : (int)f;
-            if (md >= 0 && md < hv) hv = md;
+            if (md >= 0) hv = h.combine_md == 2 ? max(hv, md) : min(hv, md);
         }
         if (h.raw) h.raw[r] = v;
     }
@@ -455,10 +464,11 @@ bool launch_gather(const GatherLaunch& L, hipStream_t s) {
     return false;
 }
 
-template <int PREC, int BM, int BN>
+template <int PREC, int OUTT, int BM, int BN>
 static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     GemmArgs g;
     g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
     g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
@@ -470,7 +480,7 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
     if (L.m_dev) g.persistent = 1;  // tile count known only on the device: stride over the cap
     const size_t lds = 2 * (size_t)(BM + BN) * 128;
-    hipLaunchKernelGGL((gemm_kernel<PREC, BM, BN>), dim3(grid), dim3(256), lds, s, g);
+    hipLaunchKernelGGL((gemm_kernel<PREC, OUTT, BM, BN>), dim3(grid), dim3(256), lds, s, g);
 }
 
 int gemm_tile_count() { return 3; }
@@ -480,22 +490,22 @@ void gemm_tile_shape(int id, int* bm, int* bn) {
     *bn = T[id][1];
 }
 
-template <int PREC>
+template <int PREC, int OUTT>
 static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
     switch (L.tile) {
-        case 0: launch_gemm_t<PREC, 128, 128>(L, s); return true;
-        case 1: launch_gemm_t<PREC, 128, 256>(L, s); return true;
-        case 2: launch_gemm_t<PREC, 64, 128>(L, s); return true;
+        case 0: launch_gemm_t<PREC, OUTT, 128, 128>(L, s); return true;
+        case 1: launch_gemm_t<PREC, OUTT, 128, 256>(L, s); return true;
+        case 2: launch_gemm_t<PREC, OUTT, 64, 128>(L, s); return true;
     }
     return false;
 }
 
 bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
-    switch (L.prec) {
-        case 0: return launch_gemm_p<0>(L, s);
-        case 1: return launch_gemm_p<1>(L, s);
-        case 2: return launch_gemm_p<2>(L, s);
-    }
+    const int out = L.out_type < 0 ? L.prec : L.out_type;
+    if (L.prec == 0 && out == 0) return launch_gemm_p<0, 0>(L, s);
+    if (L.prec == 1 && out == 1) return launch_gemm_p<1, 1>(L, s);
+    if (L.prec == 1 && out == 0) return launch_gemm_p<1, 0>(L, s);
+    if (L.prec == 2 && out == 2) return launch_gemm_p<2, 2>(L, s);
     return false;
 }
 
@@ -518,25 +528,26 @@ bool launch_head(const HeadArgs& H, int prec, int m_cap, hipStream_t s) {
     return launch_head_t<2, 1>(H, m_cap, s);
 }
 
-template <int PREC, int BM, int BN>
+template <int PREC, int OUTT, int BM, int BN>
 static hipError_t set_lds_attr() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<PREC, BM, BN>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<PREC, OUTT, BM, BN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (BM + BN) * 128);
 }
 
-template <int PREC>
+template <int PREC, int OUTT>
 static hipError_t set_lds_attr_p() {
-    hipError_t e = set_lds_attr<PREC, 128, 128>();
-    if (e == hipSuccess) e = set_lds_attr<PREC, 128, 256>();
-    if (e == hipSuccess) e = set_lds_attr<PREC, 64, 128>();
+    hipError_t e = set_lds_attr<PREC, OUTT, 128, 128>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 128, 256>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 64, 128>();
     return e;
 }
 
 // Blocks of the larger tiles use more than 64 KiB of LDS (gfx950 has 160 KiB).
 hipError_t gemm_prepare_attributes() {
-    hipError_t e = set_lds_attr_p<0>();
-    if (e == hipSuccess) e = set_lds_attr_p<1>();
-    if (e == hipSuccess) e = set_lds_attr_p<2>();
+    hipError_t e = set_lds_attr_p<0, 0>();
+    if (e == hipSuccess) e = set_lds_attr_p<1, 1>();
+    if (e == hipSuccess) e = set_lds_attr_p<1, 0>();
+    if (e == hipSuccess) e = set_lds_attr_p<2, 2>();
     return e;
 }
 

@@ -37,6 +37,8 @@ struct GemmLaunch {
     float a_scale, r_scale, out_inv_scale;
     int relu;
     int persistent_grid;    // > 0: at most this many blocks, striding over tiles
+    int out_type = -1;      // type of C/R/Mk: -1 same as prec; 0 f32 (weight gradients from bf16)
+    const void* Mk = nullptr;  // zero the result where this tensor (C's layout) is <= 0
 };
 
 struct HeadArgs {

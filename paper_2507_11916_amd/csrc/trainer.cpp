@@ -1,0 +1,492 @@
+// On-GPU training of a sliding-tile regression network (hb_trainer, include/hb.h).
+//
+// Step: forward with every activation saved; head kernel (loss, dL/dy,
+// output-layer gradient); backward through residual blocks and dense layers
+// with input-gradient GEMMs (fused ReLU mask and residual add) and weight-
+// gradient GEMMs on transposed activations (FP32 output, bias gradients as
+// column sums fused into the transposes); layer-1 gradient by scatter-add;
+// Adam on FP32 master weights, re-casting the working copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "hb.h"
+#include "kernels.hpp"
+#include "model.hpp"
+#include "train.hpp"
+
+namespace hb {
+namespace {
+
+struct TLayer {
+    int K, N, K_pad, N_pad;
+    float *master, *m, *v;     // K*N
+    float *bias, *bm, *bv;     // N_pad (the working bias is the master)
+    void* Wt;                  // [N_pad][K_pad] forward operand
+    void* Wkn;                 // [K_pad][N_pad] input-gradient operand
+    float* dW;                 // [K_pad][N_pad]
+    float* db;                 // [N_pad]
+    int in_act, out_act, res_act;
+};
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+}  // namespace hb
+
+struct hb_trainer {
+    int device = 0;
+    hb_train_opts o{};
+    hb::NetSpec spec;
+    int t = 1, eb = 2;
+    int side = 4, P = 16, S = 16, rows1 = 256;
+    int N1 = 0, N1_pad = 0, H = 0, H_pad = 0, M_pad = 0, W_pad = 0;
+    float *l1_master = nullptr, *l1_m = nullptr, *l1_v = nullptr;
+    void* l1_table = nullptr;
+    float *l1_bias = nullptr, *l1_bm = nullptr, *l1_bv = nullptr;
+    float *dW1 = nullptr, *db1 = nullptr;
+    float *ho_master = nullptr, *ho_m = nullptr, *ho_v = nullptr;
+    void* ho_W = nullptr;
+    float *ho_b = nullptr, *ho_bm = nullptr, *ho_bv = nullptr;
+    float *dWo = nullptr, *dbo = nullptr;
+    std::vector<hb::TLayer> L;
+    int n_act = 0;
+    std::vector<void*> act;
+    void *G = nullptr, *G2 = nullptr, *XT = nullptr, *GT = nullptr;
+    float* d_loss = nullptr;
+    int step = 0;
+    std::vector<void*> allocs;
+};
+
+namespace hb {
+namespace {
+
+hb_status dalloc(hb_trainer* tr, size_t bytes, void** p) {
+    if (hipMalloc(p, bytes ? bytes : 4) != hipSuccess) return fail(HB_E_NOMEM, "hipMalloc of %zu bytes", bytes);
+    tr->allocs.push_back(*p);
+    HB_HIP(hipMemset(*p, 0, bytes ? bytes : 4));
+    return HB_OK;
+}
+
+template <class T>
+hb_status dalloc_t(hb_trainer* tr, size_t count, T** p) {
+    void* q = nullptr;
+    hb_status st = dalloc(tr, count * sizeof(T), &q);
+    *p = (T*)q;
+    return st;
+}
+
+// Upload a float32 host array and return device pointer.
+hb_status up_f32(hb_trainer* tr, const std::vector<float>& h, float** d) {
+    hb_status st = dalloc_t(tr, h.size(), d);
+    if (st != HB_OK) return st;
+    HB_HIP(hipMemcpy(*d, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+    return HB_OK;
+}
+
+// Upload a working copy (fp32 or bf16) of `vals` (float32, already padded).
+hb_status up_work(hb_trainer* tr, const std::vector<float>& vals, void** d) {
+    hb_status st = dalloc(tr, vals.size() * tr->eb, d);
+    if (st != HB_OK) return st;
+    if (tr->eb == 4) {
+        HB_HIP(hipMemcpy(*d, vals.data(), vals.size() * 4, hipMemcpyHostToDevice));
+    } else {
+        std::vector<uint16_t> b(vals.size());
+        for (size_t i = 0; i < vals.size(); i++) b[i] = host_bf16(vals[i]);
+        HB_HIP(hipMemcpy(*d, b.data(), b.size() * 2, hipMemcpyHostToDevice));
+    }
+    return HB_OK;
+}
+
+hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, void* C, int ldc, const void* R,
+               const void* Mk, const float* bias, int M, int N, int K, int relu, int out_type, hipStream_t s) {
+    GemmLaunch g{};
+    g.prec = tr->t;
+    g.out_type = out_type;
+    g.A = A; g.Bt = Bt; g.C = C; g.R = R; g.Mk = Mk; g.bias = bias;
+    g.m_host = M; g.m_cap = M;
+    g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.a_scale = g.r_scale = g.out_inv_scale = 1.f;
+    g.relu = relu;
+    g.tile = (N % 256 == 0 && M >= 2048) ? 1 : 2;  // 128x256 or 64x128
+    if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM for this precision");
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status transpose(hb_trainer* tr, const void* in, int ld_in, void* out, int ld_out, int R, int C, float* colsum,
+                    int rows_sum, hipStream_t s) {
+    TransposeArgs a{in, ld_in, out, ld_out, R, C, colsum, rows_sum};
+    launch_transpose(a, tr->t, s);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+// Forward (activations saved) + backward; gradients left in the grad buffers.
+hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels, int n, hipStream_t s) {
+    const int Me = (int)round_up(n, 128);
+    const int t = tr->t;
+    // zero the accumulated gradients
+    launch_fill(tr->dW1, (int64_t)tr->rows1 * tr->N1_pad, 0.f, s);
+    launch_fill(tr->db1, tr->N1_pad, 0.f, s);
+    launch_fill(tr->dWo, tr->H_pad, 0.f, s);
+    launch_fill(tr->dbo, 1, 0.f, s);
+    launch_fill(tr->d_loss, 1, 0.f, s);
+    for (auto& l : tr->L) launch_fill(l.db, l.N_pad, 0.f, s);
+    // forward
+    GatherLaunch G{};
+    G.domain = tr->spec.domain;
+    G.prec = t;
+    G.packed = d_packed;
+    G.n_host = n;
+    G.m_rows = Me;
+    G.table = tr->l1_table;
+    G.bias = tr->l1_bias;
+    G.N = tr->N1_pad;
+    G.ld_out = tr->W_pad;
+    G.out = tr->act[0];
+    G.out_inv_scale = 1.f;
+    if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "layer-1 kernel");
+    HB_HIP(hipGetLastError());
+    hb_status st;
+    for (auto& l : tr->L) {
+        st = gemm(tr, tr->act[l.in_act], tr->W_pad, l.Wt, l.K_pad, tr->act[l.out_act], tr->W_pad,
+                  l.res_act >= 0 ? tr->act[l.res_act] : nullptr, nullptr, l.bias, Me, l.N_pad, l.K_pad, 1, -1, s);
+        if (st != HB_OK) return st;
+    }
+    HeadTrainArgs h{};
+    h.X = tr->act[tr->n_act - 1];
+    h.ldx = tr->W_pad;
+    h.K = tr->H_pad;
+    h.W = tr->ho_W;
+    h.b = tr->ho_b;
+    h.labels = d_labels;
+    h.n = n;
+    h.m_pad = Me;
+    h.inv_n = 1.f / (float)n;
+    h.asym = tr->o.asym;
+    h.alpha = tr->o.alpha;
+    h.delta = tr->G;
+    h.dWo = tr->dWo;
+    h.dbo = tr->dbo;
+    h.loss = tr->d_loss;
+    if (!launch_head_train(h, t, s)) return fail(HB_E_UNSUPPORTED, "head width");
+    HB_HIP(hipGetLastError());
+    // backward: cur holds the gradient at the pre-activation of the current layer output
+    void* cur = tr->G;
+    void* other = tr->G2;
+    for (int j = (int)tr->L.size() - 1; j >= 0; j--) {
+        TLayer& l = tr->L[j];
+        const bool res_b = l.res_act >= 0;
+        // weight and bias gradient: dW = X^T cur, db = column sums of cur
+        if ((st = transpose(tr, cur, tr->W_pad, tr->GT, Me, Me, l.N_pad, l.db, n, s)) != HB_OK) return st;
+        if ((st = transpose(tr, tr->act[l.in_act], tr->W_pad, tr->XT, Me, Me, l.K_pad, nullptr, 0, s)) != HB_OK) return st;
+        if ((st = gemm(tr, tr->XT, Me, tr->GT, Me, l.dW, l.N_pad, nullptr, nullptr, nullptr, l.K_pad, l.N_pad, Me, 0, 0, s)) != HB_OK)
+            return st;
+        // input gradient, masked by the input activation (post-ReLU, so > 0 marks the active units)
+        if (res_b) {
+            // t-gradient of a residual block: (cur W_b^T) * [t > 0]; keep cur for the identity path
+            if ((st = gemm(tr, cur, tr->W_pad, l.Wkn, l.N_pad, other, tr->W_pad, nullptr, tr->act[l.in_act], nullptr, Me,
+                           l.K_pad, l.N_pad, 0, -1, s)) != HB_OK)
+                return st;
+            TLayer& la = tr->L[j - 1];
+            if ((st = transpose(tr, other, tr->W_pad, tr->GT, Me, Me, la.N_pad, la.db, n, s)) != HB_OK) return st;
+            if ((st = transpose(tr, tr->act[la.in_act], tr->W_pad, tr->XT, Me, Me, la.K_pad, nullptr, 0, s)) != HB_OK) return st;
+            if ((st = gemm(tr, tr->XT, Me, tr->GT, Me, la.dW, la.N_pad, nullptr, nullptr, nullptr, la.K_pad, la.N_pad, Me, 0, 0, s)) !=
+                HB_OK)
+                return st;
+            // x-gradient: (t-grad W_a^T + cur) * [x_in > 0], written over cur
+            if ((st = gemm(tr, other, tr->W_pad, la.Wkn, la.N_pad, cur, tr->W_pad, cur, tr->act[la.in_act], nullptr, Me,
+                           la.K_pad, la.N_pad, 0, -1, s)) != HB_OK)
+                return st;
+            j--;  // the block's first layer is done
+        } else {
+            if ((st = gemm(tr, cur, tr->W_pad, l.Wkn, l.N_pad, other, tr->W_pad, nullptr, tr->act[l.in_act], nullptr, Me,
+                           l.K_pad, l.N_pad, 0, -1, s)) != HB_OK)
+                return st;
+            std::swap(cur, other);
+        }
+    }
+    ScatterArgs sa{};
+    sa.dz = cur;
+    sa.ld = tr->W_pad;
+    sa.packed = d_packed;
+    sa.n = n;
+    sa.N1 = tr->N1_pad;
+    sa.dW1 = tr->dW1;
+    sa.ld_w = tr->N1_pad;
+    sa.db1 = tr->db1;
+    sa.states_per_block = 256;
+    if (!launch_scatter_l1(sa, t, tr->side, s)) return fail(HB_E_UNSUPPORTED, "layer-1 gradient");
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+void adam(hb_trainer* tr, float* master, float* m, float* v, const float* grad, int64_t gk, int64_t gn, int K, int N,
+          void* out1, int64_t s1k, int64_t s1n, void* out2, int64_t s2k, int64_t s2n, hipStream_t s) {
+    AdamArgs a{};
+    a.master = master; a.m = m; a.v = v; a.grad = grad; a.gk = gk; a.gn = gn; a.K = K; a.N = N;
+    a.lr = tr->o.lr; a.b1 = tr->o.beta1; a.b2 = tr->o.beta2; a.eps = tr->o.eps;
+    a.c1 = 1.f - std::pow(tr->o.beta1, (float)tr->step);
+    a.c2 = 1.f - std::pow(tr->o.beta2, (float)tr->step);
+    a.out1 = out1; a.s1k = s1k; a.s1n = s1n; a.out2 = out2; a.s2k = s2k; a.s2n = s2n;
+    launch_adam(a, tr->t, s);
+}
+
+void apply_adam(hb_trainer* tr, hipStream_t s) {
+    tr->step++;
+    adam(tr, tr->l1_master, tr->l1_m, tr->l1_v, tr->dW1, tr->N1_pad, 1, tr->rows1, tr->N1, tr->l1_table, tr->N1_pad, 1,
+         nullptr, 0, 0, s);
+    adam(tr, tr->l1_bias, tr->l1_bm, tr->l1_bv, tr->db1, 0, 1, 1, tr->N1, nullptr, 0, 0, nullptr, 0, 0, s);
+    for (auto& l : tr->L) {
+        adam(tr, l.master, l.m, l.v, l.dW, l.N_pad, 1, l.K, l.N, l.Wt, 1, l.K_pad, l.Wkn, l.N_pad, 1, s);
+        adam(tr, l.bias, l.bm, l.bv, l.db, 0, 1, 1, l.N, nullptr, 0, 0, nullptr, 0, 0, s);
+    }
+    adam(tr, tr->ho_master, tr->ho_m, tr->ho_v, tr->dWo, 1, 0, tr->H, 1, tr->ho_W, 1, 0, nullptr, 0, 0, s);
+    adam(tr, tr->ho_b, tr->ho_bm, tr->ho_bv, tr->dbo, 0, 1, 1, 1, nullptr, 0, 0, nullptr, 0, 0, s);
+}
+
+// Copy rows x cols floats from a padded device array (row stride ld) to dst.
+hb_status copy2d(float* dst, const float* src, int rows, int cols, int ld, hipStream_t s) {
+    HB_HIP(hipMemcpy2DAsync(dst, (size_t)cols * 4, src, (size_t)ld * 4, (size_t)cols * 4, rows, hipMemcpyDeviceToDevice, s));
+    return HB_OK;
+}
+
+hb_status check_batch(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels, int64_t n) {
+    if (!d_packed || !d_labels) return fail(HB_E_INVAL, "null device buffer");
+    if (n < 1 || n > tr->o.max_batch) return fail(HB_E_INVAL, "n must be in 1..%d", tr->o.max_batch);
+    return HB_OK;
+}
+
+}  // namespace
+}  // namespace hb
+
+using namespace hb;
+
+extern "C" {
+
+hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trainer** out) {
+    if (!path || !out) return fail(HB_E_INVAL, "null argument");
+    hb_train_opts o{HB_BF16, 0, 8192, 1e-3f, 0.9f, 0.999f, 1e-8f, 0, 4.f};
+    if (opts) o = *opts;
+    if (o.prec != HB_BF16 && o.prec != HB_FP32) return fail(HB_E_UNSUPPORTED, "training runs in BF16 or FP32");
+    if (o.max_batch < 1 || o.max_batch > (1 << 20)) return fail(HB_E_INVAL, "max_batch out of range");
+    NetSpec spec;
+    const char* why = "";
+    if (!read_weight_file(path, &spec, &why)) return fail(HB_E_INVAL, "%s: %s", path, why);
+    if (spec.domain == 2) return fail(HB_E_UNSUPPORTED, "training supports the sliding-tile domains");
+    if (spec.head_kind != 0 || spec.n_out != 1) return fail(HB_E_UNSUPPORTED, "training needs a regression head");
+    for (int d : spec.dims)
+        if (d > 1024) return fail(HB_E_UNSUPPORTED, "hidden widths above 1024 are not supported in training");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(HB_E_DEVICE, "no HIP device available");
+    if (o.device < 0 || o.device >= ndev) return fail(HB_E_INVAL, "device out of range");
+    HB_HIP(hipSetDevice(o.device));
+    static bool attrs = false;
+    if (!attrs) { HB_HIP(gemm_prepare_attributes()); attrs = true; }
+    auto tr = std::make_unique<hb_trainer>();
+    hb_trainer* T = tr.get();
+    T->device = o.device;
+    T->o = o;
+    T->spec = spec;
+    T->t = o.prec == HB_FP32 ? 0 : 1;
+    T->eb = o.prec == HB_FP32 ? 4 : 2;
+    T->side = spec.domain == 0 ? 3 : 4;
+    T->P = T->S = T->side * T->side;
+    T->rows1 = T->P * T->S;
+    auto pad = [](int v) { return (int)round_up(v, 128); };
+    T->N1 = spec.dims[0];
+    T->N1_pad = pad(T->N1);
+    T->H = spec.dims.back();
+    T->H_pad = pad(T->H);
+    T->M_pad = (int)round_up(o.max_batch, 128);
+    int wmax = T->N1_pad;
+    for (int d : spec.dims) wmax = std::max(wmax, pad(d));
+    T->W_pad = wmax;
+    const auto& TS = spec.tensors;
+    hb_status st;
+    // layer 1
+    if ((st = up_f32(T, TS[0], &T->l1_master)) != HB_OK) return st;
+    if ((st = dalloc_t(T, TS[0].size(), &T->l1_m)) != HB_OK || (st = dalloc_t(T, TS[0].size(), &T->l1_v)) != HB_OK) return st;
+    {
+        std::vector<float> tab((size_t)T->rows1 * T->N1_pad, 0.f);
+        for (int r = 0; r < T->rows1; r++)
+            for (int j = 0; j < T->N1; j++) tab[(size_t)r * T->N1_pad + j] = TS[0][(size_t)r * T->N1 + j];
+        if ((st = up_work(T, tab, &T->l1_table)) != HB_OK) return st;
+        std::vector<float> b(T->N1_pad, 0.f);
+        for (int j = 0; j < T->N1; j++) b[j] = TS[1][j];
+        if ((st = up_f32(T, b, &T->l1_bias)) != HB_OK) return st;
+    }
+    if ((st = dalloc_t(T, T->N1_pad, &T->l1_bm)) != HB_OK || (st = dalloc_t(T, T->N1_pad, &T->l1_bv)) != HB_OK) return st;
+    if ((st = dalloc_t(T, (size_t)T->rows1 * T->N1_pad, &T->dW1)) != HB_OK || (st = dalloc_t(T, T->N1_pad, &T->db1)) != HB_OK)
+        return st;
+    // matrix layers
+    const int nd = (int)spec.dims.size();
+    T->n_act = nd + 2 * spec.n_res;
+    int ti = 2;
+    auto add = [&](int K, int N, int in_act, int out_act, int res_act) -> hb_status {
+        TLayer l{};
+        l.K = K; l.N = N; l.K_pad = pad(K); l.N_pad = pad(N);
+        l.in_act = in_act; l.out_act = out_act; l.res_act = res_act;
+        hb_status s2;
+        if ((s2 = up_f32(T, TS[ti], &l.master)) != HB_OK) return s2;
+        if ((s2 = dalloc_t(T, TS[ti].size(), &l.m)) != HB_OK || (s2 = dalloc_t(T, TS[ti].size(), &l.v)) != HB_OK) return s2;
+        std::vector<float> b(l.N_pad, 0.f);
+        for (int j = 0; j < N; j++) b[j] = TS[ti + 1][j];
+        if ((s2 = up_f32(T, b, &l.bias)) != HB_OK) return s2;
+        if ((s2 = dalloc_t(T, l.N_pad, &l.bm)) != HB_OK || (s2 = dalloc_t(T, l.N_pad, &l.bv)) != HB_OK) return s2;
+        std::vector<float> wt((size_t)l.N_pad * l.K_pad, 0.f), wkn((size_t)l.K_pad * l.N_pad, 0.f);
+        for (int k = 0; k < K; k++)
+            for (int n = 0; n < N; n++) {
+                wt[(size_t)n * l.K_pad + k] = TS[ti][(size_t)k * N + n];
+                wkn[(size_t)k * l.N_pad + n] = TS[ti][(size_t)k * N + n];
+            }
+        if ((s2 = up_work(T, wt, &l.Wt)) != HB_OK || (s2 = up_work(T, wkn, &l.Wkn)) != HB_OK) return s2;
+        if ((s2 = dalloc_t(T, (size_t)l.K_pad * l.N_pad, &l.dW)) != HB_OK || (s2 = dalloc_t(T, l.N_pad, &l.db)) != HB_OK) return s2;
+        T->L.push_back(l);
+        ti += 2;
+        return HB_OK;
+    };
+    for (int i = 1; i < nd; i++)
+        if ((st = add(spec.dims[i - 1], spec.dims[i], i - 1, i, -1)) != HB_OK) return st;
+    int x_act = nd - 1;
+    for (int r = 0; r < spec.n_res; r++) {
+        if ((st = add(T->H, T->H, x_act, nd + 2 * r, -1)) != HB_OK) return st;
+        if ((st = add(T->H, T->H, nd + 2 * r, nd + 2 * r + 1, x_act)) != HB_OK) return st;
+        x_act = nd + 2 * r + 1;
+    }
+    // head
+    if ((st = up_f32(T, TS[ti], &T->ho_master)) != HB_OK) return st;
+    if ((st = dalloc_t(T, T->H, &T->ho_m)) != HB_OK || (st = dalloc_t(T, T->H, &T->ho_v)) != HB_OK) return st;
+    {
+        std::vector<float> hw(T->H_pad, 0.f);
+        for (int k = 0; k < T->H; k++) hw[k] = TS[ti][k];
+        if ((st = up_work(T, hw, &T->ho_W)) != HB_OK) return st;
+    }
+    if ((st = up_f32(T, TS[ti + 1], &T->ho_b)) != HB_OK) return st;
+    if ((st = dalloc_t(T, 1, &T->ho_bm)) != HB_OK || (st = dalloc_t(T, 1, &T->ho_bv)) != HB_OK) return st;
+    if ((st = dalloc_t(T, T->H_pad, &T->dWo)) != HB_OK || (st = dalloc_t(T, 1, &T->dbo)) != HB_OK) return st;
+    // activations and scratch
+    const size_t abytes = (size_t)T->M_pad * T->W_pad * T->eb;
+    T->act.resize(T->n_act);
+    for (int a = 0; a < T->n_act; a++)
+        if ((st = dalloc(T, abytes, &T->act[a])) != HB_OK) return st;
+    if ((st = dalloc(T, abytes, &T->G)) != HB_OK || (st = dalloc(T, abytes, &T->G2)) != HB_OK ||
+        (st = dalloc(T, abytes, &T->XT)) != HB_OK || (st = dalloc(T, abytes, &T->GT)) != HB_OK)
+        return st;
+    if ((st = dalloc_t(T, 1, &T->d_loss)) != HB_OK) return st;
+    *out = tr.release();
+    return HB_OK;
+}
+
+void hb_trainer_free(hb_trainer* t) {
+    if (!t) return;
+    (void)hipSetDevice(t->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : t->allocs) (void)hipFree(p);
+    delete t;
+}
+
+int64_t hb_trainer_n_params(const hb_trainer* t) {
+    if (!t) return -1;
+    int64_t n = 0;
+    for (const auto& v : t->spec.tensors) n += (int64_t)v.size();
+    return n;
+}
+
+hb_status hb_train_step(hb_trainer* t, const uint8_t* d_packed, const float* d_labels, int64_t n, float* loss_out,
+                        void* stream) {
+    if (!t) return fail(HB_E_INVAL, "null trainer");
+    hb_status st = check_batch(t, d_packed, d_labels, n);
+    if (st != HB_OK) return st;
+    HB_HIP(hipSetDevice(t->device));
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = fwd_bwd(t, d_packed, d_labels, (int)n, s)) != HB_OK) return st;
+    apply_adam(t, s);
+    HB_HIP(hipGetLastError());
+    if (loss_out) {
+        HB_HIP(hipMemcpyAsync(loss_out, t->d_loss, 4, hipMemcpyDeviceToHost, s));
+        HB_HIP(hipStreamSynchronize(s));
+    }
+    return HB_OK;
+}
+
+hb_status hb_train_grad(hb_trainer* t, const uint8_t* d_packed, const float* d_labels, int64_t n, float* d_grads,
+                        float* loss_out) {
+    if (!t || !d_grads) return fail(HB_E_INVAL, "null argument");
+    hb_status st = check_batch(t, d_packed, d_labels, n);
+    if (st != HB_OK) return st;
+    HB_HIP(hipSetDevice(t->device));
+    hipStream_t s = nullptr;
+    if ((st = fwd_bwd(t, d_packed, d_labels, (int)n, s)) != HB_OK) return st;
+    float* p = d_grads;
+    if ((st = copy2d(p, t->dW1, t->rows1, t->N1, t->N1_pad, s)) != HB_OK) return st;
+    p += (size_t)t->rows1 * t->N1;
+    HB_HIP(hipMemcpyAsync(p, t->db1, (size_t)t->N1 * 4, hipMemcpyDeviceToDevice, s));
+    p += t->N1;
+    for (auto& l : t->L) {
+        if ((st = copy2d(p, l.dW, l.K, l.N, l.N_pad, s)) != HB_OK) return st;
+        p += (size_t)l.K * l.N;
+        HB_HIP(hipMemcpyAsync(p, l.db, (size_t)l.N * 4, hipMemcpyDeviceToDevice, s));
+        p += l.N;
+    }
+    HB_HIP(hipMemcpyAsync(p, t->dWo, (size_t)t->H * 4, hipMemcpyDeviceToDevice, s));
+    p += t->H;
+    HB_HIP(hipMemcpyAsync(p, t->dbo, 4, hipMemcpyDeviceToDevice, s));
+    if (loss_out) HB_HIP(hipMemcpyAsync(loss_out, t->d_loss, 4, hipMemcpyDeviceToHost, s));
+    HB_HIP(hipStreamSynchronize(s));
+    return HB_OK;
+}
+
+hb_status hb_trainer_get_params(hb_trainer* t, float* out) {
+    if (!t || !out) return fail(HB_E_INVAL, "null argument");
+    HB_HIP(hipSetDevice(t->device));
+    HB_HIP(hipDeviceSynchronize());
+    float* p = out;
+    HB_HIP(hipMemcpy(p, t->l1_master, (size_t)t->rows1 * t->N1 * 4, hipMemcpyDeviceToHost));
+    p += (size_t)t->rows1 * t->N1;
+    HB_HIP(hipMemcpy(p, t->l1_bias, (size_t)t->N1 * 4, hipMemcpyDeviceToHost));
+    p += t->N1;
+    for (auto& l : t->L) {
+        HB_HIP(hipMemcpy(p, l.master, (size_t)l.K * l.N * 4, hipMemcpyDeviceToHost));
+        p += (size_t)l.K * l.N;
+        HB_HIP(hipMemcpy(p, l.bias, (size_t)l.N * 4, hipMemcpyDeviceToHost));
+        p += l.N;
+    }
+    HB_HIP(hipMemcpy(p, t->ho_master, (size_t)t->H * 4, hipMemcpyDeviceToHost));
+    p += t->H;
+    HB_HIP(hipMemcpy(p, t->ho_b, 4, hipMemcpyDeviceToHost));
+    return HB_OK;
+}
+
+hb_status hb_trainer_save(hb_trainer* t, const char* path) {
+    if (!t || !path) return fail(HB_E_INVAL, "null argument");
+    std::vector<float> flat((size_t)hb_trainer_n_params(t));
+    hb_status st = hb_trainer_get_params(t, flat.data());
+    if (st != HB_OK) return st;
+    std::ofstream f(path, std::ios::binary);
+    if (!f) return fail(HB_E_INVAL, "cannot write %s", path);
+    std::vector<uint32_t> hdr = {0x31574248u, 1u, (uint32_t)t->spec.domain, (uint32_t)t->spec.n_in,
+                                 (uint32_t)t->spec.dims.size()};
+    for (int d : t->spec.dims) hdr.push_back((uint32_t)d);
+    hdr.push_back((uint32_t)t->spec.n_res);
+    hdr.push_back(1u);
+    hdr.push_back(0u);
+    f.write(reinterpret_cast<const char*>(hdr.data()), (std::streamsize)(hdr.size() * 4));
+    f.write(reinterpret_cast<const char*>(flat.data()), (std::streamsize)(flat.size() * 4));
+    if (!f) return fail(HB_E_INVAL, "write failed: %s", path);
+    return HB_OK;
+}
+
+}  // extern "C"

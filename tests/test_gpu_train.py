@@ -1,0 +1,143 @@
+"""On-GPU training (hb_trainer) against the double-precision oracle.
+
+Gradients: FP32 per-tensor max |g_gpu - g_ref| <= 1e-4 * max |g_ref|; BF16
+(bfloat16 weights and activations, float32 accumulation) relative 2-norm error
+<= 3e-2 over all parameters.  One Adam step matches the oracle's Adam applied to
+the oracle's gradient.  The learned 8-puzzle heuristic, trained on
+breadth-first distances and served as max(Manhattan, floor(y - delta)) with
+delta chosen so that no state is over-estimated, finds optimal costs with fewer
+expansions than Manhattan distance alone.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2507_11916_amd as hb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _net(path, dom, dims, n_res, seed, bias_out=8.0):
+    rng = np.random.default_rng(seed)
+    P = 9 if dom == 0 else 16
+    ts = []
+    for name, r, c in synth.net_tensor_shapes(P * P, dims, n_res, 1):
+        if name.startswith("b") or name.endswith("_b"):
+            ts.append(rng.standard_normal(c) * 0.3 + (bias_out if name == "bout" else 0.0))
+        else:
+            ts.append(rng.standard_normal((r, c)) * np.sqrt(2.0 / (P if name == "W0" else r)))
+    synth.write_weights_arrays(path, dom, P * P, dims, n_res, 1, 0, ts)
+    return path
+
+
+def _gpu_grad(path, prec, states, labels, asym):
+    tr = hb.Trainer(path, prec=prec, max_batch=1024, asym=asym, alpha=4.0)
+    dom = 0 if states.shape[1] == 9 else 1
+    d_p = torch.from_numpy(hb.hb_encode(dom, states)).cuda()
+    d_l = torch.from_numpy(labels.astype(np.float32)).cuda()
+    d_g = torch.zeros(tr.n_params, dtype=torch.float32, device="cuda")
+    loss = tr.grad(d_p, d_l, d_g)
+    return loss, d_g.cpu().numpy().astype(np.float64), tr, d_p, d_l
+
+
+@pytest.mark.parametrize("dom,dims,n_res,n", [(1, [128, 128], 1, 300), (0, [128], 2, 200), (1, [1000, 1000], 2, 96)])
+def test_fp32_gradients_match_oracle(tmp_path, dom, dims, n_res, n):
+    path = _net(str(tmp_path / "n.hbw"), dom, dims, n_res, 4)
+    st = synth.stp_walks(3 if dom == 0 else 4, synth.throughput_seeds(n, 55), lengths=60)
+    labels = (np.arange(n) % 37 + 1).astype(np.float64)
+    net = O.Net(path)
+    for asym in (False, True):
+        loss_ref, g_ref, _ = net.loss_grad(st, labels, asym=asym, alpha=4.0)
+        loss, g, _, _, _ = _gpu_grad(path, hb.HB_FP32, st, labels, asym)
+        assert abs(loss - loss_ref) <= 1e-5 * max(1.0, loss_ref)
+        off = 0
+        for name, r, c in synth.net_tensor_shapes(net.n_in, dims, n_res, 1):
+            a, b = g[off:off + r * c], g_ref[off:off + r * c]
+            assert np.abs(a - b).max() <= 1e-4 * max(1e-12, np.abs(b).max()), name
+            off += r * c
+
+
+def test_bf16_gradients_match_oracle(tmp_path):
+    path = _net(str(tmp_path / "n.hbw"), 1, [1000, 1000], 2, 6)
+    st = synth.stp_walks(4, synth.throughput_seeds(128, 77), lengths=60)
+    labels = (np.arange(128) % 41 + 1).astype(np.float64)
+    net = O.Net(path)
+    loss_ref, g_ref, _ = net.loss_grad(st, labels)
+    loss, g, _, _, _ = _gpu_grad(path, hb.HB_BF16, st, labels, False)
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print("bf16 gradient relative error", rel)
+    assert rel <= 3e-2
+    assert abs(loss - loss_ref) <= 2e-2 * loss_ref
+
+
+def test_adam_step_matches_oracle(tmp_path):
+    path = _net(str(tmp_path / "n.hbw"), 1, [128, 128], 1, 8)
+    st = synth.stp_walks(4, synth.throughput_seeds(200, 99), lengths=60)
+    labels = (np.arange(200) % 30 + 1).astype(np.float64)
+    net = O.Net(path)
+    _, g_ref, _ = net.loss_grad(st, labels)
+    tr = hb.Trainer(path, prec=hb.HB_FP32, max_batch=256, lr=1e-3)
+    d_p = torch.from_numpy(hb.hb_encode(1, st)).cuda()
+    d_l = torch.from_numpy(labels.astype(np.float32)).cuda()
+    tr.step(d_p, d_l)
+    w = net.params()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    O.adam_step(w, g_ref, m, v, 1, lr=1e-3)
+    got = tr.params().astype(np.float64)
+    # |update| <= lr for Adam; float32 master weights and gradients
+    assert np.abs(got - w).max() <= 2e-6 + 1e-6 * np.abs(w).max()
+
+
+def test_learned_8puzzle_heuristic_gains_over_manhattan(tmp_path):
+    d, _ = O.bfs8()
+    allst = O.all8()
+    ranks = np.array([O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data) for s in allst])
+    dist = d[ranks].astype(np.float32)
+    md = O.manhattan(0, allst)
+    path = str(tmp_path / "w.hbw")
+    synth.write_weights(path, "stp3_small", seed=11, head_bias=14.0)
+    tr = hb.Trainer(path, prec=hb.HB_BF16, max_batch=8192, lr=2e-3)
+    d_all = torch.from_numpy(hb.hb_encode(0, allst)).cuda()
+    d_lab = torch.from_numpy(dist).cuda()
+    g = torch.Generator(device="cpu").manual_seed(1234)
+    first = None
+    for step in range(1500):
+        idx = torch.randint(0, len(allst), (8192,), generator=g).cuda()
+        loss = tr.step(d_all[idx].contiguous(), d_lab[idx].contiguous(), want_loss=(step % 250 == 0))
+        if loss is not None:
+            first = loss if first is None else first
+            last = loss
+    print("training loss", first, "->", last)
+    assert last < 0.1 * first
+    trained = str(tmp_path / "trained.hbw")
+    tr.save(trained)
+    # offset delta: smallest value with floor(y - delta) <= h* on every state
+    m = hb.Model(trained, prec=hb.HB_BF16, combine_md=0, max_batch=16384)
+    d_h = torch.zeros(len(allst), dtype=torch.int32, device="cuda")
+    d_y = torch.zeros(len(allst), dtype=torch.float32, device="cuda")
+    m.eval_batch(d_all, d_h, d_y)
+    torch.cuda.synchronize()
+    y = d_y.cpu().numpy().astype(np.float64)
+    delta = max(0.0, float(np.max(y - dist)) - 0.999) + 1e-3
+    served = hb.Model(trained, prec=hb.HB_BF16, combine_md=2, offset=delta, max_batch=16384)
+    served.eval_batch(d_all, d_h)
+    torch.cuda.synchronize()
+    h = d_h.cpu().numpy()
+    assert np.all(h <= dist), "over-estimated states"
+    assert np.all(h >= md)
+    print("mean h learned %.2f vs Manhattan %.2f; delta %.3f" % (h.mean(), md.mean(), delta))
+    assert h.mean() > md.mean()
+    exp_nn = exp_md = 0
+    for s in synth.stp3_instances(100):
+        r = hb.cbdfs_solve(0, s, model=served, combine=hb.HB_H_NN, threads=4, params=hb.default_params(batch_size=256))
+        o = O.ida(0, s, hkind=O.H_MD)
+        assert r["cost"] == o["cost"]
+        exp_nn += r["expanded"]
+        exp_md += sum(i["expanded"] for i in o["iters"])
+    print("expanded: learned %d vs Manhattan %d" % (exp_nn, exp_md))
+    assert exp_nn < exp_md
