@@ -22,6 +22,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
+// Native vector (not HIP's uint4 class type): arrays of it stay in registers.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------ conversions
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -213,83 +215,87 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
 
         floatx16 acc[TI][TJ];
-        for (int i = 0; i < TI; i++)
-            for (int j = 0; j < TJ; j++)
-                for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
+        _Pragma("unroll") for (int i = 0; i < TI; i++)
+            _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                _Pragma("unroll") for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
 
-        uint4 ra[A_LD], rb[B_LD];
-        auto gload = [&](int kt) {
-            const int kbyte = kt * 128;
-            for (int i = 0; i < A_LD; i++) {
-                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
-                ra[i] = *reinterpret_cast<const uint4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16);
-            }
-            for (int i = 0; i < B_LD; i++) {
-                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
-                rb[i] = *reinterpret_cast<const uint4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16);
-            }
-        };
-        auto sstore = [&](int buf) {
-            for (int i = 0; i < A_LD; i++) {
-                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
-                *reinterpret_cast<uint4*>(SA(buf) + swz(row, ch)) = ra[i];
-            }
-            for (int i = 0; i < B_LD; i++) {
-                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;
-                *reinterpret_cast<uint4*>(SB(buf) + swz(row, ch)) = rb[i];
-            }
-        };
+        u32x4 ra[A_LD], rb[B_LD];
+        // Global -> registers and registers -> LDS for one K stage (macros, so
+        // that ra/rb stay in registers).
+#define HB_GLOAD(kt_)                                                                                   \
+        {                                                                                               \
+            const int kbyte = (kt_) * 128;                                                              \
+            _Pragma("unroll") for (int i = 0; i < A_LD; i++) {                                          \
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
+                ra[i] = *reinterpret_cast<const u32x4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16); \
+            }                                                                                           \
+            _Pragma("unroll") for (int i = 0; i < B_LD; i++) {                                          \
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
+                rb[i] = *reinterpret_cast<const u32x4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16); \
+            }                                                                                           \
+        }
+#define HB_SSTORE(buf_)                                                                                 \
+        {                                                                                               \
+            _Pragma("unroll") for (int i = 0; i < A_LD; i++) {                                          \
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
+                *reinterpret_cast<u32x4*>(SA(buf_) + swz(row, ch)) = ra[i];                            \
+            }                                                                                           \
+            _Pragma("unroll") for (int i = 0; i < B_LD; i++) {                                          \
+                const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
+                *reinterpret_cast<u32x4*>(SB(buf_) + swz(row, ch)) = rb[i];                            \
+            }                                                                                           \
+        }
 
-        gload(0);
+        HB_GLOAD(0);
         __syncthreads();  // previous tile's readers of buffer 0 are done
-        sstore(0);
+        HB_SSTORE(0);
         __syncthreads();
         for (int kt = 0; kt < ktiles; kt++) {
             const int cur = kt & 1;
-            if (kt + 1 < ktiles) gload(kt + 1);
+            if (kt + 1 < ktiles) HB_GLOAD(kt + 1);
             const uint8_t* a_s = SA(cur);
             const uint8_t* b_s = SB(cur);
             const int half = lane >> 5, r32 = lane & 31;
             if (PREC == 2) {
-                for (int kg = 0; kg < 2; kg++) {
+                _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
                     intx8 af[TI], bfr[TJ];
-                    for (int i = 0; i < TI; i++) {
+                    _Pragma("unroll") for (int i = 0; i < TI; i++) {
                         const int row = wm * (BM / 2) + i * 32 + r32;
-                        const uint4 lo = *reinterpret_cast<const uint4*>(a_s + swz(row, 4 * kg + 2 * half));
-                        const uint4 hi = *reinterpret_cast<const uint4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
+                        const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
+                        const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
                         af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
                     }
-                    for (int j = 0; j < TJ; j++) {
+                    _Pragma("unroll") for (int j = 0; j < TJ; j++) {
                         const int row = wn * (BN / 2) + j * 32 + r32;
-                        const uint4 lo = *reinterpret_cast<const uint4*>(b_s + swz(row, 4 * kg + 2 * half));
-                        const uint4 hi = *reinterpret_cast<const uint4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
+                        const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
+                        const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
                         bfr[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
                     }
-                    for (int i = 0; i < TI; i++)
-                        for (int j = 0; j < TJ; j++)
+                    _Pragma("unroll") for (int i = 0; i < TI; i++)
+                        _Pragma("unroll") for (int j = 0; j < TJ; j++)
                             acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[i], bfr[j], acc[i][j], 0, 0, 0,
                                                                                        127, 0, 127);
                 }
             } else {
-                for (int kg = 0; kg < 4; kg++) {
-                    uint4 af[TI], bfr[TJ];
-                    for (int i = 0; i < TI; i++) {
+                _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
+                    u32x4 af[TI], bfr[TJ];
+                    _Pragma("unroll") for (int i = 0; i < TI; i++) {
                         const int row = wm * (BM / 2) + i * 32 + r32;
-                        af[i] = *reinterpret_cast<const uint4*>(a_s + swz(row, 2 * kg + half));
+                        af[i] = *reinterpret_cast<const u32x4*>(a_s + swz(row, 2 * kg + half));
                     }
-                    for (int j = 0; j < TJ; j++) {
+                    _Pragma("unroll") for (int j = 0; j < TJ; j++) {
                         const int row = wn * (BN / 2) + j * 32 + r32;
-                        bfr[j] = *reinterpret_cast<const uint4*>(b_s + swz(row, 2 * kg + half));
+                        bfr[j] = *reinterpret_cast<const u32x4*>(b_s + swz(row, 2 * kg + half));
                     }
                     if (PREC == 1) {
-                        for (int i = 0; i < TI; i++)
-                            for (int j = 0; j < TJ; j++)
+                        _Pragma("unroll") for (int i = 0; i < TI; i++)
+                            _Pragma("unroll") for (int j = 0; j < TJ; j++)
                                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                                     __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j], 0, 0, 0);
                     } else {
-                        for (int e = 0; e < 4; e++)
-                            for (int i = 0; i < TI; i++)
-                                for (int j = 0; j < TJ; j++) {
+                        _Pragma("unroll") for (int e = 0; e < 4; e++)
+                            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                                _Pragma("unroll") for (int j = 0; j < TJ; j++) {
                                     const uint32_t ai = e == 0 ? af[i].x : e == 1 ? af[i].y : e == 2 ? af[i].z : af[i].w;
                                     const uint32_t bj = e == 0 ? bfr[j].x : e == 1 ? bfr[j].y : e == 2 ? bfr[j].z : bfr[j].w;
                                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj),
@@ -298,20 +304,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                     }
                 }
             }
-            if (kt + 1 < ktiles) sstore(cur ^ 1);
+            if (kt + 1 < ktiles) HB_SSTORE(cur ^ 1);
             __syncthreads();
         }
 
         // Epilogue.  Lane holds, for MFMA tile (i, j), column j*32 + lane%32 and
         // rows i*32 + 8a + 4*(lane/32) + b for a, b in 0..3 (value 4a + b).
         const int half = lane >> 5, c32 = lane & 31;
-        for (int j = 0; j < TJ; j++) {
+        _Pragma("unroll") for (int j = 0; j < TJ; j++) {
             const int n = n0 + wn * (BN / 2) + j * 32 + c32;
             const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
-            for (int i = 0; i < TI; i++) {
-                for (int a = 0; a < 4; a++)
-                    for (int b = 0; b < 4; b++) {
+            _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                _Pragma("unroll") for (int a = 0; a < 4; a++)
+                    _Pragma("unroll") for (int b = 0; b < 4; b++) {
                         const int m = m0 + wm * (BM / 2) + i * 32 + 8 * a + 4 * half + b;
                         float v = acc[i][j][4 * a + b] * sn + bn;
                         const size_t o = (size_t)m * g.ldc + n;
@@ -483,9 +489,9 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_kernel<PREC, OUTT, BM, BN>), dim3(grid), dim3(256), lds, s, g);
 }
 
-int gemm_tile_count() { return 3; }
+int gemm_tile_count() { return 4; }  // 256x256 spills at one wave per SIMD: not offered
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[3][2] = {{128, 128}, {128, 256}, {64, 128}};
+    static const int T[5][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {256, 256}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -496,6 +502,8 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 0: launch_gemm_t<PREC, OUTT, 128, 128>(L, s); return true;
         case 1: launch_gemm_t<PREC, OUTT, 128, 256>(L, s); return true;
         case 2: launch_gemm_t<PREC, OUTT, 64, 128>(L, s); return true;
+        case 3: launch_gemm_t<PREC, OUTT, 256, 128>(L, s); return true;
+        case 4: launch_gemm_t<PREC, OUTT, 256, 256>(L, s); return true;
     }
     return false;
 }
@@ -539,6 +547,8 @@ static hipError_t set_lds_attr_p() {
     hipError_t e = set_lds_attr<PREC, OUTT, 128, 128>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 128, 256>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 64, 128>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 128>();
+    if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 256>();
     return e;
 }
 

@@ -207,6 +207,39 @@ def test_device_count_variant_matches(net_files):
     assert int(d_h[333:].abs().sum()) == 0  # rows past n untouched (zero-initialised)
 
 
+def test_hipgraph_replay_uneven_batches(net_files):
+    """One captured graph (launch shape fixed at 16384 rows, count read on the
+    device) serves every batch size; each replay equals the eager evaluation."""
+    path = net_files["stp4_res"]
+    cap = 16384
+    m = hb.Model(path, prec=hb.HB_BF16, combine_md=True, max_batch=cap)
+    st = synth.stp_walks(4, synth.throughput_seeds(cap, 2024), lengths=200)
+    packed = torch.from_numpy(hb.hb_encode(1, st)).cuda()
+    s = torch.cuda.Stream()
+    d_p = torch.zeros((cap, 8), dtype=torch.uint8, device="cuda")
+    d_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    d_h = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s):
+        m.eval_batch_dev_n(d_p, d_n, cap, d_h, stream=s)  # allocates the stream's workspace before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        m.eval_batch_dev_n(d_p, d_n, cap, d_h, stream=s)
+    sizes = synth.uneven_batch_sizes(77, 6)
+    for size in sizes:
+        d_p[:size] = packed[:size]
+        d_n.fill_(size)
+        d_h.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        eager = torch.zeros(size, dtype=torch.int32, device="cuda")
+        m.eval_batch(packed[:size].contiguous(), eager)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(d_h[:size], eager), size
+        assert int((d_h[size:] != -7).sum()) == 0, size  # rows past n untouched
+
+
 def test_full_size_sampled_rows(net_files):
     """B = 16384 (the largest batch) in the benchmark's launch shape; 48 sampled
     rows against the oracle."""
