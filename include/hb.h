@@ -178,8 +178,11 @@ hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t
 hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_t* d_n, int64_t max_n,
                               int32_t* d_h_out, float* d_raw_out, void* stream);
 
-/* Select the GEMM tile shape (0 = automatic) used by later evaluations on this
- * model; see hb_model_tune. */
+/* Select the GEMM tile shape used by later evaluations on this model:
+ * 0 automatic (autotuned bucket, else a rule on the batch size), 1 128x128,
+ * 2 128x256, 3 64x128, 4 256x128 (LDS-staged, 4 waves), 5 32x32 (one wave per
+ * tile, operands straight from global memory: small batches).  All shapes give
+ * bitwise equal results.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
 /* Autotuner: times every tile shape on n seeded states and keeps the fastest
  * for batches of about that size.  Results (tile id, microseconds) are written
@@ -264,7 +267,8 @@ typedef struct {
 typedef struct {
     int batch_size;        /* states per batch (default 8000) */
     int work_num;          /* subtrees per search thread, workNum (default 8) */
-    int d_init;            /* depth of the initial partitioning tree (default: chosen from threads*work_num) */
+    int d_init;            /* depth of the initial partitioning tree (< 0, the default: the shallowest depth
+                              with at least 1024*threads*work_num work units, capped near 3M tree nodes) */
     int timeout_us;        /* partial-batch flush timeout (default 4000, the paper's 4 ms) */
     int n_slabs;           /* batch buffers kept in host memory (default 4) */
     int flush_when_idle;   /* also flush as soon as every search thread waits on h (default 1) */
@@ -277,6 +281,8 @@ typedef struct {
     int complete_final_iter; /* finish the final iteration (default 0) */
     int32_t start_bound;   /* resume from this bound (< 0: h(start)) */
     int max_iters;         /* safety cap on iterations (default 1000) */
+    int use_graphs;        /* replay each GPU batch as a captured hipGraph (copy in, forward, copy out),
+                              one per power-of-two size bucket (default 1); 0: direct launches */
 } cbdfs_params;
 
 /* Fill p with the defaults listed above. */

@@ -335,6 +335,92 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
 }
 
+// ------------------------------------------------------------ small-batch GEMM
+// One wave per 32 x 32 output tile, operands read from global memory straight
+// into registers (no LDS, no barriers), the next K stage prefetched while the
+// current one is multiplied.  At a few hundred rows or fewer the tiles of
+// gemm_kernel would leave most compute units idle; here every 32 x 32 tile is
+// a block of its own.  Every output element goes through exactly the MFMA
+// sequence of gemm_kernel (the same 16-byte chunk of each 128-byte K stage in
+// each MFMA, the same order), so the two kernels give bitwise equal results
+// and a state's value does not depend on the batch size that picked the kernel.
+template <int PREC, int OUTT>
+__global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
+    constexpr int EB = Ty<PREC>::EB;
+    const int lane = threadIdx.x, half = lane >> 5, r32 = lane & 31;
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + 31) / 32, g.m_tiles_cap);
+    const int n_tiles = g.N / 32;
+    const int tm = blockIdx.x / n_tiles, tn = blockIdx.x % n_tiles;
+    if (tm >= m_tiles) return;
+    const int m0 = tm * 32, n0 = tn * 32;
+    const uint8_t* Ar = g.A + (size_t)(m0 + r32) * g.lda * EB;
+    const uint8_t* Br = g.Bt + (size_t)(n0 + r32) * g.ldb * EB;
+    const int ktiles = g.K * EB / 128;
+    // Byte offset, inside a 128-byte K stage, of this lane's register slot i.
+    // fp32 / bf16: MFMA group i reads chunk 2i + half.  fp8: group kg reads
+    // chunks 4kg + 2half and 4kg + 2half + 1 (slots 2kg and 2kg + 1).
+    int off[4];
+    _Pragma("unroll") for (int i = 0; i < 4; i++)
+        off[i] = 16 * (PREC == 2 ? 4 * (i >> 1) + 2 * half + (i & 1) : 2 * i + half);
+
+    floatx16 acc;
+    _Pragma("unroll") for (int e = 0; e < 16; e++) acc[e] = 0.f;
+    u32x4 a[4], b[4];
+    _Pragma("unroll") for (int i = 0; i < 4; i++) {
+        a[i] = *reinterpret_cast<const u32x4*>(Ar + off[i]);
+        b[i] = *reinterpret_cast<const u32x4*>(Br + off[i]);
+    }
+    for (int kt = 0; kt < ktiles; kt++) {
+        u32x4 na[4], nb[4];
+        if (kt + 1 < ktiles) {
+            const int kbyte = (kt + 1) * 128;
+            _Pragma("unroll") for (int i = 0; i < 4; i++) {
+                na[i] = *reinterpret_cast<const u32x4*>(Ar + kbyte + off[i]);
+                nb[i] = *reinterpret_cast<const u32x4*>(Br + kbyte + off[i]);
+            }
+        }
+        if (PREC == 2) {
+            _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
+                const u32x4 al = a[2 * kg], ah = a[2 * kg + 1], bl = b[2 * kg], bh = b[2 * kg + 1];
+                const intx8 af = intx8{(int)al.x, (int)al.y, (int)al.z, (int)al.w, (int)ah.x, (int)ah.y, (int)ah.z, (int)ah.w};
+                const intx8 bf = intx8{(int)bl.x, (int)bl.y, (int)bl.z, (int)bl.w, (int)bh.x, (int)bh.y, (int)bh.z, (int)bh.w};
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf, acc, 0, 0, 0, 127, 0, 127);
+            }
+        } else if (PREC == 1) {
+            _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[kg]),
+                                                              __builtin_bit_cast(bf16x8, b[kg]), acc, 0, 0, 0);
+        } else {
+            _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
+                _Pragma("unroll") for (int e = 0; e < 4; e++) {
+                    const uint32_t ai = e == 0 ? a[kg].x : e == 1 ? a[kg].y : e == 2 ? a[kg].z : a[kg].w;
+                    const uint32_t bj = e == 0 ? b[kg].x : e == 1 ? b[kg].y : e == 2 ? b[kg].z : b[kg].w;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj), acc, 0, 0, 0);
+                }
+        }
+        if (kt + 1 < ktiles) {
+            _Pragma("unroll") for (int i = 0; i < 4; i++) { a[i] = na[i]; b[i] = nb[i]; }
+        }
+    }
+    // Epilogue, as in gemm_kernel: column n0 + lane%32, rows 8a + 4*half + b.
+    const int n = n0 + r32;
+    const float bn = g.bias ? g.bias[n] : 0.f;
+    const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+    _Pragma("unroll") for (int a4 = 0; a4 < 4; a4++)
+        _Pragma("unroll") for (int b4 = 0; b4 < 4; b4++) {
+            const int m = m0 + 8 * a4 + 4 * half + b4;
+            float v = acc[4 * a4 + b4] * sn + bn;
+            const size_t o = (size_t)m * g.ldc + n;
+            if (g.R) v += load_out_t<OUTT>(g.R, o, g.r_scale);
+            if (g.relu) v = fmaxf(v, 0.f);
+            if (g.Mk && !(load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f)) v = 0.f;
+            if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
+            else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
+            else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+        }
+}
+
 // ------------------------------------------------------------ head
 // One wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o] for o < n_out,
 // lanes own K slices of 4; wave-wide butterfly sums; lane 0 applies the
@@ -489,9 +575,23 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_kernel<PREC, OUTT, BM, BN>), dim3(grid), dim3(256), lds, s, g);
 }
 
-int gemm_tile_count() { return 4; }  // 256x256 spills at one wave per SIMD: not offered
+template <int PREC, int OUTT>
+static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.m_tiles_cap = (L.m_cap + 31) / 32;
+    g.persistent = 0;
+    hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
+}
+
+// Tile 4 is the small-batch kernel (one wave per 32 x 32 tile).
+int gemm_tile_count() { return 5; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[5][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {256, 256}};
+    static const int T[5][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -503,7 +603,7 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 1: launch_gemm_t<PREC, OUTT, 128, 256>(L, s); return true;
         case 2: launch_gemm_t<PREC, OUTT, 64, 128>(L, s); return true;
         case 3: launch_gemm_t<PREC, OUTT, 256, 128>(L, s); return true;
-        case 4: launch_gemm_t<PREC, OUTT, 256, 256>(L, s); return true;
+        case 4: launch_gemm_small<PREC, OUTT>(L, s); return true;
     }
     return false;
 }
@@ -548,7 +648,6 @@ static hipError_t set_lds_attr_p() {
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 128, 256>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 64, 128>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 128>();
-    if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 256>();
     return e;
 }
 

@@ -115,7 +115,10 @@ int choose_tile(const hb_model* m, int64_t M, int N_pad) {
         gemm_tile_shape(it->second, &bm, &bn);
         if (N_pad % bn == 0) return it->second;
     }
-    // Prefer the biggest tile that still gives every compute unit a block.
+    // Up to a few hundred rows: one wave per 32 x 32 tile (bitwise the same
+    // results as the large tiles).  Beyond: the biggest tile that still gives
+    // every compute unit a block.
+    if (M <= 512 && N_pad % 32 == 0) return 4;
     const int order[3] = {1, 0, 2};
     for (int id : order) {
         int bm, bn;
@@ -303,6 +306,12 @@ static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
     auto r = m->ws.emplace(s, w);
     *out = &r.first->second;
     return HB_OK;
+}
+
+hb_status model_prepare(hb_model* m, hipStream_t s) {
+    HB_HIP(hipSetDevice(m->device));
+    Workspace* w = nullptr;
+    return get_ws(m, s, &w);
 }
 
 // Per-kernel timing (hb_model_profile): events bracket each launch on its stream.

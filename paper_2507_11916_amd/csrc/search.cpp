@@ -15,7 +15,10 @@
 //    first record, or when every search thread is waiting on h; it copies the
 //    slab to the GPU, evaluates the network and writes each h back into the
 //    owning node record (ProcessBatch).  Several slabs exist so that the search
-//    threads keep filling while one is evaluated.
+//    threads keep filling while one is evaluated.  On the GPU the copy in, the
+//    forward pass and the copy out of a batch are one hipGraph launch: a graph
+//    per power-of-two size bucket, captured on first use, reads the state count
+//    from device memory, so one graph serves every batch size of its bucket.
 //  * Counting matches serial IDA*: in iteration T a node of the initial tree is
 //    generated iff every strict ancestor has f <= T and is not the goal; such a
 //    node with f <= T is expanded (or is the solution), with f > T it is pruned
@@ -80,8 +83,8 @@ struct Shared;
 
 class Batcher {
 public:
-    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, bool idle_flush)
-        : sh_(sh), cap_(cap), timeout_(timeout_s), idle_flush_(idle_flush), n_slabs_(n_slabs) {}
+    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, bool idle_flush, bool graphs)
+        : sh_(sh), cap_(cap), timeout_(timeout_s), idle_flush_(idle_flush), use_graphs_(graphs), n_slabs_(n_slabs) {}
     hb_status init();
     void start();
     void stop();
@@ -106,14 +109,16 @@ public:
         for (int t = 0; t < n; t++) idle_gen_[t].store(kBusy);
         n_search_ = n;
     }
+    // The notification is sent under the mutex: the batch thread either
+    // already waits (and wakes) or has yet to test all_idle() (and sees it).
     void mark_idle(int t, int64_t g) {
         idle_gen_[t].store(g);
-        if (idle_flush_ && all_idle()) cv_.notify_all();
+        if (idle_flush_ && all_idle()) wake();
     }
     void mark_busy(int t) { idle_gen_[t].store(kBusy); }
     void thread_done(int t) {
         idle_gen_[t].store(kDone);
-        if (idle_flush_ && all_idle()) cv_.notify_all();
+        if (idle_flush_ && all_idle()) wake();
     }
     hb_status eval_now(const std::vector<uint8_t>& packed, int64_t n, std::vector<int32_t>* h);  // synchronous
     std::atomic<int64_t> evals{0}, batches{0};
@@ -122,12 +127,19 @@ public:
     std::string error_text;
 
 private:
+    void wake() {
+        std::lock_guard<std::mutex> lk(mu_);
+        cv_.notify_all();
+    }
     void loop();
     hb_status process(Slab* s, int n);
+    hb_status gpu_eval(const uint8_t* packed, int n, int32_t* h_out);
+    hb_status capture(int bi);
     Shared* sh_;
     int cap_;
     double timeout_;
     bool idle_flush_;
+    bool use_graphs_;
     int n_slabs_;
     std::vector<std::unique_ptr<Slab>> slabs_;
     std::vector<Slab*> free_;
@@ -148,14 +160,23 @@ private:
         return any;
     }
     static constexpr int64_t kBusy = -1, kDone = -2;
+    static constexpr int kSpin = 64;  // polling rounds (16 yields each) before sleeping
     bool stop_ = false;
     bool draining_ = false;
     std::atomic<int64_t> gen_{0};
     std::unique_ptr<std::atomic<int64_t>[]> idle_gen_;
     int idle_cap_ = 0, n_search_ = 0;
-    uint8_t* d_packed_ = nullptr;
+    // GPU side: [count | pad | packed states] staged in pinned memory and
+    // copied as one block; h comes back into pinned memory.
+    static constexpr int kHdr = 256;
+    uint8_t* stage_ = nullptr;    // pinned, kHdr + cap * pb
+    int32_t* h_stage_ = nullptr;  // pinned, cap
+    uint8_t* d_stage_ = nullptr;  // device, kHdr + cap * pb
     int32_t* d_h_ = nullptr;
     hipStream_t stream_ = nullptr;
+    std::vector<int> buckets_;              // ascending batch capacities, the last is cap
+    std::vector<hipGraphExec_t> execs_;     // per bucket, null until captured
+    bool graphs_ok_ = true;
 };
 
 struct Shared {
@@ -197,8 +218,15 @@ hb_status Batcher::init() {
     if (sh_->uses_gpu) {
         HB_HIP(hipSetDevice(sh_->model->device));
         HB_HIP(hipStreamCreate(&stream_));
-        HB_HIP(hipMalloc((void**)&d_packed_, (size_t)cap_ * pb));
+        HB_HIP(hipHostMalloc((void**)&stage_, kHdr + (size_t)cap_ * pb, hipHostMallocDefault));
+        HB_HIP(hipHostMalloc((void**)&h_stage_, (size_t)cap_ * 4, hipHostMallocDefault));
+        HB_HIP(hipMalloc((void**)&d_stage_, kHdr + (size_t)cap_ * pb));
         HB_HIP(hipMalloc((void**)&d_h_, (size_t)cap_ * 4));
+        hb_status st = model_prepare(sh_->model, stream_);  // workspace exists before any capture
+        if (st != HB_OK) return st;
+        for (int b = 32; b < cap_; b *= 2) buckets_.push_back(b);
+        buckets_.push_back(cap_);
+        execs_.assign(buckets_.size(), nullptr);
     }
     return HB_OK;
 }
@@ -216,7 +244,11 @@ Batcher::~Batcher() {
     }
     if (sh_->uses_gpu) {
         if (stream_) (void)hipStreamSynchronize(stream_);
-        (void)hipFree(d_packed_);
+        for (hipGraphExec_t e : execs_)
+            if (e) (void)hipGraphExecDestroy(e);
+        (void)hipHostFree(stage_);
+        (void)hipHostFree(h_stage_);
+        (void)hipFree(d_stage_);
         (void)hipFree(d_h_);
         if (stream_) (void)hipStreamDestroy(stream_);
     }
@@ -259,16 +291,70 @@ void Batcher::drain() {
     draining_ = false;
 }
 
+// Captures copy-in, forward pass and copy-out for batches of up to
+// buckets_[bi] states; the state count is read on the device.
+hb_status Batcher::capture(int bi) {
+    const int B = buckets_[bi];
+    const int pb = sh_->D->packed_bytes;
+    hipGraph_t g = nullptr;
+    HB_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)B * pb, hipMemcpyHostToDevice, stream_);
+    hb_status st = e == hipSuccess ? model_eval(sh_->model, d_stage_ + kHdr, 0, reinterpret_cast<const int32_t*>(d_stage_),
+                                                B, d_h_, nullptr, stream_, nullptr)
+                                   : fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
+    if (st == HB_OK) {
+        e = hipMemcpyAsync(h_stage_, d_h_, (size_t)B * 4, hipMemcpyDeviceToHost, stream_);
+        if (e != hipSuccess) st = fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
+    }
+    const hipError_t ee = hipStreamEndCapture(stream_, &g);
+    if (st == HB_OK && ee != hipSuccess) st = fail(HB_E_DEVICE, "end capture: %s", hipGetErrorString(ee));
+    if (st == HB_OK) {
+        e = hipGraphInstantiate(&execs_[bi], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            execs_[bi] = nullptr;
+            st = fail(HB_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
+// One batch on the GPU: a graph launch when graphs are on, else the same
+// copy / forward / copy sequence issued directly.
+hb_status Batcher::gpu_eval(const uint8_t* packed, int n, int32_t* h_out) {
+    const int pb = sh_->D->packed_bytes;
+    const double t0 = now_s();
+    std::memcpy(stage_ + kHdr, packed, (size_t)n * pb);
+    *reinterpret_cast<int32_t*>(stage_) = n;
+    bool launched = false;
+    if (use_graphs_ && graphs_ok_ && !sh_->model->profiling) {
+        const int bi = (int)(std::lower_bound(buckets_.begin(), buckets_.end(), n) - buckets_.begin());
+        if (!execs_[bi] && capture(bi) != HB_OK) {
+            graphs_ok_ = false;  // keep searching with direct launches
+            (void)hipGetLastError();
+        }
+        if (execs_[bi]) {
+            HB_HIP(hipGraphLaunch(execs_[bi], stream_));
+            launched = true;
+        }
+    }
+    if (!launched) {
+        HB_HIP(hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)n * pb, hipMemcpyHostToDevice, stream_));
+        hb_status st = model_eval(sh_->model, d_stage_ + kHdr, n, nullptr, 0, d_h_, nullptr, stream_, nullptr);
+        if (st != HB_OK) return st;
+        HB_HIP(hipMemcpyAsync(h_stage_, d_h_, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
+    }
+    HB_HIP(hipStreamSynchronize(stream_));
+    std::memcpy(h_out, h_stage_, (size_t)n * 4);
+    gpu_busy += now_s() - t0;
+    return HB_OK;
+}
+
 hb_status Batcher::process(Slab* s, int n) {
     const int pb = sh_->D->packed_bytes;
     if (sh_->uses_gpu) {
-        const double t0 = now_s();
-        HB_HIP(hipMemcpyAsync(d_packed_, s->packed, (size_t)n * pb, hipMemcpyHostToDevice, stream_));
-        hb_status st = model_eval(sh_->model, d_packed_, n, nullptr, 0, d_h_, nullptr, stream_, nullptr);
+        hb_status st = gpu_eval(s->packed, n, s->h);
         if (st != HB_OK) return st;
-        HB_HIP(hipMemcpyAsync(s->h, d_h_, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
-        HB_HIP(hipStreamSynchronize(stream_));
-        gpu_busy += now_s() - t0;
     } else {
         uint8_t st[kMaxStateBytes];
         for (int i = 0; i < n; i++) {
@@ -294,13 +380,24 @@ void Batcher::loop() {
     for (;;) {
         Slab* s = nullptr;
         int n = 0;
+        int spin = 0;
         while (!stop_) {
             if (cur_ && cur_->reserved > 0) {
                 const bool full = cur_->reserved == cap_;
-                const bool timed = now_s() - cur_->t_first >= timeout_;
+                const double left = cur_->t_first + timeout_ - now_s();
                 const bool idle = idle_flush_ && all_idle();
-                if (full || timed || idle || draining_) break;
-                cv_.wait_for(lk, std::chrono::microseconds(100));
+                if (full || left <= 0 || idle || draining_) break;
+                // Poll briefly first (a sleeping batch thread adds a wake-up
+                // to every round trip), then sleep until notified by reserve()
+                // (full slab), mark_idle() or thread_done(), or the timeout.
+                if (idle_flush_ && spin < kSpin) {
+                    lk.unlock();
+                    for (int i = 0; i < 16 && !all_idle(); i++) std::this_thread::yield();
+                    lk.lock();
+                    spin++;
+                    continue;
+                }
+                cv_.wait_for(lk, std::chrono::microseconds(std::max<int64_t>(1, std::min<int64_t>(1000, (int64_t)(left * 1e6)))));
             } else {
                 cv_.wait_for(lk, std::chrono::microseconds(200));
             }
@@ -344,11 +441,8 @@ hb_status Batcher::eval_now(const std::vector<uint8_t>& packed, int64_t n, std::
     for (int64_t off = 0; off < n; off += cap_) {
         const int c = (int)std::min<int64_t>(cap_, n - off);
         if (sh_->uses_gpu) {
-            HB_HIP(hipMemcpyAsync(d_packed_, packed.data() + off * pb, (size_t)c * pb, hipMemcpyHostToDevice, stream_));
-            hb_status st = model_eval(sh_->model, d_packed_, c, nullptr, 0, d_h_, nullptr, stream_, nullptr);
+            hb_status st = gpu_eval(packed.data() + off * pb, c, h->data() + off);
             if (st != HB_OK) return st;
-            HB_HIP(hipMemcpyAsync(h->data() + off, d_h_, (size_t)c * 4, hipMemcpyDeviceToHost, stream_));
-            HB_HIP(hipStreamSynchronize(stream_));
         } else {
             uint8_t st[kMaxStateBytes];
             for (int i = 0; i < c; i++) {
@@ -381,7 +475,7 @@ struct Solver;
 struct IterOut {
     int64_t expanded = 0, generated = 0;
     int32_t next = INT32_MAX;
-    bool found = false, exceeded = false, aborted = false;
+    bool found = false, exceeded = false, aborted = false, timed_out = false;
     std::vector<int8_t> path;
 };
 
@@ -405,6 +499,8 @@ struct Solver {
     std::atomic<int64_t> expanded_shared{0};
     std::atomic<bool> exceeded_flag{false};
     std::atomic<bool> depth_error{false};
+    std::atomic<bool> timed_out{false};
+    double deadline = 0;  // wall-clock stop (now_s() scale), 0 = none
     int64_t limit = -1;
     bool stop_at_goal = true;
     int32_t bound = 0;
@@ -433,12 +529,15 @@ hb_status Solver::build_tree(const uint8_t* start) {
     tree.clear();
     tree.push_back(root);
     int level_begin = 0, level_end = 1;
-    const int want = P->d_init >= 0 ? -1 : std::max(1, 2 * threads * std::max(1, P->work_num));
+    // Automatic depth: the early iterations of IDA* reach only a small part of
+    // the initial tree, so the tree is grown until it holds many more work
+    // units than there are subtree slots (at most about 3M nodes).
+    const int want = P->d_init >= 0 ? -1 : (int)std::min<int64_t>(1 << 20, 1024LL * threads * std::max(1, P->work_num));
     int depth = 0;
     const int max_depth = P->d_init >= 0 ? P->d_init : 40;
     while (depth < max_depth) {
         if (want > 0 && level_end - level_begin >= want) break;
-        if (tree.size() > 2000000) break;
+        if ((int64_t)tree.size() + (int64_t)(level_end - level_begin) * D.n_actions > 3000000) break;
         for (int i = level_begin; i < level_end; i++) {
             int nc = 0;
             if (is_goal(D, tree[i].s)) { tree[i].n_children = 0; continue; }  // goals are never expanded
@@ -580,6 +679,11 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
                     return 2;
                 }
             }
+            if (deadline > 0 && (expanded & 255) == 0 && now_s() > deadline) {
+                timed_out.store(true);
+                stop.store(true);
+                return 2;
+            }
             if (top[w] + D.n_actions > stack_cap) {  // deeper than kMaxDepth
                 depth_error.store(true);
                 stop.store(true);
@@ -684,6 +788,7 @@ IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
     sol_path.clear();
     exceeded_flag.store(false);
     depth_error.store(false);
+    timed_out.store(false);
     // Accounting on the initial tree.  A node is generated in this iteration
     // iff its parent is generated, is not the goal and has f <= T (the tree is
     // in breadth-first order, so parents precede children).
@@ -735,6 +840,7 @@ IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
     peak_nodes = std::max(peak_nodes, peak);
     if (limit >= 0 && expanded_shared.load() > limit) exceeded_flag.store(true);
     out.exceeded = exceeded_flag.load();
+    out.timed_out = timed_out.load();
     if (depth_error.load()) out.aborted = true;
     if (batcher && batcher->error != HB_OK) out.aborted = true;
     out.found = found_flag.load();
@@ -770,6 +876,7 @@ void cbdfs_params_default(cbdfs_params* p) {
     p->complete_final_iter = 0;
     p->start_bound = -1;
     p->max_iters = 1000;
+    p->use_graphs = 1;
 }
 
 void cbdfs_result_free(cbdfs_result* r) {
@@ -819,10 +926,12 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     S->P = &P;
     S->threads = threads;
     S->t_start = now_s();
+    S->deadline = P.time_limit_s > 0 ? S->t_start + P.time_limit_s : 0;
     if (S->sh.uses_batches) {
         int cap = P.batch_size;
         if (nn) cap = std::min(cap, h->model->opts.max_batch);
-        S->batcher = std::make_unique<Batcher>(&S->sh, cap, P.n_slabs, P.timeout_us * 1e-6, P.flush_when_idle != 0);
+        S->batcher = std::make_unique<Batcher>(&S->sh, cap, P.n_slabs, P.timeout_us * 1e-6, P.flush_when_idle != 0,
+                                               P.use_graphs != 0);
         hb_status st = S->batcher->init();
         if (st != HB_OK) return st;
     }
@@ -856,15 +965,15 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
             const bool stop_goal = !P.complete_final_iter;
             IterOut o = S->run(bound, lim, stop_goal);
             if (o.aborted) { result = HB_E_DEVICE; break; }
-            const bool complete = !o.exceeded && !(o.found && stop_goal);
+            const bool complete = !o.exceeded && !o.timed_out && !(o.found && stop_goal);
             push_iter(bound, lim, o, complete);
-            if (o.found) {
+            if (o.found) {  // any solution at bound T costs T, the optimum (no smaller bound had one)
                 cost = (int32_t)o.path.size();
                 path = o.path;
                 result = HB_OK;
                 break;
             }
-            if (o.exceeded || over_nodes() || over_time()) { result = HB_E_BUDGET; break; }
+            if (o.timed_out || o.exceeded || over_nodes() || over_time()) { result = HB_E_BUDGET; break; }
             if (o.next == INT32_MAX) { result = HB_E_NOSOLUTION; break; }
             bound = o.next;
         }
@@ -885,6 +994,11 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
             if (budget_cut) lim = rem;
             IterOut o = S->run(probe, lim, false);
             if (o.aborted) { result = HB_E_DEVICE; break; }
+            if (o.timed_out) {
+                push_iter(probe, lim, o, false);
+                result = HB_E_BUDGET;
+                break;
+            }
             push_iter(probe, lim, o, !o.exceeded);
             if (o.exceeded && budget_cut) { result = HB_E_BUDGET; break; }
             if (!o.exceeded && o.found) {

@@ -166,17 +166,25 @@ def test_batch_sizes_and_position_independence(net_files, n):
     np.testing.assert_array_equal(h, h_all[1000 - n:])
 
 
-def test_tile_shapes_give_identical_results(net_files):
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
+def test_tile_shapes_give_identical_results(net_files, prec):
+    """Every tile shape, the one-wave small-batch kernel included, runs the same
+    MFMA sequence per output: results are bitwise equal, so a state's h does not
+    depend on the batch size that selects the kernel."""
     path = net_files["stp4_res"]
     st = synth.stp_walks(4, synth.throughput_seeds(700), lengths=200)
     packed = hb.hb_encode(1, st)
+    calib = _dev(hb.hb_encode(1, synth.stp_walks(4, synth.throughput_seeds(1024, 4242), lengths=200)))
     outs = []
-    for tile in (1, 2, 3):
-        m = hb.Model(path, prec=hb.HB_BF16)
+    for tile in range(1, 6):
+        m = hb.Model(path, prec=prec)
+        if prec == hb.HB_FP8_E4M3:
+            m.calibrate(calib)
         m.set_tile(tile)
-        outs.append(_eval(m, packed, 1)[1])
-    np.testing.assert_array_equal(outs[0], outs[1])
-    np.testing.assert_array_equal(outs[0], outs[2])
+        outs.append(_eval(m, packed, 1))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(outs[0][1], o[1])
+        np.testing.assert_array_equal(outs[0][0], o[0])
 
 
 def test_chunking_beyond_max_batch(net_files):
