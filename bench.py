@@ -35,6 +35,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TILE_KERNELS = {0: "gemm_kernel<0, 0, 128, 128>", 1: "gemm_kernel<0, 0, 128, 256>", 2: "gemm_kernel<0, 0, 64, 128>",
+                3: "gemm_kernel<0, 0, 256, 128>", 4: "gemm_small_kernel<0, 0>"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    when the summary covers another kernel or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_f32_stp4res_b8000_hbm_bytes.md")
+    try:
+        fields = dict(l.strip().split(": ", 1) for l in open(path) if l.startswith("    ") and ": " in l)
+        src = os.path.join(ROOT, "paper_2507_11916_amd", "csrc", "kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if fields.get("traffic_kernel") != kernel or fields.get("kernels_hip_sha256_16") != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,7 +64,11 @@ def main():
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--profile-only", action="store_true", help="only the FP32 timed loop (for profilers)")
+    ap.add_argument("--profile-only", action="store_true", help="only one precision's timed loop (for profilers)")
+    ap.add_argument("--prec", default="f32", choices=["f32", "bf16", "fp8"], help="precision of --profile-only")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="with --profile-only: also copy a buffer of this many MiB five times (the known-size "
+                         "copy kernel that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported"}))
@@ -102,7 +126,8 @@ def main():
     results = {}
     calib = synth.stp_walks(4, synth.throughput_seeds(4096, 4242), lengths=200)
     d_calib = torch.from_numpy(hb.hb_encode(hb.HB_STP4, calib)).cuda()
-    precs = [("f32", hb.HB_FP32)] if args.profile_only else [("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)]
+    all_precs = [("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)]
+    precs = [p for p in all_precs if p[0] == args.prec] if args.profile_only else all_precs
     models = {}
     for name, prec in precs:
         m = hb.Model(wpath, prec=prec, combine_md=True, max_batch=max(B, 16384))
@@ -130,9 +155,15 @@ def main():
         models[name] = m
 
     if args.profile_only:
-        r = results["f32"]
+        if args.copy_mib > 0:
+            src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+        r = results[args.prec]
         print(json.dumps({"metric": "heuristic evals/s", "value": r["evals_per_s"], "unit": "evals/s",
-                          "ms_per_step": r["ms_per_step"], "profile_only": True}))
+                          "ms_per_step": r["ms_per_step"], "prec": args.prec, "profile_only": True}))
         return
 
     flops_eval = models["f32"].flops_per_eval
@@ -164,20 +195,30 @@ def main():
         results[name]["max_abs_dy_fp64"] = float(np.abs(results[name]["_y"][sample] - y64).max())
 
     # search nodes/s: Batch IDA* on a 15-puzzle start (200-move walk), fixed-tree
-    # mode (network evaluated on every generated state, Manhattan pruning), FP32
+    # mode (network evaluated on every generated state, Manhattan pruning), at
+    # each precision; a budget of 1M expansions each
     search = None
     if not args.no_search:
         start = synth.stp4_instances(1)[0]
         threads = min(32, max(4, len(os.sched_getaffinity(0))))
-        p = hb.default_params(batch_size=8000, work_num=8, node_limit=3_000_000, time_limit_s=20.0)
-        r = hb.cbdfs_solve(hb.HB_STP4, start, model=models["f32"], combine=hb.HB_H_FIXED_TREE,
-                           classic=hb.HB_CLASSIC_MD, threads=threads, params=p)
-        search = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
-                  "expanded": r["expanded"], "wall_s": r["wall_s"], "evals": r["evals"], "batches": r["batches"],
-                  "mean_batch": r["mean_batch"], "gpu_busy_s": r["gpu_busy_s"], "threads": threads,
-                  "host_cores": len(os.sched_getaffinity(0)), "status": r["status"],
-                  "iterations": len(r["iters"])}
-        log(f"[bench] search: {search['nodes_per_s']:.3e} nodes/s mean batch {search['mean_batch']:.0f}")
+        search = {"workload": "15-puzzle start (200-move walk), fixed-tree Batch IDA*, Manhattan pruning, "
+                              "work_num 8, 1M expansions", "threads": threads,
+                  "host_cores": len(os.sched_getaffinity(0))}
+        for name in ("f32", "bf16", "fp8"):
+            p = hb.default_params(batch_size=8000, work_num=8, node_limit=1_000_000, time_limit_s=20.0)
+            r = hb.cbdfs_solve(hb.HB_STP4, start, model=models[name], combine=hb.HB_H_FIXED_TREE,
+                               classic=hb.HB_CLASSIC_MD, threads=threads, params=p, raise_on_error=False)
+            search[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
+                            "expanded": r["expanded"], "wall_s": r["wall_s"], "evals": r["evals"],
+                            "batches": r["batches"], "mean_batch": r["mean_batch"],
+                            "gpu_us_per_batch": r["gpu_busy_s"] / max(1, r["batches"]) * 1e6,
+                            "status": r["status"], "iterations": len(r["iters"]),
+                            "per_iteration": [(i["bound"], i["expanded"], i["generated"]) for i in r["iters"]]}
+            log(f"[bench] search {name}: {search[name]['nodes_per_s']:.3e} nodes/s, mean batch "
+                f"{r['mean_batch']:.0f}, {search[name]['gpu_us_per_batch']:.0f} us GPU per batch")
+        # node counts do not depend on the precision in fixed-tree mode
+        search["counts_equal_across_precisions"] = (
+            search["f32"]["per_iteration"][:-1] == search["bf16"]["per_iteration"][:-1] == search["fp8"]["per_iteration"][:-1])
 
     # training step of the learned heuristic: same network shape, BF16 operands,
     # FP32 master weights and Adam, batch 8192 (labels: walk lengths)
@@ -228,6 +269,8 @@ def main():
 
     f32 = results["f32"]
     ach = f32["gemm_tflops"]
+    f32_kernel = TILE_KERNELS.get(min(f32["tile_us"], key=lambda t: t[1])[0])
+    traffic = measured_traffic(f32_kernel)
     line = {
         "metric": "heuristic evals/s + search nodes/s per GPU (FP32 vs BF16/FP8) at matched h",
         "value": f32["evals_per_s"],
@@ -244,8 +287,9 @@ def main():
         "config": {"workload": "4x4 sliding tile, residual MLP 256-1000-1000-2x(1000,1000)-1, batch 8000, FP32",
                    "batch": B, "flops_per_eval": flops_eval},
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": ach / PEAK_TFLOPS["f32"], "traffic": None,
-                     "kernel": "gemm_kernel (dense/residual layer, M=batch, K=N=1000 padded to 1024)",
+                     "frac": ach / PEAK_TFLOPS["f32"], "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "kernel": f"{f32_kernel} (dense/residual layer, M=batch, K=N=1000 padded to 1024)",
                      "avg_launch_us": f32["gemm_avg_us"], "flops_per_launch": f32["gemm_flops_per_launch"]},
         "cpu_baseline": cpu,
         "precisions": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},

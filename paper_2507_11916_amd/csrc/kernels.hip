@@ -30,10 +30,10 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 
 // Round to nearest even (NaN kept quiet).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? quiet : rounded);
 }
 
 // OCP e4m3, round to nearest even, saturating at +-448.  The hardware
@@ -174,12 +174,87 @@ __device__ __forceinline__ int swz(int row, int chunk) { return row * 128 + ((ch
 // OUTT is the type of C, R and Mk (0 f32, 1 bf16, 2 fp8): equal to PREC for the
 // forward and input-gradient products, float32 for weight gradients.
 template <int OUTT>
-__device__ __forceinline__ float load_out_t(const uint8_t* p, size_t o, float fp8_scale) {
+__device__ __forceinline__ float load_out_t(const uint8_t* p, int o, float fp8_scale) {
     if (OUTT == 0) return reinterpret_cast<const float*>(p)[o];
     if (OUTT == 1) return bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[o]);
     return fp8_to_f32(p[o]) * fp8_scale;
 }
 
+// Fused epilogue of one output element, shared by both GEMM kernels so that
+// they round identically: column scale and bias, residual, ReLU, mask, cast.
+// o: element offset into C, R and Mk (those buffers hold fewer than 2^31
+// elements).
+template <int OUTT>
+__device__ __forceinline__ void epi_store(const GemmArgs& g, float accv, float sn, float bn, int o) {
+    float v = accv * sn + bn;
+    if (g.R) v += load_out_t<OUTT>(g.R, o, g.r_scale);
+    if (g.relu) v = fmaxf(v, 0.f);
+    if (g.Mk) v = load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f ? v : 0.f;
+    if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
+    else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
+    else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+}
+
+// MFMAs of one 128-byte K stage held in LDS (a_s: BM rows, b_s: BN rows, both
+// swizzled) into the wave's (BM/2) x (BN/2) accumulator tiles.
+template <int PREC, int BM, int BN>
+__device__ __forceinline__ void mma_stage(const uint8_t* a_s, const uint8_t* b_s, floatx16 (&acc)[BM / 64][BN / 64],
+                                          int wm, int wn, int lane) {
+    constexpr int TI = BM / 64, TJ = BN / 64;
+    const int half = lane >> 5, r32 = lane & 31;
+    if (PREC == 2) {
+        _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
+            intx8 af[TI], bfr[TJ];
+            _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                const int row = wm * (BM / 2) + i * 32 + r32;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
+                af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+            _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+                const int row = wn * (BN / 2) + j * 32 + r32;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
+                bfr[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[i], bfr[j], acc[i][j], 0, 0, 0,
+                                                                               127, 0, 127);
+        }
+    } else {
+        _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
+            u32x4 af[TI], bfr[TJ];
+            _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                const int row = wm * (BM / 2) + i * 32 + r32;
+                af[i] = *reinterpret_cast<const u32x4*>(a_s + swz(row, 2 * kg + half));
+            }
+            _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+                const int row = wn * (BN / 2) + j * 32 + r32;
+                bfr[j] = *reinterpret_cast<const u32x4*>(b_s + swz(row, 2 * kg + half));
+            }
+            if (PREC == 1) {
+                _Pragma("unroll") for (int i = 0; i < TI; i++)
+                    _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j], 0, 0, 0);
+            } else {
+                _Pragma("unroll") for (int e = 0; e < 4; e++)
+                    _Pragma("unroll") for (int i = 0; i < TI; i++)
+                        _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+                            const uint32_t ai = e == 0 ? af[i].x : e == 1 ? af[i].y : e == 2 ? af[i].z : af[i].w;
+                            const uint32_t bj = e == 0 ? bfr[j].x : e == 1 ? bfr[j].y : e == 2 ? bfr[j].z : bfr[j].w;
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj),
+                                                                             acc[i][j], 0, 0, 0);
+                        }
+            }
+        }
+    }
+}
+
+// Stage k + 1 is fetched into registers while stage k is multiplied out of
+// LDS.  (A second register set fetching stage k + 2 measured slower: the extra
+// registers halve the waves per SIMD, which hide latency better.)
 template <int PREC, int OUTT, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int EB = Ty<PREC>::EB;
@@ -219,94 +294,46 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             _Pragma("unroll") for (int j = 0; j < TJ; j++)
                 _Pragma("unroll") for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
 
-        u32x4 ra[A_LD], rb[B_LD];
         // Global -> registers and registers -> LDS for one K stage (macros, so
-        // that ra/rb stay in registers).
-#define HB_GLOAD(kt_)                                                                                   \
+        // that the register sets stay in registers).
+#define HB_GLOAD(kt_, RA, RB)                                                                           \
         {                                                                                               \
             const int kbyte = (kt_) * 128;                                                              \
             _Pragma("unroll") for (int i = 0; i < A_LD; i++) {                                          \
                 const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
-                ra[i] = *reinterpret_cast<const u32x4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16); \
+                RA[i] = *reinterpret_cast<const u32x4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16); \
             }                                                                                           \
             _Pragma("unroll") for (int i = 0; i < B_LD; i++) {                                          \
                 const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
-                rb[i] = *reinterpret_cast<const u32x4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16); \
+                RB[i] = *reinterpret_cast<const u32x4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16); \
             }                                                                                           \
         }
-#define HB_SSTORE(buf_)                                                                                 \
+#define HB_SSTORE(buf_, RA, RB)                                                                         \
         {                                                                                               \
             _Pragma("unroll") for (int i = 0; i < A_LD; i++) {                                          \
                 const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
-                *reinterpret_cast<u32x4*>(SA(buf_) + swz(row, ch)) = ra[i];                            \
+                *reinterpret_cast<u32x4*>(SA(buf_) + swz(row, ch)) = RA[i];                            \
             }                                                                                           \
             _Pragma("unroll") for (int i = 0; i < B_LD; i++) {                                          \
                 const int id = i * 256 + tid, row = id >> 3, ch = id & 7;                               \
-                *reinterpret_cast<u32x4*>(SB(buf_) + swz(row, ch)) = rb[i];                            \
+                *reinterpret_cast<u32x4*>(SB(buf_) + swz(row, ch)) = RB[i];                            \
             }                                                                                           \
         }
 
-        HB_GLOAD(0);
+        u32x4 ra[A_LD], rb[B_LD];
+        HB_GLOAD(0, ra, rb);
         __syncthreads();  // previous tile's readers of buffer 0 are done
-        HB_SSTORE(0);
+        HB_SSTORE(0, ra, rb);
         __syncthreads();
         for (int kt = 0; kt < ktiles; kt++) {
             const int cur = kt & 1;
-            if (kt + 1 < ktiles) HB_GLOAD(kt + 1);
-            const uint8_t* a_s = SA(cur);
-            const uint8_t* b_s = SB(cur);
-            const int half = lane >> 5, r32 = lane & 31;
-            if (PREC == 2) {
-                _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
-                    intx8 af[TI], bfr[TJ];
-                    _Pragma("unroll") for (int i = 0; i < TI; i++) {
-                        const int row = wm * (BM / 2) + i * 32 + r32;
-                        const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
-                        const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
-                        af[i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-                    }
-                    _Pragma("unroll") for (int j = 0; j < TJ; j++) {
-                        const int row = wn * (BN / 2) + j * 32 + r32;
-                        const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
-                        const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
-                        bfr[j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-                    }
-                    _Pragma("unroll") for (int i = 0; i < TI; i++)
-                        _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[i], bfr[j], acc[i][j], 0, 0, 0,
-                                                                                       127, 0, 127);
-                }
-            } else {
-                _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
-                    u32x4 af[TI], bfr[TJ];
-                    _Pragma("unroll") for (int i = 0; i < TI; i++) {
-                        const int row = wm * (BM / 2) + i * 32 + r32;
-                        af[i] = *reinterpret_cast<const u32x4*>(a_s + swz(row, 2 * kg + half));
-                    }
-                    _Pragma("unroll") for (int j = 0; j < TJ; j++) {
-                        const int row = wn * (BN / 2) + j * 32 + r32;
-                        bfr[j] = *reinterpret_cast<const u32x4*>(b_s + swz(row, 2 * kg + half));
-                    }
-                    if (PREC == 1) {
-                        _Pragma("unroll") for (int i = 0; i < TI; i++)
-                            _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                    __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j], 0, 0, 0);
-                    } else {
-                        _Pragma("unroll") for (int e = 0; e < 4; e++)
-                            _Pragma("unroll") for (int i = 0; i < TI; i++)
-                                _Pragma("unroll") for (int j = 0; j < TJ; j++) {
-                                    const uint32_t ai = e == 0 ? af[i].x : e == 1 ? af[i].y : e == 2 ? af[i].z : af[i].w;
-                                    const uint32_t bj = e == 0 ? bfr[j].x : e == 1 ? bfr[j].y : e == 2 ? bfr[j].z : bfr[j].w;
-                                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj),
-                                                                                     acc[i][j], 0, 0, 0);
-                                }
-                    }
-                }
-            }
-            if (kt + 1 < ktiles) HB_SSTORE(cur ^ 1);
+            if (kt + 1 < ktiles) HB_GLOAD(kt + 1, ra, rb);
+            mma_stage<PREC, BM, BN>(SA(cur), SB(cur), acc, wm, wn, lane);
+            if (kt + 1 < ktiles) HB_SSTORE(cur ^ 1, ra, rb);
             __syncthreads();
         }
+#undef HB_GLOAD
+#undef HB_SSTORE
 
         // Epilogue.  Lane holds, for MFMA tile (i, j), column j*32 + lane%32 and
         // rows i*32 + 8a + 4*(lane/32) + b for a, b in 0..3 (value 4a + b).
@@ -316,29 +343,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
             _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                const int o0 = (m0 + wm * (BM / 2) + i * 32 + 4 * half) * g.ldc + n;
                 _Pragma("unroll") for (int a = 0; a < 4; a++)
-                    _Pragma("unroll") for (int b = 0; b < 4; b++) {
-                        const int m = m0 + wm * (BM / 2) + i * 32 + 8 * a + 4 * half + b;
-                        float v = acc[i][j][4 * a + b] * sn + bn;
-                        const size_t o = (size_t)m * g.ldc + n;
-                        if (g.R) {
-                            v += load_out_t<OUTT>(g.R, o, g.r_scale);
-                        }
-                        if (g.relu) v = fmaxf(v, 0.f);
-                        if (g.Mk && !(load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f)) v = 0.f;
-                        if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
-                        else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
-                        else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
-                    }
+                    _Pragma("unroll") for (int b = 0; b < 4; b++)
+                        epi_store<OUTT>(g, acc[i][j][4 * a + b], sn, bn, o0 + (8 * a + b) * g.ldc);
             }
         }
     }
 }
 
+#undef SA
+#undef SB
+
 // ------------------------------------------------------------ small-batch GEMM
 // One wave per 32 x 32 output tile, operands read from global memory straight
-// into registers (no LDS, no barriers), the next K stage prefetched while the
-// current one is multiplied.  At a few hundred rows or fewer the tiles of
+// into registers (no LDS, no barriers), several K stages prefetched ahead of
+// the one being multiplied.  At a few hundred rows or fewer the tiles of
 // gemm_kernel would leave most compute units idle; here every 32 x 32 tile is
 // a block of its own.  Every output element goes through exactly the MFMA
 // sequence of gemm_kernel (the same 16-byte chunk of each 128-byte K stage in
@@ -364,61 +384,62 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
     _Pragma("unroll") for (int i = 0; i < 4; i++)
         off[i] = 16 * (PREC == 2 ? 4 * (i >> 1) + 2 * half + (i & 1) : 2 * i + half);
 
+    // A ring of DEPTH K stages in registers: at a few dozen waves on the
+    // chip, the loads in flight per wave decide how well memory latency is hidden.
+    constexpr int DEPTH = 4;
     floatx16 acc;
     _Pragma("unroll") for (int e = 0; e < 16; e++) acc[e] = 0.f;
-    u32x4 a[4], b[4];
-    _Pragma("unroll") for (int i = 0; i < 4; i++) {
-        a[i] = *reinterpret_cast<const u32x4*>(Ar + off[i]);
-        b[i] = *reinterpret_cast<const u32x4*>(Br + off[i]);
-    }
-    for (int kt = 0; kt < ktiles; kt++) {
-        u32x4 na[4], nb[4];
-        if (kt + 1 < ktiles) {
-            const int kbyte = (kt + 1) * 128;
+    u32x4 a[DEPTH][4], b[DEPTH][4];
+    _Pragma("unroll") for (int j = 0; j < DEPTH; j++) {
+        if (j < ktiles) {
             _Pragma("unroll") for (int i = 0; i < 4; i++) {
-                na[i] = *reinterpret_cast<const u32x4*>(Ar + kbyte + off[i]);
-                nb[i] = *reinterpret_cast<const u32x4*>(Br + kbyte + off[i]);
+                a[j][i] = *reinterpret_cast<const u32x4*>(Ar + j * 128 + off[i]);
+                b[j][i] = *reinterpret_cast<const u32x4*>(Br + j * 128 + off[i]);
             }
         }
-        if (PREC == 2) {
-            _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
-                const u32x4 al = a[2 * kg], ah = a[2 * kg + 1], bl = b[2 * kg], bh = b[2 * kg + 1];
-                const intx8 af = intx8{(int)al.x, (int)al.y, (int)al.z, (int)al.w, (int)ah.x, (int)ah.y, (int)ah.z, (int)ah.w};
-                const intx8 bf = intx8{(int)bl.x, (int)bl.y, (int)bl.z, (int)bl.w, (int)bh.x, (int)bh.y, (int)bh.z, (int)bh.w};
-                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf, acc, 0, 0, 0, 127, 0, 127);
-            }
-        } else if (PREC == 1) {
-            _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[kg]),
-                                                              __builtin_bit_cast(bf16x8, b[kg]), acc, 0, 0, 0);
-        } else {
-            _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
-                _Pragma("unroll") for (int e = 0; e < 4; e++) {
-                    const uint32_t ai = e == 0 ? a[kg].x : e == 1 ? a[kg].y : e == 2 ? a[kg].z : a[kg].w;
-                    const uint32_t bj = e == 0 ? b[kg].x : e == 1 ? b[kg].y : e == 2 ? b[kg].z : b[kg].w;
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj), acc, 0, 0, 0);
+    }
+    for (int k0 = 0; k0 < ktiles; k0 += DEPTH) {
+        _Pragma("unroll") for (int j = 0; j < DEPTH; j++) {
+            const int kt = k0 + j;
+            if (kt < ktiles) {
+                if (PREC == 2) {
+                    _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
+                        const u32x4 al = a[j][2 * kg], ah = a[j][2 * kg + 1], bl = b[j][2 * kg], bh = b[j][2 * kg + 1];
+                        const intx8 af = intx8{(int)al.x, (int)al.y, (int)al.z, (int)al.w, (int)ah.x, (int)ah.y, (int)ah.z, (int)ah.w};
+                        const intx8 bf = intx8{(int)bl.x, (int)bl.y, (int)bl.z, (int)bl.w, (int)bh.x, (int)bh.y, (int)bh.z, (int)bh.w};
+                        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf, acc, 0, 0, 0, 127, 0, 127);
+                    }
+                } else if (PREC == 1) {
+                    _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[j][kg]),
+                                                                      __builtin_bit_cast(bf16x8, b[j][kg]), acc, 0, 0, 0);
+                } else {
+                    _Pragma("unroll") for (int kg = 0; kg < 4; kg++)
+                        _Pragma("unroll") for (int e = 0; e < 4; e++) {
+                            const u32x4 av = a[j][kg], bv = b[j][kg];
+                            const uint32_t ai = e == 0 ? av.x : e == 1 ? av.y : e == 2 ? av.z : av.w;
+                            const uint32_t bj = e == 0 ? bv.x : e == 1 ? bv.y : e == 2 ? bv.z : bv.w;
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(ai), __uint_as_float(bj), acc, 0, 0, 0);
+                        }
                 }
-        }
-        if (kt + 1 < ktiles) {
-            _Pragma("unroll") for (int i = 0; i < 4; i++) { a[i] = na[i]; b[i] = nb[i]; }
+                if (kt + DEPTH < ktiles) {
+                    const int kbyte = (kt + DEPTH) * 128;
+                    _Pragma("unroll") for (int i = 0; i < 4; i++) {
+                        a[j][i] = *reinterpret_cast<const u32x4*>(Ar + kbyte + off[i]);
+                        b[j][i] = *reinterpret_cast<const u32x4*>(Br + kbyte + off[i]);
+                    }
+                }
+            }
         }
     }
     // Epilogue, as in gemm_kernel: column n0 + lane%32, rows 8a + 4*half + b.
     const int n = n0 + r32;
     const float bn = g.bias ? g.bias[n] : 0.f;
     const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+    const int o0 = (m0 + 4 * half) * g.ldc + n;
     _Pragma("unroll") for (int a4 = 0; a4 < 4; a4++)
-        _Pragma("unroll") for (int b4 = 0; b4 < 4; b4++) {
-            const int m = m0 + 8 * a4 + 4 * half + b4;
-            float v = acc[4 * a4 + b4] * sn + bn;
-            const size_t o = (size_t)m * g.ldc + n;
-            if (g.R) v += load_out_t<OUTT>(g.R, o, g.r_scale);
-            if (g.relu) v = fmaxf(v, 0.f);
-            if (g.Mk && !(load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f)) v = 0.f;
-            if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
-            else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
-            else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
-        }
+        _Pragma("unroll") for (int b4 = 0; b4 < 4; b4++)
+            epi_store<OUTT>(g, acc[4 * a4 + b4], sn, bn, o0 + (8 * a4 + b4) * g.ldc);
 }
 
 // ------------------------------------------------------------ head
