@@ -179,10 +179,13 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
                               int32_t* d_h_out, float* d_raw_out, void* stream);
 
 /* Select the GEMM tile shape used by later evaluations on this model:
- * 0 automatic (autotuned bucket, else a rule on the batch size), 1 128x128,
- * 2 128x256, 3 64x128, 4 256x128 (LDS-staged, 4 waves), 5 32x32 (one wave per
- * tile, operands straight from global memory: small batches).  All shapes give
- * bitwise equal results.  See hb_model_tune. */
+ * 0 automatic (autotuned bucket, else a rule on the batch size);
+ * 1 128x128, 2 128x256, 3 64x128, 4 256x128: LDS double buffer filled through
+ *   registers, 4 waves;
+ * 5 32x32: one wave per tile, operands straight from global memory (small batches);
+ * 6 256x128, 7 128x128, 8 128x256 (3-stage LDS ring), 9 64x128 (4-stage ring):
+ *   LDS ring filled by direct global-to-LDS loads, 4 waves.
+ * All shapes give bitwise equal results.  HB_E_INVAL outside 0..9.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
 /* Autotuner: times every tile shape on n seeded states and keeps the fastest
  * for batches of about that size.  Results (tile id, microseconds) are written

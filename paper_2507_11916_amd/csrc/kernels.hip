@@ -136,8 +136,11 @@ __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restri
 // transposed, Bt[N][K] (weights, K contiguous).  Block tile BM x BN, 4 waves in
 // a 2 x 2 grid, each wave (BM/2) x (BN/2) built from 32x32 MFMA tiles.  Each
 // K stage moves 128 bytes of every A and Bt row through LDS (double-buffered);
-// 16-byte chunks are XOR-swizzled by row so that both the global->LDS stores
-// and the MFMA operand reads are free of bank conflicts.
+// 16-byte chunks are XOR-swizzled with key (row / 2) mod 8: one 16-lane group of
+// a 128-bit LDS access spans 16 consecutive rows, two rows per 256-byte line of
+// banks, and the key gives the 8 rows of each parity 8 distinct chunk slots, so
+// both the global->LDS stores and the MFMA operand reads are conflict-free.
+// (Keyed on row mod 8, a third of the LDS cycles went to bank conflicts.)
 //   PREC 0: fp32, v_mfma_f32_32x32x2_f32 (a lane reads 4 K values, one per MFMA);
 //   PREC 1: bf16, v_mfma_f32_32x32x16_bf16 (8 K values per lane);
 //   PREC 2: fp8,  v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales
@@ -169,7 +172,7 @@ struct Ty {
     static constexpr int EB = PREC == 0 ? 4 : PREC == 1 ? 2 : 1;  // bytes per element
 };
 
-__device__ __forceinline__ int swz(int row, int chunk) { return row * 128 + ((chunk ^ (row & 7)) << 4); }
+__device__ __forceinline__ int swz(int row, int chunk) { return row * 128 + ((chunk ^ ((row >> 1) & 7)) << 4); }
 
 // OUTT is the type of C, R and Mk (0 f32, 1 bf16, 2 fp8): equal to PREC for the
 // forward and input-gradient products, float32 for weight gradients.
@@ -180,19 +183,47 @@ __device__ __forceinline__ float load_out_t(const uint8_t* p, int o, float fp8_s
     return fp8_to_f32(p[o]) * fp8_scale;
 }
 
-// Fused epilogue of one output element, shared by both GEMM kernels so that
+// Fused epilogue of one 32x32 MFMA tile held by a wave (lane: column n, rows
+// 8a + 4*(lane/32) + b for element 4a + b), shared by every GEMM kernel so that
 // they round identically: column scale and bias, residual, ReLU, mask, cast.
-// o: element offset into C, R and Mk (those buffers hold fewer than 2^31
-// elements).
+// o0: element offset of the lane's first element in C, R and Mk; element 4a + b
+// sits (8a + b) rows further.  Offsets are formed as unsigned 32-bit byte
+// offsets from the (uniform) base pointers, which the compiler turns into
+// scalar-base + 32-bit-offset accesses (the buffers are below 4 GiB).  The
+// residual and mask values are all loaded before any store: R may be C itself
+// (in-place residual), and reading first lets the 16 loads overlap instead of
+// each waiting behind the previous store.
 template <int OUTT>
-__device__ __forceinline__ void epi_store(const GemmArgs& g, float accv, float sn, float bn, int o) {
-    float v = accv * sn + bn;
-    if (g.R) v += load_out_t<OUTT>(g.R, o, g.r_scale);
-    if (g.relu) v = fmaxf(v, 0.f);
-    if (g.Mk) v = load_out_t<OUTT>(g.Mk, o, 1.f) > 0.f ? v : 0.f;
-    if (OUTT == 0) reinterpret_cast<float*>(g.C)[o] = v;
-    else if (OUTT == 1) reinterpret_cast<uint16_t*>(g.C)[o] = f32_to_bf16(v);
-    else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+__device__ __forceinline__ float load_at(const uint8_t* p, uint32_t byte_off, float fp8_scale) {
+    if (OUTT == 0) return *reinterpret_cast<const float*>(p + byte_off);
+    if (OUTT == 1) return bf16_to_f32(*reinterpret_cast<const uint16_t*>(p + byte_off));
+    return fp8_to_f32(p[byte_off]) * fp8_scale;
+}
+
+template <int OUTT>
+__device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc, float sn, float bn, int o0) {
+    constexpr uint32_t EO = OUTT == 0 ? 4 : OUTT == 1 ? 2 : 1;
+    const uint32_t b0 = (uint32_t)o0 * EO, row = (uint32_t)g.ldc * EO;
+    float rv[16], mk[16];
+    if (g.R) {
+        _Pragma("unroll") for (int e = 0; e < 16; e++)
+            rv[e] = load_at<OUTT>(g.R, b0 + (8 * (e >> 2) + (e & 3)) * row, g.r_scale);
+    }
+    if (g.Mk) {
+        _Pragma("unroll") for (int e = 0; e < 16; e++)
+            mk[e] = load_at<OUTT>(g.Mk, b0 + (8 * (e >> 2) + (e & 3)) * row, 1.f);
+    }
+    _Pragma("unroll") for (int e = 0; e < 16; e++) {
+        const uint32_t o = b0 + (8 * (e >> 2) + (e & 3)) * row;
+        float v = acc[e] * sn + bn;
+        if (g.R) v += rv[e];
+        if (g.relu) v = fmaxf(v, 0.f);
+        if (g.Mk) v = mk[e] > 0.f ? v : 0.f;
+        if (OUTT == 0) *reinterpret_cast<float*>(g.C + o) = v;
+        else if (OUTT == 1) *reinterpret_cast<uint16_t*>(g.C + o) = f32_to_bf16(v);
+        else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+    }
+    asm volatile("" ::: "memory");  // one tile's loads at a time: bounded register use
 }
 
 // MFMAs of one 128-byte K stage held in LDS (a_s: BM rows, b_s: BN rows, both
@@ -342,18 +373,121 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             const int n = n0 + wn * (BN / 2) + j * 32 + c32;
             const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
-            _Pragma("unroll") for (int i = 0; i < TI; i++) {
-                const int o0 = (m0 + wm * (BM / 2) + i * 32 + 4 * half) * g.ldc + n;
-                _Pragma("unroll") for (int a = 0; a < 4; a++)
-                    _Pragma("unroll") for (int b = 0; b < 4; b++)
-                        epi_store<OUTT>(g, acc[i][j][4 * a + b], sn, bn, o0 + (8 * a + b) * g.ldc);
-            }
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * (BM / 2) + i * 32 + 4 * half) * g.ldc + n);
         }
     }
 }
 
 #undef SA
 #undef SB
+
+// ------------------------------------------------------------ GEMM, LDS ring
+// Same tiles, MFMA sequence and epilogue as gemm_kernel (bitwise equal
+// results), but the operands go from global memory straight into LDS
+// (global_load_lds_dwordx4: each lane's 16 bytes land at the instruction's LDS
+// base + 16 * lane, no registers involved) through a ring of NS stages, so
+// NS - 1 stages are in flight while one is multiplied.  The swizzle is applied
+// on the global side: the lane that fills LDS slot s of row r fetches chunk
+// s ^ key(r).  Waiting: each wave issues LD load instructions per stage and
+// they complete in order, so at the top of stage k the wave waits until at
+// most (stages issued after k) * LD of its loads are outstanding; the barrier
+// that follows makes every wave's part of stage k visible and frees the slot
+// that stage k - 1 was read from, which the next issue refills.
+// s_waitcnt vmcnt(N) with the expcnt and lgkmcnt fields at their maxima (no
+// wait on them); vmcnt is split over bits 3:0 and 15:14.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <int PREC, int OUTT, int BM, int BN, int NS>
+__global__ __launch_bounds__(256) void gemm_ring_kernel(GemmArgs g) {
+    constexpr int EB = Ty<PREC>::EB;
+    constexpr int TI = BM / 64, TJ = BN / 64;
+    constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
+    constexpr int STAGE = A_BYTES + B_BYTES;
+    constexpr int LD_A = BM / 32, LD_B = BN / 32;  // 1 KiB (8-row) load instructions per wave per stage
+    constexpr int LD = LD_A + LD_B;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + BM - 1) / BM, g.m_tiles_cap);
+    const int n_tiles = g.N / BN;
+    const int total = m_tiles * n_tiles;
+    const int ktiles = g.K * EB / 128;
+
+    const int grid = gridDim.x;
+    const int grid8 = grid & ~7;
+    int first = blockIdx.x;
+    if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
+
+    const int lrow = lane >> 3;  // row of this lane within an 8-row load instruction
+
+    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+        const int tm = t / n_tiles, tn = t % n_tiles;
+        const int m0 = tm * BM, n0 = tn * BN;
+        const uint8_t* Ag = g.A + (size_t)m0 * g.lda * EB;
+        const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
+
+        floatx16 acc[TI][TJ];
+        _Pragma("unroll") for (int i = 0; i < TI; i++)
+            _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                _Pragma("unroll") for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
+
+        // Stage kt into ring slot sl: this wave's instructions q = wave + 4i.
+        auto issue = [&](int kt, int sl) {
+            uint8_t* base = smem + sl * STAGE;
+            const int kbyte = kt * 128;
+            _Pragma("unroll") for (int i = 0; i < LD; i++) {
+                const int q = wave + 4 * i;
+                const bool isA = q < BM / 8;
+                const int qq = isA ? q : q - BM / 8;
+                const int row = 8 * qq + lrow;
+                const int key = ((row >> 1) & 7);
+                const int ch = (lane & 7) ^ key;
+                const uint8_t* src = (isA ? Ag + (size_t)row * g.lda * EB : Bg + (size_t)row * g.ldb * EB) + kbyte + ch * 16;
+                uint8_t* dst = base + (isA ? 0 : A_BYTES) + qq * 1024;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+            }
+        };
+
+        __syncthreads();  // the previous tile's readers are done with every slot
+        _Pragma("unroll") for (int s0 = 0; s0 < NS - 1; s0++)
+            if (s0 < ktiles) issue(s0, s0);
+        for (int kt = 0; kt < ktiles; kt++) {
+            // stages issued so far: min(ktiles, kt + NS - 1); this wave may
+            // leave the ones after kt in flight
+            const int ahead = min(ktiles, kt + NS - 1) - (kt + 1);
+            static_assert(NS >= 2 && NS <= 4, "ring depth");
+            if (NS == 4 && ahead >= 2) wait_vmcnt<(NS == 4 ? 2 * LD : 0)>();
+            else if (ahead >= 1) wait_vmcnt<LD>();
+            else wait_vmcnt<0>();
+            // A bare s_barrier: __syncthreads() would also wait for every
+            // outstanding load (its release fence), draining the ring.  The
+            // empty asm statements keep the compiler from moving LDS accesses
+            // across the barrier.
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (kt + NS - 1 < ktiles) issue(kt + NS - 1, (kt + NS - 1) % NS);
+            const uint8_t* a_s = smem + (kt % NS) * STAGE;
+            mma_stage<PREC, BM, BN>(a_s, a_s + A_BYTES, acc, wm, wn, lane);
+        }
+
+        const int half = lane >> 5, c32 = lane & 31;
+        _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+            const int n = n0 + wn * (BN / 2) + j * 32 + c32;
+            const float bn = g.bias ? g.bias[n] : 0.f;
+            const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * (BM / 2) + i * 32 + 4 * half) * g.ldc + n);
+        }
+    }
+}
 
 // ------------------------------------------------------------ small-batch GEMM
 // One wave per 32 x 32 output tile, operands read from global memory straight
@@ -436,10 +570,7 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
     const int n = n0 + r32;
     const float bn = g.bias ? g.bias[n] : 0.f;
     const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
-    const int o0 = (m0 + 4 * half) * g.ldc + n;
-    _Pragma("unroll") for (int a4 = 0; a4 < 4; a4++)
-        _Pragma("unroll") for (int b4 = 0; b4 < 4; b4++)
-            epi_store<OUTT>(g, acc[4 * a4 + b4], sn, bn, o0 + (8 * a4 + b4) * g.ldc);
+    epi_tile<OUTT>(g, acc, sn, bn, (m0 + 4 * half) * g.ldc + n);
 }
 
 // ------------------------------------------------------------ head
@@ -609,10 +740,31 @@ static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
 }
 
-// Tile 4 is the small-batch kernel (one wave per 32 x 32 tile).
-int gemm_tile_count() { return 5; }
+template <int PREC, int OUTT, int BM, int BN, int NS>
+static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    const int m_tiles = (L.m_cap + BM - 1) / BM;
+    const int tiles = m_tiles * (L.N / BN);
+    g.m_tiles_cap = m_tiles;
+    int grid = tiles;
+    g.persistent = 0;
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.m_dev) g.persistent = 1;
+    const size_t lds = (size_t)NS * (BM + BN) * 128;
+    hipLaunchKernelGGL((gemm_ring_kernel<PREC, OUTT, BM, BN, NS>), dim3(grid), dim3(256), lds, s, g);
+}
+
+// Tile ids: 0-3 LDS double buffer fed through registers, 4 the small-batch
+// kernel (one wave per 32 x 32 tile), 5-8 the LDS ring fed by direct loads.
+int gemm_tile_count() { return 9; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[5][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32}};
+    static const int T[9][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+                                {256, 128}, {128, 128}, {128, 256}, {64, 128}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -625,6 +777,10 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 2: launch_gemm_t<PREC, OUTT, 64, 128>(L, s); return true;
         case 3: launch_gemm_t<PREC, OUTT, 256, 128>(L, s); return true;
         case 4: launch_gemm_small<PREC, OUTT>(L, s); return true;
+        case 5: launch_gemm_ring<PREC, OUTT, 256, 128, 3>(L, s); return true;
+        case 6: launch_gemm_ring<PREC, OUTT, 128, 128, 3>(L, s); return true;
+        case 7: launch_gemm_ring<PREC, OUTT, 128, 256, 3>(L, s); return true;
+        case 8: launch_gemm_ring<PREC, OUTT, 64, 128, 4>(L, s); return true;
     }
     return false;
 }
@@ -663,12 +819,22 @@ static hipError_t set_lds_attr() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (BM + BN) * 128);
 }
 
+template <int PREC, int OUTT, int BM, int BN, int NS>
+static hipError_t set_ring_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_ring_kernel<PREC, OUTT, BM, BN, NS>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, NS * (BM + BN) * 128);
+}
+
 template <int PREC, int OUTT>
 static hipError_t set_lds_attr_p() {
     hipError_t e = set_lds_attr<PREC, OUTT, 128, 128>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 128, 256>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 64, 128>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 128>();
+    if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 256, 128, 3>();
+    if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 128, 3>();
+    if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 256, 3>();
+    if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 64, 128, 4>();
     return e;
 }
 

@@ -168,15 +168,16 @@ def test_batch_sizes_and_position_independence(net_files, n):
 
 @pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16, hb.HB_FP8_E4M3])
 def test_tile_shapes_give_identical_results(net_files, prec):
-    """Every tile shape, the one-wave small-batch kernel included, runs the same
-    MFMA sequence per output: results are bitwise equal, so a state's h does not
-    depend on the batch size that selects the kernel."""
+    """Every tile shape (register-staged LDS tiles, the one-wave small-batch
+    kernel, the direct-load LDS ring) runs the same MFMA sequence per output:
+    results are bitwise equal, so a state's h does not depend on the batch size
+    or the tile that the autotuner picks."""
     path = net_files["stp4_res"]
     st = synth.stp_walks(4, synth.throughput_seeds(700), lengths=200)
     packed = hb.hb_encode(1, st)
     calib = _dev(hb.hb_encode(1, synth.stp_walks(4, synth.throughput_seeds(1024, 4242), lengths=200)))
     outs = []
-    for tile in range(1, 6):
+    for tile in range(1, 10):
         m = hb.Model(path, prec=prec)
         if prec == hb.HB_FP8_E4M3:
             m.calibrate(calib)
@@ -196,9 +197,13 @@ def test_chunking_beyond_max_batch(net_files):
     np.testing.assert_array_equal(a[1], b[1])
 
 
-def test_device_count_variant_matches(net_files):
+@pytest.mark.parametrize("tile", [0, 1, 5, 6, 9])
+def test_device_count_variant_matches(net_files, tile):
+    """The device-count entry point (grid sized for max_n, tiles strided on the
+    device) equals the host-count evaluation, for each kernel family."""
     path = net_files["rc_cls"]
     m = hb.Model(path, prec=hb.HB_BF16, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4096)
+    m.set_tile(tile)
     st = _cube_states(333)
     packed = hb.hb_encode(2, st)
     h0, z0 = _eval(m, packed, 21)
