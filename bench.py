@@ -35,8 +35,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TILE_KERNELS = {0: "gemm_kernel<0, 0, 128, 128>", 1: "gemm_kernel<0, 0, 128, 256>", 2: "gemm_kernel<0, 0, 64, 128>",
-                3: "gemm_kernel<0, 0, 256, 128>", 4: "gemm_small_kernel<0, 0>"}
+# FP32 kernel of each tile id (hb_model_set_tile numbering)
+TILE_KERNELS = {1: "gemm_kernel<0, 0, 128, 128>", 2: "gemm_kernel<0, 0, 128, 256>", 3: "gemm_kernel<0, 0, 64, 128>",
+                4: "gemm_kernel<0, 0, 256, 128>", 5: "gemm_small_kernel<0, 0>",
+                6: "gemm_ring_kernel<0, 0, 256, 128, 3>", 7: "gemm_ring_kernel<0, 0, 128, 128, 3>",
+                8: "gemm_ring_kernel<0, 0, 128, 256, 3>", 9: "gemm_ring_kernel<0, 0, 64, 128, 4>"}
 
 
 def measured_traffic(kernel):
@@ -133,10 +136,14 @@ def main():
         m = hb.Model(wpath, prec=prec, combine_md=True, max_batch=max(B, 16384))
         if prec == hb.HB_FP8_E4M3:
             m.calibrate(d_calib)
-        tune = m.tune(d_packed)
+        table, rec = m.autotune(d_packed)
+        tile = m.tile_for(B)
         ms = timed_loop(m, args.steps, args.warmup)
-        log(f"[bench] {name}: {ms * 1e3:.1f} us/step  {B / ms * 1e3:.3e} evals/s  tiles {tune}")
-        entry = {"ms_per_step": ms, "evals_per_s": B / ms * 1e3, "tile_us": tune}
+        log(f"[bench] {name}: {ms * 1e3:.1f} us/step  {B / ms * 1e3:.3e} evals/s  tile {tile}  "
+            f"autotune {[(e['batch'], e['tile'], round(e['us'], 1)) for e in table]}  recommended batch {rec}")
+        entry = {"ms_per_step": ms, "evals_per_s": B / ms * 1e3, "tile": tile,
+                 "autotune": {"recommended_batch": rec,
+                              "buckets": [[e["batch"], e["tile"], round(e["us"], 2)] for e in table]}}
         if not args.profile_only:
             prof = profile_gemm(m, max(10, args.steps // 10))
             gemm_avg_ms = prof.gemm_ms / max(1, prof.gemm_launches)
@@ -269,7 +276,7 @@ def main():
 
     f32 = results["f32"]
     ach = f32["gemm_tflops"]
-    f32_kernel = TILE_KERNELS.get(min(f32["tile_us"], key=lambda t: t[1])[0])
+    f32_kernel = TILE_KERNELS.get(f32["tile"])
     traffic = measured_traffic(f32_kernel)
     line = {
         "metric": "heuristic evals/s + search nodes/s per GPU (FP32 vs BF16/FP8) at matched h",

@@ -187,10 +187,37 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
  *   LDS ring filled by direct global-to-LDS loads, 4 waves.
  * All shapes give bitwise equal results.  HB_E_INVAL outside 0..9.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
-/* Autotuner: times every tile shape on n seeded states and keeps the fastest
- * for batches of about that size.  Results (tile id, microseconds) are written
- * to `report` (host, cap entries) if non-NULL. */
+/* Autotuner for one batch size: times every tile shape on the n packed states
+ * (device) and keeps the fastest for batches in n's power-of-two bucket
+ * (floor(log2 n)).  If `report` (host) is non-NULL, up to cap/2 pairs
+ * (tile id as in hb_model_set_tile, microseconds per forward pass) are written. */
 hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
+
+/* One row of the autotuner's table. */
+typedef struct {
+    int32_t batch;       /* batch size timed */
+    int32_t tile;        /* fastest tile id (hb_model_set_tile numbering) */
+    double us;           /* forward pass at that tile, microseconds */
+    double evals_per_s;  /* batch / us */
+} hb_tune_entry;
+
+/* Autotuner over batch sizes and tile shapes (Appendix: the batch size and
+ * workNum trade-off): for every power of two b <= min(n, max_batch), and for
+ * min(n, max_batch) itself, times each tile shape on the first b of the n
+ * packed states (device) and keeps the fastest for b's bucket.  Writes up to
+ * cap rows to `table` (host), their count to *rows, and to *recommended_batch
+ * the smallest timed batch whose evaluations/s reach 90% of the best.  Runs
+ * synchronously on the default stream. */
+hb_status hb_model_autotune(hb_model* m, const uint8_t* d_packed, int64_t n, hb_tune_entry* table, int cap,
+                            int* rows, int32_t* recommended_batch);
+/* Tile the model would use for a batch of n states (hb_model_set_tile numbering). */
+hb_status hb_model_tile_for(const hb_model* m, int64_t n, int* tile);
+/* Tuning cache on disk (text): the device architecture, the network shape and
+ * precision, then one line per bucket.  Loading checks that architecture,
+ * shape and precision match this model (else HB_E_INVAL) and replaces the
+ * model's bucket table. */
+hb_status hb_model_save_tuning(const hb_model* m, const char* path);
+hb_status hb_model_load_tuning(hb_model* m, const char* path);
 
 /* Per-kernel timing: while enabled, every launch of this model's kernels is
  * bracketed by HIP events recorded on the stream it runs on.  Reading

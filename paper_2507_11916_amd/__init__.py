@@ -37,6 +37,10 @@ class ModelOpts(C.Structure):
                 ("offset", C.c_float), ("combine_md", C.c_int), ("max_batch", C.c_int)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("tile", C.c_int32), ("us", C.c_double), ("evals_per_s", C.c_double)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("domain", C.c_int), ("n_in", C.c_int), ("n_dense", C.c_int), ("n_res", C.c_int),
                 ("n_out", C.c_int), ("head_kind", C.c_int), ("n_act", C.c_int), ("prec", C.c_int),
@@ -110,6 +114,11 @@ def lib():
             "hb_eval_batch_dev_n": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
             "hb_model_set_tile": ([vp, C.c_int], C.c_int),
             "hb_model_tune": ([vp, vp, i64, vp, C.c_int], C.c_int),
+            "hb_model_autotune": ([vp, vp, i64, C.POINTER(TuneEntry), C.c_int, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int32)], C.c_int),
+            "hb_model_tile_for": ([vp, i64, C.POINTER(C.c_int)], C.c_int),
+            "hb_model_save_tuning": ([vp, C.c_char_p], C.c_int),
+            "hb_model_load_tuning": ([vp, C.c_char_p], C.c_int),
             "hb_model_profile": ([vp, C.c_int], C.c_int),
             "hb_model_profile_read": ([vp, vp], C.c_int),
             "hb_trainer_create": ([C.c_char_p, C.POINTER(TrainOpts), C.POINTER(vp)], C.c_int),
@@ -268,10 +277,32 @@ class Model:
         _check(lib().hb_model_set_tile(self.handle, tile_id))
 
     def tune(self, d_packed, n=None):
+        """Tile timings [(tile id, us)] at one batch size; keeps the fastest for its bucket."""
         n = d_packed.shape[0] if n is None else n
         rep = np.zeros(32, dtype=np.float64)
         _check(lib().hb_model_tune(self.handle, C.c_void_p(d_packed.data_ptr()), n, _np_ptr(rep), 32))
         return [(int(rep[2 * i]), float(rep[2 * i + 1])) for i in range(16) if rep[2 * i + 1] > 0]
+
+    def autotune(self, d_packed, n=None):
+        """Bucket table [{batch, tile, us, evals_per_s}] and the recommended batch size."""
+        n = d_packed.shape[0] if n is None else n
+        table = (TuneEntry * 64)()
+        rows, rec = C.c_int(0), C.c_int32(0)
+        _check(lib().hb_model_autotune(self.handle, C.c_void_p(d_packed.data_ptr()), n, table, 64,
+                                       C.byref(rows), C.byref(rec)))
+        return [{"batch": e.batch, "tile": e.tile, "us": e.us, "evals_per_s": e.evals_per_s}
+                for e in table[:rows.value]], rec.value
+
+    def tile_for(self, n):
+        t = C.c_int(0)
+        _check(lib().hb_model_tile_for(self.handle, n, C.byref(t)))
+        return t.value
+
+    def save_tuning(self, path):
+        _check(lib().hb_model_save_tuning(self.handle, os.fsencode(path)))
+
+    def load_tuning(self, path):
+        _check(lib().hb_model_load_tuning(self.handle, os.fsencode(path)))
 
 
 # --------------------------------------------------------------- training

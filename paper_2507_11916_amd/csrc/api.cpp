@@ -202,6 +202,33 @@ hb_status hb_model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double*
     return model_tune(m, d_packed, n, report, cap);
 }
 
+hb_status hb_model_autotune(hb_model* m, const uint8_t* d_packed, int64_t n, hb_tune_entry* table, int cap,
+                            int* rows, int32_t* recommended_batch) {
+    if (!m || !d_packed) return fail(HB_E_INVAL, "null argument");
+    return model_autotune(m, d_packed, n, table, cap, rows, recommended_batch);
+}
+
+hb_status hb_model_tile_for(const hb_model* m, int64_t n, int* tile) {
+    if (!m || !tile || n < 1) return fail(HB_E_INVAL, "bad argument");
+    int id = -1;
+    for (const MatLayer& L : m->layers) {  // every layer uses the same rule; report the first
+        id = choose_tile(m, n, L.N_pad);
+        break;
+    }
+    *tile = id + 1;
+    return HB_OK;
+}
+
+hb_status hb_model_save_tuning(const hb_model* m, const char* path) {
+    if (!m || !path) return fail(HB_E_INVAL, "null argument");
+    return model_save_tuning(m, path);
+}
+
+hb_status hb_model_load_tuning(hb_model* m, const char* path) {
+    if (!m || !path) return fail(HB_E_INVAL, "null argument");
+    return model_load_tuning(m, path);
+}
+
 hb_status hb_model_profile(hb_model* m, int enable) {
     if (!m) return fail(HB_E_INVAL, "null model");
     return model_profile(m, enable != 0);

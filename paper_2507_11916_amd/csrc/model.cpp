@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <fstream>
 
@@ -516,43 +517,170 @@ hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n) {
     return HB_OK;
 }
 
-hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap) {
-    if (n <= 0 || n > m->opts.max_batch) return fail(HB_E_INVAL, "tuning batch must be in 1..max_batch");
+// Device buffers and events of one tuning session, released on every path.
+struct TuneScratch {
     int32_t* d_h = nullptr;
-    if (hipMalloc((void**)&d_h, (size_t)n * 4) != hipSuccess) return fail(HB_E_NOMEM, "tuning buffer");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(d_h);
+    }
+};
+
+static int bucket_of(int64_t n) {
+    int b = 0;
+    while ((1LL << (b + 1)) <= n) b++;
+    return b;
+}
+
+// Times every tile shape on the first n states; the fastest goes to *best_id
+// (internal id) and *best_us.  Pairs (set_tile id, us) go to report.
+static hb_status time_tiles(hb_model* m, const uint8_t* d_packed, int64_t n, TuneScratch& t, int* best_id,
+                            double* best_us, double* report, int cap) {
     hipStream_t s = nullptr;
-    hipEvent_t e0, e1;
-    HB_HIP(hipEventCreate(&e0));
-    HB_HIP(hipEventCreate(&e1));
-    double best = 1e30;
-    int best_id = -1, nrep = 0;
+    *best_id = -1;
+    *best_us = 1e30;
+    int nrep = 0;
     for (int id = 0; id < gemm_tile_count(); id++) {
         int bm, bn;
         gemm_tile_shape(id, &bm, &bn);
         bool ok = true;
         for (const MatLayer& L : m->layers) ok &= (L.N_pad % bn == 0);
         if (!ok) continue;
-        hb_status st = HB_OK;
-        for (int w = 0; w < 3 && st == HB_OK; w++) st = model_eval(m, d_packed, n, nullptr, 0, d_h, nullptr, s, nullptr, id);
-        if (st != HB_OK) { (void)hipFree(d_h); return st; }
-        const int reps = 10;
-        HB_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; r++) model_eval(m, d_packed, n, nullptr, 0, d_h, nullptr, s, nullptr, id);
-        HB_HIP(hipEventRecord(e1, s));
-        HB_HIP(hipEventSynchronize(e1));
+        for (int w = 0; w < 2; w++) {
+            hb_status st = model_eval(m, d_packed, n, nullptr, 0, t.d_h, nullptr, s, nullptr, id);
+            if (st != HB_OK) return st;
+        }
+        // about 2 ms of work per tile, 3 to 50 repetitions
+        const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(50, 2000000 / std::max<int64_t>(1, n * 20)));
+        HB_HIP(hipEventRecord(t.e0, s));
+        for (int r = 0; r < reps; r++) {
+            hb_status st = model_eval(m, d_packed, n, nullptr, 0, t.d_h, nullptr, s, nullptr, id);
+            if (st != HB_OK) return st;
+        }
+        HB_HIP(hipEventRecord(t.e1, s));
+        HB_HIP(hipEventSynchronize(t.e1));
         float ms = 0.f;
-        HB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        HB_HIP(hipEventElapsedTime(&ms, t.e0, t.e1));
         const double us = 1000.0 * ms / reps;
-        if (report && 2 * nrep + 1 < cap) { report[2 * nrep] = id; report[2 * nrep + 1] = us; }
+        if (report && 2 * nrep + 1 < cap) { report[2 * nrep] = id + 1; report[2 * nrep + 1] = us; }
         nrep++;
-        if (us < best) { best = us; best_id = id; }
+        if (us < *best_us) { *best_us = us; *best_id = id; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(d_h);
-    int bucket = 0;
-    while ((1LL << (bucket + 1)) <= n) bucket++;
-    if (best_id >= 0) m->tuned[bucket] = best_id;
+    return HB_OK;
+}
+
+static hb_status tune_prepare(hb_model* m, int64_t n, TuneScratch& t) {
+    HB_HIP(hipSetDevice(m->device));
+    if (hipMalloc((void**)&t.d_h, (size_t)n * 4) != hipSuccess) return fail(HB_E_NOMEM, "tuning buffer");
+    HB_HIP(hipEventCreate(&t.e0));
+    HB_HIP(hipEventCreate(&t.e1));
+    return HB_OK;
+}
+
+hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap) {
+    if (n <= 0 || n > m->opts.max_batch) return fail(HB_E_INVAL, "tuning batch must be in 1..max_batch");
+    TuneScratch t;
+    hb_status st = tune_prepare(m, n, t);
+    if (st != HB_OK) return st;
+    int best_id;
+    double best_us;
+    st = time_tiles(m, d_packed, n, t, &best_id, &best_us, report, cap);
+    if (st != HB_OK) return st;
+    if (best_id >= 0) m->tuned[bucket_of(n)] = best_id;
+    return HB_OK;
+}
+
+hb_status model_autotune(hb_model* m, const uint8_t* d_packed, int64_t n, hb_tune_entry* table, int cap, int* rows,
+                         int32_t* recommended) {
+    const int64_t top = std::min<int64_t>(n, m->opts.max_batch);
+    if (top <= 0) return fail(HB_E_INVAL, "autotuning needs at least one state");
+    std::vector<int64_t> batches;
+    for (int64_t b = 1; b <= top; b *= 2) batches.push_back(b);
+    if (batches.back() != top) batches.push_back(top);
+    TuneScratch t;
+    hb_status st = tune_prepare(m, top, t);
+    if (st != HB_OK) return st;
+    std::vector<hb_tune_entry> out;
+    for (int64_t b : batches) {
+        int best_id;
+        double best_us;
+        st = time_tiles(m, d_packed, b, t, &best_id, &best_us, nullptr, 0);
+        if (st != HB_OK) return st;
+        if (best_id < 0) return fail(HB_E_UNSUPPORTED, "no tile shape fits this network");
+        m->tuned[bucket_of(b)] = best_id;
+        out.push_back(hb_tune_entry{(int32_t)b, best_id + 1, best_us, b / (best_us * 1e-6)});
+    }
+    double best_rate = 0;
+    for (const auto& e : out) best_rate = std::max(best_rate, e.evals_per_s);
+    int32_t rec = out.back().batch;
+    for (const auto& e : out)
+        if (e.evals_per_s >= 0.9 * best_rate) { rec = e.batch; break; }
+    if (recommended) *recommended = rec;
+    const int k = (int)std::min<size_t>(out.size(), (size_t)std::max(0, cap));
+    if (table) std::copy(out.begin(), out.begin() + k, table);
+    if (rows) *rows = table ? k : (int)out.size();
+    return HB_OK;
+}
+
+// Tuning file: "hbtune 1", "arch <gcnArchName>", "model <signature>", then
+// "bucket <log2> tile <internal id>" lines.
+static std::string model_signature(const hb_model* m) {
+    std::string sig = "d" + std::to_string(m->spec.domain) + " in" + std::to_string(m->spec.n_in) + " dims";
+    for (int d : m->spec.dims) sig += "_" + std::to_string(d);
+    sig += " res" + std::to_string(m->spec.n_res) + " out" + std::to_string(m->spec.n_out) + " prec" +
+           std::to_string((int)m->opts.prec);
+    return sig;
+}
+
+static hb_status device_arch(int device, std::string* arch) {
+    hipDeviceProp_t prop;
+    HB_HIP(hipGetDeviceProperties(&prop, device));
+    *arch = prop.gcnArchName;
+    const size_t colon = arch->find(':');
+    if (colon != std::string::npos) arch->resize(colon);
+    return HB_OK;
+}
+
+hb_status model_save_tuning(const hb_model* m, const char* path) {
+    std::string arch;
+    hb_status st = device_arch(m->device, &arch);
+    if (st != HB_OK) return st;
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(HB_E_INVAL, "cannot write %s", path);
+    fprintf(f, "hbtune 1\narch %s\nmodel %s\n", arch.c_str(), model_signature(m).c_str());
+    for (const auto& kv : m->tuned) fprintf(f, "bucket %d tile %d\n", kv.first, kv.second);
+    const bool ok = fclose(f) == 0;
+    return ok ? HB_OK : fail(HB_E_INVAL, "cannot write %s", path);
+}
+
+hb_status model_load_tuning(hb_model* m, const char* path) {
+    std::string arch;
+    hb_status st = device_arch(m->device, &arch);
+    if (st != HB_OK) return st;
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(HB_E_INVAL, "cannot read %s", path);
+    std::vector<std::string> lines;
+    char buf[512];
+    while (fgets(buf, sizeof buf, f)) {
+        std::string l(buf);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        lines.push_back(l);
+    }
+    fclose(f);
+    if (lines.size() < 3 || lines[0] != "hbtune 1") return fail(HB_E_INVAL, "%s is not a tuning file", path);
+    if (lines[1] != "arch " + arch) return fail(HB_E_INVAL, "%s was tuned on %s, this device is %s", path, lines[1].c_str() + 5, arch.c_str());
+    if (lines[2] != "model " + model_signature(m)) return fail(HB_E_INVAL, "%s was tuned for another network or precision", path);
+    std::map<int, int> tuned;
+    for (size_t i = 3; i < lines.size(); i++) {
+        int b = -1, id = -1;
+        if (sscanf(lines[i].c_str(), "bucket %d tile %d", &b, &id) != 2 || b < 0 || b > 40 || id < 0 ||
+            id >= gemm_tile_count())
+            return fail(HB_E_INVAL, "%s: bad line %zu", path, i + 1);
+        tuned[b] = id;
+    }
+    m->tuned = tuned;
     return HB_OK;
 }
 

@@ -83,6 +83,10 @@ hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int3
 hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n);
 hb_status model_prepare(hb_model* m, hipStream_t s);  // allocate the stream's workspace now
 hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
+hb_status model_autotune(hb_model* m, const uint8_t* d_packed, int64_t n, hb_tune_entry* table, int cap, int* rows,
+                         int32_t* recommended);
+hb_status model_save_tuning(const hb_model* m, const char* path);
+hb_status model_load_tuning(hb_model* m, const char* path);
 int choose_tile(const hb_model* m, int64_t M, int N_pad);
 hb_status model_profile(hb_model* m, bool enable);
 hb_status model_profile_read(hb_model* m, hb_profile* out);

@@ -273,3 +273,34 @@ def test_fp8_requires_calibration(net_files):
     st = synth.stp_walks(4, [1, 2], lengths=10)
     with pytest.raises(hb.HBError, match="calibrate"):
         _eval(m, hb.hb_encode(1, st), 1)
+
+
+def test_autotuner_table_and_tuning_cache(net_files, tmp_path):
+    """Bucket autotuner: one row per power-of-two batch, the model then uses the
+    tuned tile per bucket, the table survives a save/load round trip, a file for
+    another precision is refused, and outputs do not depend on the table."""
+    path = net_files["stp4_res"]
+    st = synth.stp_walks(4, synth.throughput_seeds(1500, 31), lengths=200)
+    d = _dev(hb.hb_encode(1, st))
+    m = hb.Model(path, prec=hb.HB_BF16, max_batch=2048)
+    ref = _eval(m, hb.hb_encode(1, st), 1)
+    table, rec = m.autotune(d)
+    print("autotune", [(e["batch"], e["tile"], round(e["us"], 1)) for e in table], "recommended", rec)
+    assert [e["batch"] for e in table] == [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 1500]
+    assert all(1 <= e["tile"] <= 9 and e["us"] > 0 for e in table)
+    assert rec in [e["batch"] for e in table]
+    best = max(e["evals_per_s"] for e in table)
+    assert next(e for e in table if e["batch"] == rec)["evals_per_s"] >= 0.9 * best
+    for e in table[:-2]:  # rows 1024 and 1500 share a bucket: the later row holds it
+        assert m.tile_for(e["batch"]) == e["tile"]
+    assert m.tile_for(1024) == m.tile_for(1500) == table[-1]["tile"]
+    f = str(tmp_path / "tuning.txt")
+    m.save_tuning(f)
+    m2 = hb.Model(path, prec=hb.HB_BF16, max_batch=2048)
+    m2.load_tuning(f)
+    for b in (1, 3, 100, 700, 1500):
+        assert m2.tile_for(b) == m.tile_for(b)
+    out = _eval(m2, hb.hb_encode(1, st), 1)
+    np.testing.assert_array_equal(out[1], ref[1])
+    with pytest.raises(hb.HBError, match="another network or precision"):
+        hb.Model(path, prec=hb.HB_FP32, max_batch=2048).load_tuning(f)
