@@ -76,57 +76,87 @@ struct Dec<2> {  // cube
 };
 
 // ------------------------------------------------------------ layer 1
-// One block of 256 threads handles ROWS states; thread t owns four
-// consecutive columns per 1024-column slab.  Rows >= n are written as zeros.
+// Gather-sum over a column slice.  A block owns GCOLS columns of the table for
+// GROWS consecutive states: it copies the table's column slice (all
+// P * S rows, a few tens of KiB) into LDS once, then each thread forms 8
+// columns of one state at a time by summing the state's P rows out of LDS.
+// Reading the slice once per block instead of once per state cuts the
+// gathered L2 traffic by about GROWS / S.  Sum order per output: bias, then
+// the cells in order.  Rows in [n, m_rows) are written as zeros.
+constexpr int GCOLS = 64, GROWS = 256;
+
 template <int DOM, int WT /*0 f32, 1 bf16 table*/, int OUT /*0 f32, 1 bf16, 2 fp8*/>
 __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restrict__ packed, const int32_t* n_dev,
                                                         int n_host, int m_rows, const void* __restrict__ table,
-                                                        const float* __restrict__ bias, int N, int ld_out,
-                                                        void* __restrict__ out, float out_inv_scale) {
+                                                        int t_rows, const float* __restrict__ bias, int N,
+                                                        int ld_out, void* __restrict__ out, float out_inv_scale) {
     using D = Dec<DOM>;
-    constexpr int ROWS = 8;
+    constexpr int TB = WT == 0 ? 4 : 2;             // table bytes per element
+    constexpr int ROWB = GCOLS * TB;                // bytes of one table row's slice
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * GCOLS;
+    const int r0 = blockIdx.y * GROWS;
     const int n = min(n_dev ? *n_dev : n_host, m_rows);
-    const int r0 = blockIdx.x * ROWS;
-    for (int rr = 0; rr < ROWS; rr++) {
+
+    // table slice -> LDS, 16-byte pieces
+    const int pieces = t_rows * (ROWB / 16);
+    for (int i = tid; i < pieces; i += 256) {
+        const int r = i / (ROWB / 16), q = i % (ROWB / 16);
+        const uint8_t* src = reinterpret_cast<const uint8_t*>(table) + ((size_t)r * N + c0) * TB + q * 16;
+        *reinterpret_cast<uint4*>(smem + r * ROWB + q * 16) = *reinterpret_cast<const uint4*>(src);
+    }
+    __syncthreads();
+
+    const int chunk = tid & 7;                      // 8 columns: c0 + 8 * chunk ..
+    const int col = c0 + 8 * chunk;
+    float b[8];
+    _Pragma("unroll") for (int j = 0; j < 8; j++) b[j] = bias[col + j];
+    for (int rr = tid >> 3; rr < GROWS; rr += 32) {
         const int r = r0 + rr;
-        if (r >= m_rows) return;
-        uint64_t w[D::WORDS];
-        const bool live = r < n;
-        if (live)
-            for (int i = 0; i < D::WORDS; i++) w[i] = packed[(size_t)r * D::WORDS + i];
-        for (int c = threadIdx.x * 4; c < N; c += 1024) {
-            float acc[4] = {0.f, 0.f, 0.f, 0.f};
-            if (live) {
-                const float4 b = *reinterpret_cast<const float4*>(bias + c);
-                acc[0] = b.x; acc[1] = b.y; acc[2] = b.z; acc[3] = b.w;
-                for (int p = 0; p < D::P; p++) {
-                    const size_t g = (size_t)D::row(w, p) * N + c;
-                    if (WT == 0) {
-                        const float4 v = *reinterpret_cast<const float4*>((const float*)table + g);
-                        acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
-                    } else {
-                        const uint2 v = *reinterpret_cast<const uint2*>((const uint16_t*)table + g);
-                        acc[0] += bf16_to_f32((uint16_t)(v.x & 0xFFFF));
-                        acc[1] += bf16_to_f32((uint16_t)(v.x >> 16));
-                        acc[2] += bf16_to_f32((uint16_t)(v.y & 0xFFFF));
-                        acc[3] += bf16_to_f32((uint16_t)(v.y >> 16));
+        if (r >= m_rows) break;
+        float acc[8];
+        _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = 0.f;
+        if (r < n) {
+            uint64_t w[D::WORDS];
+            _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[i] = packed[(size_t)r * D::WORDS + i];
+            _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = b[j];
+            _Pragma("unroll 16") for (int p = 0; p < D::P; p++) {
+                const uint8_t* src = smem + D::row(w, p) * ROWB + chunk * 8 * TB;
+                if (WT == 0) {
+                    const float4 v0 = *reinterpret_cast<const float4*>(src);
+                    const float4 v1 = *reinterpret_cast<const float4*>(src + 16);
+                    acc[0] += v0.x; acc[1] += v0.y; acc[2] += v0.z; acc[3] += v0.w;
+                    acc[4] += v1.x; acc[5] += v1.y; acc[6] += v1.z; acc[7] += v1.w;
+                } else {
+                    const uint4 v = *reinterpret_cast<const uint4*>(src);
+                    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+                    _Pragma("unroll") for (int j = 0; j < 4; j++) {
+                        acc[2 * j] += bf16_to_f32((uint16_t)(u[j] & 0xFFFF));
+                        acc[2 * j + 1] += bf16_to_f32((uint16_t)(u[j] >> 16));
                     }
                 }
-                for (int i = 0; i < 4; i++) acc[i] = fmaxf(acc[i], 0.f);
             }
-            const size_t o = (size_t)r * ld_out + c;
-            if (OUT == 0) {
-                *reinterpret_cast<float4*>((float*)out + o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-            } else if (OUT == 1) {
-                uint2 v;
-                v.x = (uint32_t)f32_to_bf16(acc[0]) | ((uint32_t)f32_to_bf16(acc[1]) << 16);
-                v.y = (uint32_t)f32_to_bf16(acc[2]) | ((uint32_t)f32_to_bf16(acc[3]) << 16);
-                *reinterpret_cast<uint2*>((uint16_t*)out + o) = v;
-            } else {
-                const uint32_t lo = f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale);
-                const uint32_t hi = f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale);
-                *reinterpret_cast<uint32_t*>((uint8_t*)out + o) = lo | (hi << 16);
-            }
+            _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = fmaxf(acc[j], 0.f);
+        }
+        const size_t o = (size_t)r * ld_out + col;
+        if (OUT == 0) {
+            *reinterpret_cast<float4*>((float*)out + o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            *reinterpret_cast<float4*>((float*)out + o + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        } else if (OUT == 1) {
+            uint4 v;
+            v.x = (uint32_t)f32_to_bf16(acc[0]) | ((uint32_t)f32_to_bf16(acc[1]) << 16);
+            v.y = (uint32_t)f32_to_bf16(acc[2]) | ((uint32_t)f32_to_bf16(acc[3]) << 16);
+            v.z = (uint32_t)f32_to_bf16(acc[4]) | ((uint32_t)f32_to_bf16(acc[5]) << 16);
+            v.w = (uint32_t)f32_to_bf16(acc[6]) | ((uint32_t)f32_to_bf16(acc[7]) << 16);
+            *reinterpret_cast<uint4*>((uint16_t*)out + o) = v;
+        } else {
+            uint2 v;
+            v.x = f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale) |
+                  (f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale) << 16);
+            v.y = f32x2_to_fp8x2(acc[4] * out_inv_scale, acc[5] * out_inv_scale) |
+                  (f32x2_to_fp8x2(acc[6] * out_inv_scale, acc[7] * out_inv_scale) << 16);
+            *reinterpret_cast<uint2*>((uint8_t*)out + o) = v;
         }
     }
 }
@@ -574,11 +604,92 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
 }
 
 // ------------------------------------------------------------ head
-// One wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o] for o < n_out,
-// lanes own K slices of 4; wave-wide butterfly sums; lane 0 applies the
-// output rule.
+// Manhattan distance of a packed sliding-tile state (board side known at
+// compile time).
+template <int SIDE>
+__device__ __forceinline__ int manhattan_packed(uint64_t w) {
+    int md = 0;
+    _Pragma("unroll") for (int p = 0; p < SIDE * SIDE; p++) {
+        const int t = (int)((w >> (4 * p)) & 15);
+        if (t) md += abs(p / SIDE - t / SIDE) + abs(p % SIDE - t % SIDE);
+    }
+    return md;
+}
+
+__device__ __forceinline__ int head_md(const HeadArgs& h, int r) {
+    if (!h.combine_md || h.domain >= 2) return -1;
+    const uint64_t w = reinterpret_cast<const uint64_t*>(h.packed)[r];
+    return h.domain == 0 ? manhattan_packed<3>(w) : manhattan_packed<4>(w);
+}
+
+// Regression output rule: h = floor / round-half-even of y - offset, clamped
+// at 0, then min / max with Manhattan distance; non-finite -> MD or 0.
+__device__ __forceinline__ void regression_rule(const HeadArgs& h, int r, float y, int md) {
+    const float v = y - h.offset;
+    int hv;
+    if (!isfinite(v)) {
+        hv = md >= 0 ? md : 0;
+    } else {
+        const float f = h.mode == 1 ? rintf(v) : floorf(v);
+        hv = f < 0.f ? 0 : f > 1e9f ? 1000000000 : (int)f;
+        if (md >= 0) hv = h.combine_md == 2 ? max(hv, md) : min(hv, md);
+    }
+    if (h.raw) h.raw[r] = v;
+    h.h_out[r] = hv;
+}
+
+// Regression head: 16 lanes per state (4 states per wave, 16 per block), each
+// lane summing x[k] * w[k] over 16-byte slices k = 16-lane stride apart, then
+// a 16-lane butterfly; the first lane of each group applies the rule.
+template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/>
+__global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
+    constexpr int CH = IN == 0 ? 4 : IN == 1 ? 8 : 16;  // elements per 16-byte load of x
+    const int j = threadIdx.x & 15;
+    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
+    const int r = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = r < n;
+    float y = 0.f;
+    if (live) {
+        const uint8_t* xrow = reinterpret_cast<const uint8_t*>(h.X) + (size_t)r * h.ldx * (IN == 0 ? 4 : IN == 1 ? 2 : 1);
+        for (int k = j * CH; k < h.K; k += 16 * CH) {
+            float x[CH], w[CH];
+            const uint4 xv = *reinterpret_cast<const uint4*>(xrow + (size_t)k * (IN == 0 ? 4 : IN == 1 ? 2 : 1));
+            const uint32_t xu[4] = {xv.x, xv.y, xv.z, xv.w};
+            if (IN == 0) {
+                _Pragma("unroll") for (int e = 0; e < 4; e++) x[e] = __uint_as_float(xu[e]);
+            } else if (IN == 1) {
+                _Pragma("unroll") for (int e = 0; e < 4; e++) {
+                    x[2 * e] = bf16_to_f32((uint16_t)(xu[e] & 0xFFFF));
+                    x[2 * e + 1] = bf16_to_f32((uint16_t)(xu[e] >> 16));
+                }
+            } else {
+                _Pragma("unroll") for (int e = 0; e < 16; e++) x[e] = fp8_to_f32((xu[e >> 2] >> (8 * (e & 3))) & 0xFF) * h.x_scale;
+            }
+            if (HW == 0) {
+                _Pragma("unroll") for (int e = 0; e < CH; e++) w[e] = reinterpret_cast<const float*>(h.W)[k + e];
+            } else {
+                _Pragma("unroll") for (int q = 0; q < CH / 8; q++) {
+                    const uint4 wv = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(h.W) + k + 8 * q);
+                    const uint32_t wu[4] = {wv.x, wv.y, wv.z, wv.w};
+                    _Pragma("unroll") for (int e = 0; e < 4; e++) {
+                        w[8 * q + 2 * e] = bf16_to_f32((uint16_t)(wu[e] & 0xFFFF));
+                        w[8 * q + 2 * e + 1] = bf16_to_f32((uint16_t)(wu[e] >> 16));
+                    }
+                }
+            }
+            _Pragma("unroll") for (int e = 0; e < CH; e++) y += x[e] * w[e];
+        }
+    }
+    _Pragma("unroll") for (int s = 8; s >= 1; s >>= 1) y += __shfl_xor(y, s, 64);
+    if (!live || j != 0) return;
+    regression_rule(h, r, y + h.b[0], head_md(h, r));
+}
+
+// Classifier head: one wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o]
+// for o < n_out, lanes own K slices of 4; wave-wide butterfly sums; lane 0
+// applies the quantile or arg-max rule.
 template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/, int NOUT>
-__global__ __launch_bounds__(256) void head_kernel(HeadArgs h) {
+__global__ __launch_bounds__(256) void head_cls_kernel(HeadArgs h) {
     const int lane = threadIdx.x & 63;
     const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -621,51 +732,33 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs h) {
         y[o] = v + h.b[o];
     }
     if (lane != 0) return;
-    int md = -1;
-    if (h.combine_md && h.domain < 2) {
-        const uint64_t w = reinterpret_cast<const uint64_t*>(h.packed)[r];
-        const int side = h.domain == 0 ? 3 : 4;
-        md = 0;
-        for (int p = 0; p < side * side; p++) {
-            const int t = (int)((w >> (4 * p)) & 15);
-            if (t) md += abs(p / side - t / side) + abs(p % side - t % side);
-        }
-    }
+    const int md = head_md(h, r);
     int hv;
-    if (h.mode >= 3) {
-        if (h.mode == 4) {
-            int best = 0;
-            for (int o = 1; o < NOUT; o++)
-                if (o < h.n_out && y[o] > y[best]) best = o;
-            hv = best;
-        } else {
-            float mx = y[0];
-            for (int o = 1; o < NOUT; o++)
-                if (o < h.n_out) mx = fmaxf(mx, y[o]);
-            float e[NOUT], sum = 0.f;
-            for (int o = 0; o < NOUT; o++)
-                if (o < h.n_out) { e[o] = expf(y[o] - mx); sum += e[o]; }
-            float cdf = 0.f;
-            hv = h.n_out - 1;
-            for (int o = 0; o < NOUT; o++) {
-                if (o >= h.n_out) break;
-                cdf += e[o] / sum;
-                if (cdf >= h.q) { hv = o; break; }
-            }
-            if (!(sum > 0.f) || !isfinite(mx)) hv = md >= 0 ? md : 0;
+    if (h.mode == 4) {
+        int best = 0;
+        for (int o = 1; o < NOUT; o++)
+            if (o < h.n_out && y[o] > y[best]) best = o;
+        hv = best;
+    } else if (h.mode == 3) {
+        float mx = y[0];
+        for (int o = 1; o < NOUT; o++)
+            if (o < h.n_out) mx = fmaxf(mx, y[o]);
+        float e[NOUT], sum = 0.f;
+        for (int o = 0; o < NOUT; o++)
+            if (o < h.n_out) { e[o] = expf(y[o] - mx); sum += e[o]; }
+        float cdf = 0.f;
+        hv = h.n_out - 1;
+        for (int o = 0; o < NOUT; o++) {
+            if (o >= h.n_out) break;
+            cdf += e[o] / sum;
+            if (cdf >= h.q) { hv = o; break; }
         }
-        if (h.raw) for (int o = 0; o < NOUT; o++) if (o < h.n_out) h.raw[(size_t)r * h.n_out + o] = y[o];
+        if (!(sum > 0.f) || !isfinite(mx)) hv = md >= 0 ? md : 0;
     } else {
-        const float v = y[0] - h.offset;
-        if (!isfinite(v)) {
-            hv = md >= 0 ? md : 0;
-        } else {
-            const float f = h.mode == 1 ? rintf(v) : floorf(v);
-            hv = f < 0.f ? 0 : f > 1e9f ? 1000000000 : (int)f;
-            if (md >= 0) hv = h.combine_md == 2 ? max(hv, md) : min(hv, md);
-        }
-        if (h.raw) h.raw[r] = v;
+        regression_rule(h, r, y[0], md);  // a one-output network under a regression rule
+        return;
     }
+    if (h.raw) for (int o = 0; o < NOUT; o++) if (o < h.n_out) h.raw[(size_t)r * h.n_out + o] = y[o];
     h.h_out[r] = hv;
 }
 
@@ -685,10 +778,11 @@ __global__ void absmax_kernel(const float* __restrict__ x, int n, int N, int ld,
 // ------------------------------------------------------------ launchers
 template <int DOM, int WT, int OUT>
 static void launch_gather_t(const GatherLaunch& L, hipStream_t s) {
-    const int blocks = (L.m_rows + 7) / 8;
-    hipLaunchKernelGGL((gather_l1_kernel<DOM, WT, OUT>), dim3(blocks), dim3(256), 0, s,
-                       reinterpret_cast<const uint64_t*>(L.packed), L.n_dev, L.n_host, L.m_rows, L.table, L.bias, L.N,
-                       L.ld_out, L.out, L.out_inv_scale);
+    const dim3 grid(L.N / GCOLS, (L.m_rows + GROWS - 1) / GROWS);
+    const size_t lds = (size_t)L.t_rows * GCOLS * (WT == 0 ? 4 : 2);
+    hipLaunchKernelGGL((gather_l1_kernel<DOM, WT, OUT>), grid, dim3(256), lds, s,
+                       reinterpret_cast<const uint64_t*>(L.packed), L.n_dev, L.n_host, L.m_rows, L.table, L.t_rows,
+                       L.bias, L.N, L.ld_out, L.out, L.out_inv_scale);
 }
 
 template <int DOM>
@@ -797,11 +891,10 @@ bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
 template <int IN, int HW>
 static bool launch_head_t(HeadArgs H, int m_cap, hipStream_t s) {
     H.m_cap = m_cap;
-    const int blocks = (m_cap + 3) / 4;
-    if (H.n_out == 1)
-        hipLaunchKernelGGL((head_kernel<IN, HW, 1>), dim3(blocks), dim3(256), 0, s, H);
+    if (H.n_out == 1 && H.mode <= 2)
+        hipLaunchKernelGGL((head_reg_kernel<IN, HW>), dim3((m_cap + 15) / 16), dim3(256), 0, s, H);
     else if (H.n_out <= 32)
-        hipLaunchKernelGGL((head_kernel<IN, HW, 32>), dim3(blocks), dim3(256), 0, s, H);
+        hipLaunchKernelGGL((head_cls_kernel<IN, HW, 32>), dim3((m_cap + 3) / 4), dim3(256), 0, s, H);
     else
         return false;
     return true;
@@ -838,9 +931,26 @@ static hipError_t set_lds_attr_p() {
     return e;
 }
 
-// Blocks of the larger tiles use more than 64 KiB of LDS (gfx950 has 160 KiB).
+template <int DOM, int WT, int OUT>
+static hipError_t set_gather_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_l1_kernel<DOM, WT, OUT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 288 * GCOLS * 4);
+}
+
+template <int DOM>
+static hipError_t set_gather_attr_d() {
+    hipError_t e = set_gather_attr<DOM, 0, 0>();
+    if (e == hipSuccess) e = set_gather_attr<DOM, 1, 1>();
+    if (e == hipSuccess) e = set_gather_attr<DOM, 1, 2>();
+    return e;
+}
+
+// Kernels whose blocks may use more than 64 KiB of LDS (gfx950 has 160 KiB).
 hipError_t gemm_prepare_attributes() {
-    hipError_t e = set_lds_attr_p<0, 0>();
+    hipError_t e = set_gather_attr_d<0>();
+    if (e == hipSuccess) e = set_gather_attr_d<1>();
+    if (e == hipSuccess) e = set_gather_attr_d<2>();
+    if (e == hipSuccess) e = set_lds_attr_p<0, 0>();
     if (e == hipSuccess) e = set_lds_attr_p<1, 1>();
     if (e == hipSuccess) e = set_lds_attr_p<1, 0>();
     if (e == hipSuccess) e = set_lds_attr_p<2, 2>();

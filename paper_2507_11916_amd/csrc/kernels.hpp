@@ -13,9 +13,10 @@ struct GatherLaunch {
     const int32_t* n_dev;   // device state count or null
     int n_host;
     int m_rows;             // rows written (>= n, padded rows are zero)
-    const void* table;      // [rows][N] layer-1 table (fp32 or bf16)
+    const void* table;      // [t_rows][N] layer-1 table (fp32 or bf16)
+    int t_rows;             // table rows (P * S)
     const float* bias;      // [N]
-    int N;                  // padded width (multiple of 4)
+    int N;                  // padded width (multiple of 64)
     int ld_out;             // elements
     void* out;
     float out_inv_scale;    // fp8 output

@@ -383,6 +383,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     G.n_host = n;
     G.m_rows = rows;
     G.table = m->l1_table;
+    G.t_rows = m->table_rows;
     G.bias = m->l1_bias;
     G.N = m->N1_pad;
     G.ld_out = m->width_cap;
