@@ -212,10 +212,13 @@ class Pdb:
         _check(lib().hb_pdb_lookup(self.handle, _np_ptr(s), s.shape[0], _np_ptr(out)))
         return out
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None):
             lib().hb_pdb_free(self.handle)
             self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 # ----------------------------------------------------------------- model

@@ -78,8 +78,9 @@ struct Dec<2> {  // cube
 // ------------------------------------------------------------ layer 1
 // Gather-sum over a column slice.  A block owns GCOLS columns of the table for
 // GROWS consecutive states: it copies the table's column slice (all
-// P * S rows, a few tens of KiB) into LDS once, then each thread forms 8
-// columns of one state at a time by summing the state's P rows out of LDS.
+// P * S rows, a few tens of KiB) and the states' packed records into LDS once,
+// then each thread forms 4 columns of one state at a time by summing the
+// state's P rows out of LDS.
 // Reading the slice once per block instead of once per state cuts the
 // gathered L2 traffic by about GROWS / S.  Sum order per output: bias, then
 // the cells in order.  Rows in [n, m_rows) are written as zeros.
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restri
     constexpr int TB = WT == 0 ? 4 : 2;             // table bytes per element
     constexpr int ROWB = GCOLS * TB;                // bytes of one table row's slice
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    __shared__ uint64_t recs[GROWS * D::WORDS];     // packed records of the block's states
     const int tid = threadIdx.x;
     const int c0 = blockIdx.x * GCOLS;
     const int r0 = blockIdx.y * GROWS;
@@ -106,57 +108,53 @@ __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restri
         const uint8_t* src = reinterpret_cast<const uint8_t*>(table) + ((size_t)r * N + c0) * TB + q * 16;
         *reinterpret_cast<uint4*>(smem + r * ROWB + q * 16) = *reinterpret_cast<const uint4*>(src);
     }
+    for (int i = tid; i < GROWS * D::WORDS; i += 256) {
+        const int r = r0 + i / D::WORDS;
+        recs[i] = r < n ? packed[(size_t)r0 * D::WORDS + i] : 0;
+    }
     __syncthreads();
 
-    const int chunk = tid & 7;                      // 8 columns: c0 + 8 * chunk ..
-    const int col = c0 + 8 * chunk;
-    float b[8];
-    _Pragma("unroll") for (int j = 0; j < 8; j++) b[j] = bias[col + j];
-    for (int rr = tid >> 3; rr < GROWS; rr += 32) {
+    // 16 lanes per state, 4 columns per lane: a 16-lane group reads one
+    // table row's slice contiguously (a full bank line for float32 entries).
+    const int chunk = tid & 15;
+    const int col = c0 + 4 * chunk;
+    float b[4];
+    _Pragma("unroll") for (int j = 0; j < 4; j++) b[j] = bias[col + j];
+    for (int rr = tid >> 4; rr < GROWS; rr += 16) {
         const int r = r0 + rr;
         if (r >= m_rows) break;
-        float acc[8];
-        _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = 0.f;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
         if (r < n) {
             uint64_t w[D::WORDS];
-            _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[i] = packed[(size_t)r * D::WORDS + i];
-            _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = b[j];
+            _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[i] = recs[rr * D::WORDS + i];
+            _Pragma("unroll") for (int j = 0; j < 4; j++) acc[j] = b[j];
             _Pragma("unroll 16") for (int p = 0; p < D::P; p++) {
-                const uint8_t* src = smem + D::row(w, p) * ROWB + chunk * 8 * TB;
+                const uint8_t* src = smem + D::row(w, p) * ROWB + chunk * 4 * TB;
                 if (WT == 0) {
-                    const float4 v0 = *reinterpret_cast<const float4*>(src);
-                    const float4 v1 = *reinterpret_cast<const float4*>(src + 16);
-                    acc[0] += v0.x; acc[1] += v0.y; acc[2] += v0.z; acc[3] += v0.w;
-                    acc[4] += v1.x; acc[5] += v1.y; acc[6] += v1.z; acc[7] += v1.w;
+                    const float4 v = *reinterpret_cast<const float4*>(src);
+                    acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
                 } else {
-                    const uint4 v = *reinterpret_cast<const uint4*>(src);
-                    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-                    _Pragma("unroll") for (int j = 0; j < 4; j++) {
-                        acc[2 * j] += bf16_to_f32((uint16_t)(u[j] & 0xFFFF));
-                        acc[2 * j + 1] += bf16_to_f32((uint16_t)(u[j] >> 16));
-                    }
+                    const uint2 v = *reinterpret_cast<const uint2*>(src);
+                    acc[0] += bf16_to_f32((uint16_t)(v.x & 0xFFFF));
+                    acc[1] += bf16_to_f32((uint16_t)(v.x >> 16));
+                    acc[2] += bf16_to_f32((uint16_t)(v.y & 0xFFFF));
+                    acc[3] += bf16_to_f32((uint16_t)(v.y >> 16));
                 }
             }
-            _Pragma("unroll") for (int j = 0; j < 8; j++) acc[j] = fmaxf(acc[j], 0.f);
+            _Pragma("unroll") for (int j = 0; j < 4; j++) acc[j] = fmaxf(acc[j], 0.f);
         }
         const size_t o = (size_t)r * ld_out + col;
         if (OUT == 0) {
             *reinterpret_cast<float4*>((float*)out + o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-            *reinterpret_cast<float4*>((float*)out + o + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
         } else if (OUT == 1) {
-            uint4 v;
+            uint2 v;
             v.x = (uint32_t)f32_to_bf16(acc[0]) | ((uint32_t)f32_to_bf16(acc[1]) << 16);
             v.y = (uint32_t)f32_to_bf16(acc[2]) | ((uint32_t)f32_to_bf16(acc[3]) << 16);
-            v.z = (uint32_t)f32_to_bf16(acc[4]) | ((uint32_t)f32_to_bf16(acc[5]) << 16);
-            v.w = (uint32_t)f32_to_bf16(acc[6]) | ((uint32_t)f32_to_bf16(acc[7]) << 16);
-            *reinterpret_cast<uint4*>((uint16_t*)out + o) = v;
+            *reinterpret_cast<uint2*>((uint16_t*)out + o) = v;
         } else {
-            uint2 v;
-            v.x = f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale) |
-                  (f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale) << 16);
-            v.y = f32x2_to_fp8x2(acc[4] * out_inv_scale, acc[5] * out_inv_scale) |
-                  (f32x2_to_fp8x2(acc[6] * out_inv_scale, acc[7] * out_inv_scale) << 16);
-            *reinterpret_cast<uint2*>((uint8_t*)out + o) = v;
+            *reinterpret_cast<uint32_t*>((uint8_t*)out + o) =
+                f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale) |
+                (f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale) << 16);
         }
     }
 }
@@ -648,6 +646,8 @@ __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
     const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
     const int r = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = r < n;
+    // the record for the Manhattan rule is fetched before the dot product
+    const uint64_t rec = live && j == 0 && h.combine_md && h.domain < 2 ? reinterpret_cast<const uint64_t*>(h.packed)[r] : 0;
     float y = 0.f;
     if (live) {
         const uint8_t* xrow = reinterpret_cast<const uint8_t*>(h.X) + (size_t)r * h.ldx * (IN == 0 ? 4 : IN == 1 ? 2 : 1);
@@ -682,7 +682,9 @@ __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
     }
     _Pragma("unroll") for (int s = 8; s >= 1; s >>= 1) y += __shfl_xor(y, s, 64);
     if (!live || j != 0) return;
-    regression_rule(h, r, y + h.b[0], head_md(h, r));
+    int md = -1;
+    if (h.combine_md && h.domain < 2) md = h.domain == 0 ? manhattan_packed<3>(rec) : manhattan_packed<4>(rec);
+    regression_rule(h, r, y + h.b[0], md);
 }
 
 // Classifier head: one wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o]
@@ -787,9 +789,15 @@ static void launch_gather_t(const GatherLaunch& L, hipStream_t s) {
 
 template <int DOM>
 static bool launch_gather_d(const GatherLaunch& L, hipStream_t s) {
-    if (L.prec == 0) launch_gather_t<DOM, 0, 0>(L, s);
-    else if (L.prec == 1) launch_gather_t<DOM, 1, 1>(L, s);
-    else launch_gather_t<DOM, 1, 2>(L, s);
+    if (L.table_f32) {
+        if (L.prec == 0) launch_gather_t<DOM, 0, 0>(L, s);
+        else if (L.prec == 1) launch_gather_t<DOM, 0, 1>(L, s);
+        else launch_gather_t<DOM, 0, 2>(L, s);
+    } else {
+        if (L.prec == 1) launch_gather_t<DOM, 1, 1>(L, s);
+        else if (L.prec == 2) launch_gather_t<DOM, 1, 2>(L, s);
+        else return false;
+    }
     return true;
 }
 
@@ -940,6 +948,8 @@ static hipError_t set_gather_attr() {
 template <int DOM>
 static hipError_t set_gather_attr_d() {
     hipError_t e = set_gather_attr<DOM, 0, 0>();
+    if (e == hipSuccess) e = set_gather_attr<DOM, 0, 1>();
+    if (e == hipSuccess) e = set_gather_attr<DOM, 0, 2>();
     if (e == hipSuccess) e = set_gather_attr<DOM, 1, 1>();
     if (e == hipSuccess) e = set_gather_attr<DOM, 1, 2>();
     return e;

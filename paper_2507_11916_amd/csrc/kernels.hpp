@@ -8,12 +8,13 @@ namespace hb {
 
 struct GatherLaunch {
     int domain;             // 0 3x3, 1 4x4, 2 cube
-    int prec;               // 0 fp32 table -> fp32, 1 bf16 -> bf16, 2 bf16 -> fp8
+    int prec;               // output type: 0 fp32, 1 bf16, 2 fp8
     const void* packed;     // device, packed states
     const int32_t* n_dev;   // device state count or null
     int n_host;
     int m_rows;             // rows written (>= n, padded rows are zero)
-    const void* table;      // [t_rows][N] layer-1 table (fp32 or bf16)
+    const void* table;      // [t_rows][N] layer-1 table
+    int table_f32;          // 1: float32 table, 0: bfloat16 table
     int t_rows;             // table rows (P * S)
     const float* bias;      // [N]
     int N;                  // padded width (multiple of 64)

@@ -181,17 +181,13 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
             const int p = 9 * f + 4;
             for (int j = 0; j < m->N1; j++) bias1[j] += wq(T[0][((size_t)p * 6 + f) * m->N1 + j]);
         }
-    hb_status st;
-    if (prec == 0) {
-        st = dev_upload(m.get(), tab.data(), tab.size() * 4, &m->l1_table);
-    } else {
-        std::vector<uint16_t> tb(tab.size());
-        for (size_t i = 0; i < tab.size(); i++) tb[i] = bf16_bits(tab[i]);
-        st = dev_upload(m.get(), tb.data(), tb.size() * 2, &m->l1_table);
-    }
+    // The table is kept in float32 at every precision (at BF16/FP8 holding the
+    // bfloat16-rounded values, which float32 represents exactly): the gather
+    // is bound by vector ALU work, and float32 entries need no conversion.
+    hb_status st = dev_upload(m.get(), tab.data(), tab.size() * 4, &m->l1_table);
     if (st != HB_OK) return st;
     if ((st = dev_upload(m.get(), bias1.data(), bias1.size() * 4, (void**)&m->l1_bias)) != HB_OK) return st;
-    m->weight_bytes += (int64_t)tab.size() * (prec == 0 ? 4 : 2);
+    m->weight_bytes += (int64_t)tab.size() * 4;
     m->flops = (double)P_eff * m->N1;  // gathered adds
 
     // Matrix layers: dense layers 2..n_dense, then residual pairs.
@@ -383,6 +379,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     G.n_host = n;
     G.m_rows = rows;
     G.table = m->l1_table;
+    G.table_f32 = 1;
     G.t_rows = m->table_rows;
     G.bias = m->l1_bias;
     G.N = m->N1_pad;

@@ -152,6 +152,7 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     G.n_host = n;
     G.m_rows = Me;
     G.table = tr->l1_table;
+    G.table_f32 = t == 0;
     G.t_rows = tr->rows1;
     G.bias = tr->l1_bias;
     G.N = tr->N1_pad;
