@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true", help="only one precision's timed loop (for profilers)")
     ap.add_argument("--prec", default="f32", choices=["f32", "bf16", "fp8"], help="precision of --profile-only")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the benchmark line: evals/s and fixed-tree search nodes/s of the 15-puzzle "
+                         "net at several hidden widths (same depth) and each precision; prints its own JSON line")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --profile-only: also copy a buffer of this many MiB five times (the known-size "
                          "copy kernel that scales hardware byte counters)")
@@ -125,6 +128,10 @@ def main():
 
     hb.lib().hb_model_profile.argtypes = [C.c_void_p, C.c_int]
     hb.lib().hb_model_profile_read.argtypes = [C.c_void_p, C.POINTER(Profile)]
+
+    if args.size_sweep:
+        size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp)
+        return
 
     results = {}
     calib = synth.stp_walks(4, synth.throughput_seeds(4096, 4242), lengths=200)
@@ -343,6 +350,43 @@ def main():
         "training": training,
     }
     print(json.dumps(line))
+
+
+def size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp):
+    """Model-size analysis: the 15-puzzle residual architecture at hidden widths
+    96 .. 2000 (FP32 sizes 0.3 .. 82 MB), evaluations/s at batch B and
+    fixed-tree Batch IDA* nodes/s (same tree at every width and precision)."""
+    calib = synth.stp_walks(4, synth.throughput_seeds(4096, 4242), lengths=200)
+    d_calib = torch.from_numpy(hb.hb_encode(hb.HB_STP4, calib)).cuda()
+    start = synth.stp4_instances(1)[0]
+    threads = min(32, max(4, len(os.sched_getaffinity(0))))
+    rows = []
+    for width in (96, 320, 800, 1000, 2000):
+        spec = synth.widened("stp4_res", width)
+        path = os.path.join(tmp, f"stp4_w{width}.hbw")
+        synth.write_weights(path, "stp4_res", spec=spec, **netcfg.DEFAULTS["stp4_res"])
+        params = sum(r * c for _, r, c in synth.net_tensor_shapes(spec["n_in"], spec["dims"], spec["n_res"], 1))
+        row = {"width": width, "params": params, "fp32_mb": params * 4 / 1e6}
+        for name, prec in (("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)):
+            m = hb.Model(path, prec=prec, combine_md=True, max_batch=max(B, 16384))
+            if prec == hb.HB_FP8_E4M3:
+                m.calibrate(d_calib)
+            m.tune(d_packed)
+            ms = timed_loop(m, max(20, args.steps // 4), args.warmup)
+            tflops = m.flops_per_eval * B / (ms * 1e-3) / 1e12
+            p = hb.default_params(batch_size=8000, work_num=8, node_limit=300_000, time_limit_s=20.0)
+            r = hb.cbdfs_solve(hb.HB_STP4, start, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_MD,
+                               threads=threads, params=p, raise_on_error=False)
+            row[name] = {"evals_per_s": B / ms * 1e3, "us_per_batch": ms * 1e3, "tflops": tflops,
+                         "mfma_frac": tflops / PEAK_TFLOPS[name], "tile": m.tile_for(B),
+                         "search_nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]),
+                         "search_generated": r["generated"], "search_mean_batch": r["mean_batch"]}
+            log(f"[sweep] width {width} {name}: {B / ms * 1e3:.3e} evals/s ({tflops:.0f} TFLOP/s), search "
+                f"{row[name]['search_nodes_per_s']:.3e} nodes/s")
+            m.close()
+        rows.append(row)
+    print(json.dumps({"metric": "model-size sweep: evals/s at batch %d and fixed-tree Batch IDA* nodes/s" % B,
+                      "batch": B, "threads": threads, "rows": rows}))
 
 
 if __name__ == "__main__":

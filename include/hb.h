@@ -126,7 +126,8 @@ typedef struct {
     float q;             /* classifier quantile, e.g. 0.99 */
     float offset;        /* regression offset, e.g. 2.2 */
     int combine_md;      /* sliding tile: 1 h = min(h, Manhattan) (guard for untrained nets);
-                            2 h = max(h, Manhattan) (learned heuristic with Manhattan fallback) */
+                            2 h = max(h, Manhattan) (learned heuristic with Manhattan fallback);
+                            3 h = Manhattan + h (Manhattan distance plus a learned non-negative residual) */
     int max_batch;       /* largest n per launch; larger calls are split (0: 16384) */
 } hb_model_opts;
 
@@ -143,6 +144,21 @@ typedef struct hb_model hb_model;
  * opts NULL = {FP32, device 0, FLOOR, 0.99, 0, 0, 16384}. */
 hb_status hb_model_load(const char* weights_path, const hb_model_opts* opts, hb_model** out);
 void hb_model_free(hb_model* m); /* NULL-safe; synchronises the model's device work first */
+
+/* Ensemble heuristics: k (1..4) regression networks with the same architecture
+ * (weight files as for hb_model_load) evaluated as one model.  The related work
+ * makes a learned heuristic admissible by taking the minimum over an ensemble;
+ * the sliding-tile heuristic of the experiments adds learned residuals to
+ * Manhattan distance.  Member outputs y_i are combined as
+ * HB_ENSEMBLE_MIN: y = min_i y_i, or HB_ENSEMBLE_SUM: y = y_0 + y_1 + ... (in
+ * member order), then opts' output rule applies to y (offset, floor or round,
+ * combine_md; combine_md = 3 gives Manhattan plus the summed residuals).  On
+ * the GPU the members' layer-1 tables sit side by side in one gather, and each
+ * matrix layer is one grouped launch over all members.  The model is used
+ * like any other (hb_eval_batch, cbdfs_solve, calibration, autotuning). */
+typedef enum { HB_ENSEMBLE_MIN = 0, HB_ENSEMBLE_SUM = 1 } hb_ensemble_rule;
+hb_status hb_model_load_ensemble(const char* const* weights_paths, int k, hb_ensemble_rule rule,
+                                 const hb_model_opts* opts, hb_model** out);
 
 typedef struct {
     int domain, n_in, n_dense, n_res, n_out, head_kind, n_act, prec;

@@ -255,6 +255,48 @@ class Net:
         return out
 
 
+# ----------------------------------------------------------------- ensembles
+ENS_MIN, ENS_SUM = 0, 1
+
+
+def ensemble_forward(nets, states, rule, mode=0, act_scales=None):
+    """Output of an ensemble of one-output regression networks: the minimum of
+    the members' outputs (the related work's admissibility device) or their sum
+    in member order (learned residuals added together, as in the experiments'
+    sliding-tile heuristic).  act_scales: one FP8 scale vector per member."""
+    ys = [net.forward(states, mode=mode, act_scale=None if act_scales is None else act_scales[i])[:, 0]
+          for i, net in enumerate(nets)]
+    out = ys[0].copy()
+    for y in ys[1:]:
+        out = np.minimum(out, y) if rule == ENS_MIN else out + y
+    return out
+
+
+def h_regression(y, md=None, combine=0, offset=0.0, mode=0):
+    """Regression output rule, written out: v = floor(y - offset) (mode 1:
+    round half to even), clamped at 0 and at 1e9; then with Manhattan distance md:
+    combine 1 min(v, md), 2 max(v, md), 3 md + v.  A non-finite y gives md (0
+    without it)."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.zeros(y.shape[0], dtype=np.int64)
+    for i, yi in enumerate(y):
+        c = None if md is None or combine == 0 else int(md[i])
+        if not np.isfinite(yi):
+            out[i] = c if c is not None else 0
+            continue
+        t = yi - offset
+        r = np.floor(t)
+        if mode == 1:
+            frac = t - r
+            if frac > 0.5 or (frac == 0.5 and r % 2 != 0):
+                r += 1
+        v = int(min(max(r, 0.0), 1e9))
+        if c is not None:
+            v = min(v, c) if combine == 1 else max(v, c) if combine == 2 else c + min(v, int(1e9) - c)
+        out[i] = v
+    return out
+
+
 def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """In-place Adam step on float64 arrays."""
     for a in (w, g, m, v):

@@ -24,6 +24,7 @@ HB_OUT_REG_FLOOR, HB_OUT_REG_ROUND, HB_OUT_REG_REAL, HB_OUT_CLS_QUANTILE, HB_OUT
 HB_IDA, HB_BTS = 0, 1
 HB_H_NN, HB_H_MIN_NN_CLASSIC, HB_H_FIXED_TREE, HB_H_CLASSIC, HB_H_CLASSIC_BATCHED = 0, 1, 2, 3, 4
 HB_CLASSIC_ZERO, HB_CLASSIC_MD, HB_CLASSIC_PDB = 0, 1, 2
+HB_ENSEMBLE_MIN, HB_ENSEMBLE_SUM = 0, 1
 
 
 class HBError(RuntimeError):
@@ -105,6 +106,8 @@ def lib():
             "hb_pdb_lookup": ([vp, vp, i64, vp], C.c_int),
             "hb_pdb_free": ([vp], None),
             "hb_model_load": ([C.c_char_p, C.POINTER(ModelOpts), C.POINTER(vp)], C.c_int),
+            "hb_model_load_ensemble": ([C.POINTER(C.c_char_p), C.c_int, C.c_int, C.POINTER(ModelOpts), C.POINTER(vp)],
+                                       C.c_int),
             "hb_model_free": ([vp], None),
             "hb_model_get_info": ([vp, C.POINTER(ModelInfo)], C.c_int),
             "hb_model_calibrate": ([vp, vp, i64], C.c_int),
@@ -226,10 +229,17 @@ class Model:
     """A network resident on one GPU (hb_model)."""
 
     def __init__(self, path, prec=HB_FP32, out=HB_OUT_REG_FLOOR, q=0.99, offset=0.0, combine_md=False,
-                 max_batch=16384, device=0):
+                 max_batch=16384, device=0, ensemble_rule=HB_ENSEMBLE_MIN):
+        """path: a weight file, or a list of 1-4 weight files of one architecture
+        (an ensemble combined by ensemble_rule).  combine_md: 0/False none, 1/True
+        min, 2 max, 3 plus (Manhattan distance)."""
         o = ModelOpts(prec, device, out, q, offset, int(combine_md), max_batch)
         h = C.c_void_p()
-        _check(lib().hb_model_load(path.encode(), C.byref(o), C.byref(h)))
+        if isinstance(path, (list, tuple)):
+            arr = (C.c_char_p * len(path))(*[os.fsencode(p) for p in path])
+            _check(lib().hb_model_load_ensemble(arr, len(path), ensemble_rule, C.byref(o), C.byref(h)))
+        else:
+            _check(lib().hb_model_load(os.fsencode(path), C.byref(o), C.byref(h)))
         self.handle = h
         self.opts = o
         info = ModelInfo()

@@ -136,6 +136,24 @@ hb_status hb_model_load(const char* weights_path, const hb_model_opts* opts, hb_
     }
 }
 
+hb_status hb_model_load_ensemble(const char* const* weights_paths, int k, hb_ensemble_rule rule,
+                                 const hb_model_opts* opts, hb_model** out) {
+    if (!weights_paths || !out || k < 1) return fail(HB_E_INVAL, "null paths or output, or k < 1");
+    hb_model_opts o{HB_FP32, 0, HB_OUT_REG_FLOOR, 0.99f, 0.f, 0, 16384};
+    if (opts) o = *opts;
+    if (o.max_batch < 0 || o.max_batch > (1 << 22)) return fail(HB_E_INVAL, "max_batch out of range");
+    std::vector<std::string> paths;
+    for (int i = 0; i < k; i++) {
+        if (!weights_paths[i]) return fail(HB_E_INVAL, "null path %d", i);
+        paths.emplace_back(weights_paths[i]);
+    }
+    try {
+        return model_load_members(paths, (int)rule, o, out);
+    } catch (const std::bad_alloc&) {
+        return fail(HB_E_NOMEM, "host allocation while loading the model");
+    }
+}
+
 void hb_model_free(hb_model* m) { model_free(m); }
 
 hb_status hb_model_get_info(const hb_model* m, hb_model_info* out) {

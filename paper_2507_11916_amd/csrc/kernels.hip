@@ -193,7 +193,13 @@ struct GemmArgs {
     int relu;
     int persistent;          // loop over tiles with a grid stride
     const uint8_t* Mk;       // mask (C's type and layout) or null: zero where Mk <= 0
+    int group_n, group_k;    // grouped product: C columns of group g read A columns from g * group_k
 };
+
+// Column offset in A of the group that output column n0 belongs to.
+__device__ __forceinline__ size_t group_a_col(const GemmArgs& g, int n0) {
+    return g.group_n ? (size_t)(n0 / g.group_n) * g.group_k : 0;
+}
 
 template <int PREC>
 struct Ty {
@@ -345,7 +351,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
         const int tm = t / n_tiles, tn = t % n_tiles;
         const int m0 = tm * BM, n0 = tn * BN;
-        const uint8_t* Ag = g.A + (size_t)m0 * g.lda * EB;
+        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
         const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
 
         floatx16 acc[TI][TJ];
@@ -458,7 +464,7 @@ __global__ __launch_bounds__(256) void gemm_ring_kernel(GemmArgs g) {
     for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
         const int tm = t / n_tiles, tn = t % n_tiles;
         const int m0 = tm * BM, n0 = tn * BN;
-        const uint8_t* Ag = g.A + (size_t)m0 * g.lda * EB;
+        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
         const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
 
         floatx16 acc[TI][TJ];
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
     const int tm = blockIdx.x / n_tiles, tn = blockIdx.x % n_tiles;
     if (tm >= m_tiles) return;
     const int m0 = tm * 32, n0 = tn * 32;
-    const uint8_t* Ar = g.A + (size_t)(m0 + r32) * g.lda * EB;
+    const uint8_t* Ar = g.A + ((size_t)(m0 + r32) * g.lda + group_a_col(g, n0)) * EB;
     const uint8_t* Br = g.Bt + (size_t)(n0 + r32) * g.ldb * EB;
     const int ktiles = g.K * EB / 128;
     // Byte offset, inside a 128-byte K stage, of this lane's register slot i.
@@ -621,7 +627,8 @@ __device__ __forceinline__ int head_md(const HeadArgs& h, int r) {
 }
 
 // Regression output rule: h = floor / round-half-even of y - offset, clamped
-// at 0, then min / max with Manhattan distance; non-finite -> MD or 0.
+// at 0, then combined with Manhattan distance (min, max, or MD plus the
+// clamped value); non-finite -> MD or 0.
 __device__ __forceinline__ void regression_rule(const HeadArgs& h, int r, float y, int md) {
     const float v = y - h.offset;
     int hv;
@@ -630,7 +637,7 @@ __device__ __forceinline__ void regression_rule(const HeadArgs& h, int r, float 
     } else {
         const float f = h.mode == 1 ? rintf(v) : floorf(v);
         hv = f < 0.f ? 0 : f > 1e9f ? 1000000000 : (int)f;
-        if (md >= 0) hv = h.combine_md == 2 ? max(hv, md) : min(hv, md);
+        if (md >= 0) hv = h.combine_md == 3 ? min(hv, 1000000000 - md) + md : h.combine_md == 2 ? max(hv, md) : min(hv, md);
     }
     if (h.raw) h.raw[r] = v;
     h.h_out[r] = hv;
@@ -638,22 +645,29 @@ __device__ __forceinline__ void regression_rule(const HeadArgs& h, int r, float 
 
 // Regression head: 16 lanes per state (4 states per wave, 16 per block), each
 // lane summing x[k] * w[k] over 16-byte slices k = 16-lane stride apart, then
-// a 16-lane butterfly; the first lane of each group applies the rule.
+// a 16-lane butterfly; the first lane of each group applies the rule.  An
+// ensemble's x holds the members' last activations side by side (K values
+// each) and w their output weights; member outputs y_i = w_i . x_i + b_i are
+// combined as min_i y_i or y_0 + y_1 + ... before the rule.
+constexpr int kMaxMembers = 4;
+
 template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/>
 __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
     constexpr int CH = IN == 0 ? 4 : IN == 1 ? 8 : 16;  // elements per 16-byte load of x
+    constexpr int XB = IN == 0 ? 4 : IN == 1 ? 2 : 1;
     const int j = threadIdx.x & 15;
     const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
     const int r = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = r < n;
     // the record for the Manhattan rule is fetched before the dot product
     const uint64_t rec = live && j == 0 && h.combine_md && h.domain < 2 ? reinterpret_cast<const uint64_t*>(h.packed)[r] : 0;
-    float y = 0.f;
+    float y[kMaxMembers] = {0.f, 0.f, 0.f, 0.f};
     if (live) {
-        const uint8_t* xrow = reinterpret_cast<const uint8_t*>(h.X) + (size_t)r * h.ldx * (IN == 0 ? 4 : IN == 1 ? 2 : 1);
-        for (int k = j * CH; k < h.K; k += 16 * CH) {
+        const uint8_t* xrow = reinterpret_cast<const uint8_t*>(h.X) + (size_t)r * h.ldx * XB;
+        const int Ktot = h.K * h.members;
+        for (int k = j * CH; k < Ktot; k += 16 * CH) {
             float x[CH], w[CH];
-            const uint4 xv = *reinterpret_cast<const uint4*>(xrow + (size_t)k * (IN == 0 ? 4 : IN == 1 ? 2 : 1));
+            const uint4 xv = *reinterpret_cast<const uint4*>(xrow + (size_t)k * XB);
             const uint32_t xu[4] = {xv.x, xv.y, xv.z, xv.w};
             if (IN == 0) {
                 _Pragma("unroll") for (int e = 0; e < 4; e++) x[e] = __uint_as_float(xu[e]);
@@ -677,14 +691,25 @@ __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
                     }
                 }
             }
-            _Pragma("unroll") for (int e = 0; e < CH; e++) y += x[e] * w[e];
+            float d = 0.f;
+            _Pragma("unroll") for (int e = 0; e < CH; e++) d += x[e] * w[e];
+            const int member = k / h.K;  // a slice never straddles members (K is a multiple of 128)
+            _Pragma("unroll") for (int i = 0; i < kMaxMembers; i++)
+                if (i == member) y[i] += d;
         }
     }
-    _Pragma("unroll") for (int s = 8; s >= 1; s >>= 1) y += __shfl_xor(y, s, 64);
+    _Pragma("unroll") for (int i = 0; i < kMaxMembers; i++)
+        _Pragma("unroll") for (int s = 8; s >= 1; s >>= 1) y[i] += __shfl_xor(y[i], s, 64);
     if (!live || j != 0) return;
+    float yc = y[0] + h.b[0];
+    for (int i = 1; i < h.members && i < kMaxMembers; i++) {
+        const float yi = y[i] + h.b[i];
+        // minimum that keeps a NaN (the rule then falls back to Manhattan / 0)
+        yc = h.ens_rule != 0 ? yc + yi : (yc != yc || yi != yi) ? yc + yi : fminf(yc, yi);
+    }
     int md = -1;
     if (h.combine_md && h.domain < 2) md = h.domain == 0 ? manhattan_packed<3>(rec) : manhattan_packed<4>(rec);
-    regression_rule(h, r, y + h.b[0], md);
+    regression_rule(h, r, yc, md);
 }
 
 // Classifier head: one wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o]
@@ -818,6 +843,7 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;
@@ -837,6 +863,7 @@ static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
     g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
     hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
@@ -850,6 +877,7 @@ static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
     g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;

@@ -41,6 +41,9 @@ struct GemmLaunch {
     int persistent_grid;    // > 0: at most this many blocks, striding over tiles
     int out_type = -1;      // type of C/R/Mk: -1 same as prec; 0 f32 (weight gradients from bf16)
     const void* Mk = nullptr;  // zero the result where this tensor (C's layout) is <= 0
+    // Grouped product (ensembles): columns [g*group_n, (g+1)*group_n) of C use
+    // A's columns [g*group_k, (g+1)*group_k).  0: one group.
+    int group_n = 0, group_k = 0;
 };
 
 struct HeadArgs {
@@ -57,7 +60,9 @@ struct HeadArgs {
     int domain;
     int mode;               // hb_out_mode
     float q, offset;
-    int combine_md;
+    int combine_md;         // 0 none, 1 min, 2 max, 3 plus (with Manhattan distance)
+    int members;            // ensemble members (regression): x holds members * K values
+    int ens_rule;           // 0 min, 1 sum of the members' outputs
     int32_t* h_out;
     float* raw;             // nullable
 };

@@ -132,14 +132,36 @@ int choose_tile(const hb_model* m, int64_t M, int N_pad) {
 }
 
 hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
-    NetSpec spec;
-    const char* why = "";
-    if (!read_weight_file(path, &spec, &why)) return fail(HB_E_INVAL, "%s: %s", path, why);
+    return model_load_members(std::vector<std::string>{path}, 0, o, out);
+}
+
+// One network, or an ensemble of networks with the same architecture fused
+// into one model: layer-1 tables side by side, every matrix layer one grouped
+// product over the members (weights stacked), the members' outputs combined in
+// the head.
+hb_status model_load_members(const std::vector<std::string>& paths, int rule, const hb_model_opts& o, hb_model** out) {
+    const int k = (int)paths.size();
+    if (k < 1 || k > 4) return fail(HB_E_INVAL, "an ensemble has 1 to 4 members");
+    if (rule < 0 || rule > 1) return fail(HB_E_INVAL, "unknown ensemble rule %d", rule);
+    std::vector<NetSpec> specs(k);
+    for (int i = 0; i < k; i++) {
+        const char* why = "";
+        if (!read_weight_file(paths[i].c_str(), &specs[i], &why)) return fail(HB_E_INVAL, "%s: %s", paths[i].c_str(), why);
+    }
+    const NetSpec& spec = specs[0];
+    for (int i = 1; i < k; i++) {
+        const NetSpec& t = specs[i];
+        if (t.domain != spec.domain || t.n_in != spec.n_in || t.dims != spec.dims || t.n_res != spec.n_res ||
+            t.n_out != spec.n_out || t.head_kind != spec.head_kind)
+            return fail(HB_E_INVAL, "ensemble member %d has another architecture than member 0", i);
+    }
+    if (k > 1 && (spec.head_kind != 0 || spec.n_out != 1)) return fail(HB_E_INVAL, "ensembles are of regression networks");
     if (o.prec < HB_FP32 || o.prec > HB_FP8_E4M3) return fail(HB_E_INVAL, "unknown precision %d", (int)o.prec);
     if (o.out < HB_OUT_REG_FLOOR || o.out > HB_OUT_CLS_ARGMAX) return fail(HB_E_INVAL, "unknown output mode");
     const bool cls_mode = o.out >= HB_OUT_CLS_QUANTILE;
     if (cls_mode != (spec.head_kind == 1)) return fail(HB_E_INVAL, "output mode does not match the network head");
     if (!cls_mode && spec.n_out != 1) return fail(HB_E_INVAL, "a regression head has one output");
+    if (o.combine_md < 0 || o.combine_md > 3) return fail(HB_E_INVAL, "combine_md must be 0..3");
     if (o.combine_md && spec.domain == 2) return fail(HB_E_INVAL, "Manhattan distance applies to sliding tiles only");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(HB_E_DEVICE, "no HIP device available");
@@ -153,10 +175,12 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
     m->opts = o;
     if (m->opts.max_batch <= 0) m->opts.max_batch = 16384;
     m->spec = spec;
-    m->path = path;
+    m->path = paths[0];
+    m->paths = paths;
+    m->members = k;
+    m->ens_rule = rule;
     const int prec = (int)o.prec;
     const int eb = prec == 0 ? 4 : prec == 1 ? 2 : 1;
-    const auto& T = spec.tensors;
     auto pad = [](int v) { return (int)round_up(v, 128); };
 
     // Layer 1: table of gathered rows (cube: non-centre stickers only, the
@@ -168,19 +192,25 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
     const int P_eff = spec.domain == 2 ? 48 : m->P;
     m->table_rows = P_eff * m->S;
     auto wq = [&](float v) { return prec == 0 ? v : bf16_val(v); };  // layer-1 / head weight rounding
-    std::vector<float> bias1(m->N1_pad, 0.f);
-    for (int j = 0; j < m->N1; j++) bias1[j] = T[1][j];
-    std::vector<float> tab((size_t)m->table_rows * m->N1_pad, 0.f);
-    for (int q = 0; q < P_eff; q++) {
-        const int p = spec.domain == 2 ? q + q / 8 + (q % 8 >= 4 ? 1 : 0) : q;
-        for (int s = 0; s < m->S; s++)
-            for (int j = 0; j < m->N1; j++) tab[((size_t)q * m->S + s) * m->N1_pad + j] = wq(T[0][((size_t)p * m->S + s) * m->N1 + j]);
-    }
-    if (spec.domain == 2)
-        for (int f = 0; f < 6; f++) {
-            const int p = 9 * f + 4;
-            for (int j = 0; j < m->N1; j++) bias1[j] += wq(T[0][((size_t)p * 6 + f) * m->N1 + j]);
+    const int W1 = k * m->N1_pad;  // member i owns columns [i * N1_pad, i * N1_pad + N1)
+    std::vector<float> bias1(W1, 0.f);
+    std::vector<float> tab((size_t)m->table_rows * W1, 0.f);
+    for (int i = 0; i < k; i++) {
+        const auto& T = specs[i].tensors;
+        const int c0 = i * m->N1_pad;
+        for (int j = 0; j < m->N1; j++) bias1[c0 + j] = T[1][j];
+        for (int q = 0; q < P_eff; q++) {
+            const int p = spec.domain == 2 ? q + q / 8 + (q % 8 >= 4 ? 1 : 0) : q;
+            for (int s = 0; s < m->S; s++)
+                for (int j = 0; j < m->N1; j++)
+                    tab[((size_t)q * m->S + s) * W1 + c0 + j] = wq(T[0][((size_t)p * m->S + s) * m->N1 + j]);
         }
+        if (spec.domain == 2)
+            for (int f = 0; f < 6; f++) {
+                const int p = 9 * f + 4;
+                for (int j = 0; j < m->N1; j++) bias1[c0 + j] += wq(T[0][((size_t)p * 6 + f) * m->N1 + j]);
+            }
+    }
     // The table is kept in float32 at every precision (at BF16/FP8 holding the
     // bfloat16-rounded values, which float32 represents exactly): the gather
     // is bound by vector ALU work, and float32 entries need no conversion.
@@ -188,73 +218,88 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
     if (st != HB_OK) return st;
     if ((st = dev_upload(m.get(), bias1.data(), bias1.size() * 4, (void**)&m->l1_bias)) != HB_OK) return st;
     m->weight_bytes += (int64_t)tab.size() * 4;
-    m->flops = (double)P_eff * m->N1;  // gathered adds
+    m->flops = (double)k * P_eff * m->N1;  // gathered adds
 
     // Matrix layers: dense layers 2..n_dense, then residual pairs.
     const int n_dense = (int)spec.dims.size();
     m->n_act = n_dense + 2 * spec.n_res;
     int ti = 2, act = 0;
-    int width_cap = m->N1_pad;
-    auto add_layer = [&](const std::vector<float>& W, const std::vector<float>& b, int K, int N, int in_act, int out_act,
-                         int res_act) -> hb_status {
+    int width_cap = W1;
+    // Tensor `t` of every member as one matrix layer: member i's output
+    // columns are rows [i * N_pad, (i + 1) * N_pad) of Wt.
+    auto add_layer = [&](int t, int K, int N, int in_act, int out_act, int res_act) -> hb_status {
         MatLayer L;
         L.K = K; L.N = N; L.K_pad = pad(K); L.N_pad = pad(N);
         L.in_act = in_act; L.out_act = out_act; L.res_act = res_act;
-        std::vector<float> bp(L.N_pad, 0.f);
-        for (int j = 0; j < N; j++) bp[j] = b[j];
+        L.groups = k;
+        const int NT = k * L.N_pad;
+        std::vector<float> bp(NT, 0.f);
+        for (int i = 0; i < k; i++)
+            for (int j = 0; j < N; j++) bp[i * L.N_pad + j] = specs[i].tensors[t + 1][j];
         hb_status s2 = dev_upload(m.get(), bp.data(), bp.size() * 4, (void**)&L.bias);
         if (s2 != HB_OK) return s2;
-        const size_t cnt = (size_t)L.N_pad * L.K_pad;
+        const size_t cnt = (size_t)NT * L.K_pad;
+        auto w_at = [&](int i, int kk, int n) { return specs[i].tensors[t][(size_t)kk * N + n]; };
         if (prec == 0) {
             std::vector<float> wt(cnt, 0.f);
-            for (int k = 0; k < K; k++)
-                for (int n = 0; n < N; n++) wt[(size_t)n * L.K_pad + k] = W[(size_t)k * N + n];
+            for (int i = 0; i < k; i++)
+                for (int kk = 0; kk < K; kk++)
+                    for (int n = 0; n < N; n++) wt[(size_t)(i * L.N_pad + n) * L.K_pad + kk] = w_at(i, kk, n);
             s2 = dev_upload(m.get(), wt.data(), cnt * 4, &L.Wt);
         } else if (prec == 1) {
             std::vector<uint16_t> wt(cnt, 0);
-            for (int k = 0; k < K; k++)
-                for (int n = 0; n < N; n++) wt[(size_t)n * L.K_pad + k] = bf16_bits(W[(size_t)k * N + n]);
+            for (int i = 0; i < k; i++)
+                for (int kk = 0; kk < K; kk++)
+                    for (int n = 0; n < N; n++) wt[(size_t)(i * L.N_pad + n) * L.K_pad + kk] = bf16_bits(w_at(i, kk, n));
             s2 = dev_upload(m.get(), wt.data(), cnt * 2, &L.Wt);
         } else {
             std::vector<uint8_t> wt(cnt, 0);
-            std::vector<float> cs(L.N_pad, 0.f);
-            for (int n = 0; n < N; n++) {
-                float mx = 0.f;
-                for (int k = 0; k < K; k++) mx = std::max(mx, std::fabs(W[(size_t)k * N + n]));
-                const float s = mx / 448.f;
-                cs[n] = s;
-                if (s > 0.f)
-                    for (int k = 0; k < K; k++) wt[(size_t)n * L.K_pad + k] = e4m3_bits(W[(size_t)k * N + n] / s);
-            }
+            std::vector<float> cs(NT, 0.f);
+            for (int i = 0; i < k; i++)
+                for (int n = 0; n < N; n++) {
+                    float mx = 0.f;
+                    for (int kk = 0; kk < K; kk++) mx = std::max(mx, std::fabs(w_at(i, kk, n)));
+                    const float s = mx / 448.f;
+                    cs[i * L.N_pad + n] = s;
+                    if (s > 0.f)
+                        for (int kk = 0; kk < K; kk++)
+                            wt[(size_t)(i * L.N_pad + n) * L.K_pad + kk] = e4m3_bits(w_at(i, kk, n) / s);
+                }
             s2 = dev_upload(m.get(), wt.data(), cnt, &L.Wt);
             if (s2 == HB_OK) s2 = dev_upload(m.get(), cs.data(), cs.size() * 4, (void**)&L.colscale);
         }
         if (s2 != HB_OK) return s2;
         m->weight_bytes += (int64_t)cnt * eb;
-        m->flops += 2.0 * K * N;
-        width_cap = std::max(width_cap, std::max(L.K_pad, L.N_pad));
+        m->flops += 2.0 * k * K * N;
+        width_cap = std::max(width_cap, k * std::max(L.K_pad, L.N_pad));
         m->layers.push_back(L);
         return HB_OK;
     };
     for (int i = 1; i < n_dense; i++) {
-        if ((st = add_layer(T[ti], T[ti + 1], spec.dims[i - 1], spec.dims[i], act, act + 1, -1)) != HB_OK) return st;
+        if ((st = add_layer(ti, spec.dims[i - 1], spec.dims[i], act, act + 1, -1)) != HB_OK) return st;
         ti += 2;
         act++;
     }
     const int H = spec.dims.back();
     for (int r = 0; r < spec.n_res; r++) {
         const int x_act = act;
-        if ((st = add_layer(T[ti], T[ti + 1], H, H, x_act, n_dense + 2 * r, -1)) != HB_OK) return st;
-        if ((st = add_layer(T[ti + 2], T[ti + 3], H, H, n_dense + 2 * r, n_dense + 2 * r + 1, x_act)) != HB_OK) return st;
+        if ((st = add_layer(ti, H, H, x_act, n_dense + 2 * r, -1)) != HB_OK) return st;
+        if ((st = add_layer(ti + 2, H, H, n_dense + 2 * r, n_dense + 2 * r + 1, x_act)) != HB_OK) return st;
         m->layers.back().res_in_place = true;
         ti += 4;
         act = n_dense + 2 * r + 1;
     }
-    // Head: [n_out][K_pad], float32 or bfloat16.
+    // Head: [n_out][K_pad] per member (members side by side), float32 or bfloat16.
     m->K_last_pad = pad(H);
-    std::vector<float> hw((size_t)spec.n_out * m->K_last_pad, 0.f);
-    for (int k = 0; k < H; k++)
-        for (int oo = 0; oo < spec.n_out; oo++) hw[(size_t)oo * m->K_last_pad + k] = wq(T[ti][(size_t)k * spec.n_out + oo]);
+    std::vector<float> hw((size_t)k * spec.n_out * m->K_last_pad, 0.f);
+    std::vector<float> hbias((size_t)k * spec.n_out, 0.f);
+    for (int i = 0; i < k; i++) {
+        const auto& T = specs[i].tensors;
+        for (int kk = 0; kk < H; kk++)
+            for (int oo = 0; oo < spec.n_out; oo++)
+                hw[((size_t)i * spec.n_out + oo) * m->K_last_pad + kk] = wq(T[ti][(size_t)kk * spec.n_out + oo]);
+        for (int oo = 0; oo < spec.n_out; oo++) hbias[(size_t)i * spec.n_out + oo] = T[ti + 1][oo];
+    }
     if (prec == 0) {
         st = dev_upload(m.get(), hw.data(), hw.size() * 4, &m->head_W);
     } else {
@@ -263,9 +308,9 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out) {
         st = dev_upload(m.get(), hb16.data(), hb16.size() * 2, &m->head_W);
     }
     if (st != HB_OK) return st;
-    if ((st = dev_upload(m.get(), T[ti + 1].data(), T[ti + 1].size() * 4, (void**)&m->head_b)) != HB_OK) return st;
+    if ((st = dev_upload(m.get(), hbias.data(), hbias.size() * 4, (void**)&m->head_b)) != HB_OK) return st;
     m->weight_bytes += (int64_t)hw.size() * (prec == 0 ? 4 : 2);
-    m->flops += 2.0 * H * spec.n_out;
+    m->flops += 2.0 * k * H * spec.n_out;
     m->width_cap = width_cap;
     m->act_scale.assign(m->n_act, 1.f);
     m->calibrated = prec != 2;
@@ -382,7 +427,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     G.table_f32 = 1;
     G.t_rows = m->table_rows;
     G.bias = m->l1_bias;
-    G.N = m->N1_pad;
+    G.N = m->members * m->N1_pad;
     G.ld_out = m->width_cap;
     G.out = X;
     G.out_inv_scale = 1.f / m->act_scale[0];
@@ -390,7 +435,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "no layer-1 kernel for this domain/precision");
     HB_HIP(hipGetLastError());
     prof_end(m, pi, 0.0, s);
-    if (cap) launch_absmax((const float*)X, n, m->N1, m->width_cap, w->absmax + 0, s);
+    if (cap) launch_absmax((const float*)X, n, m->members * m->N1_pad, m->width_cap, w->absmax + 0, s);
     // X holds the running activation x, Tb is scratch.  A dense layer writes
     // Tb and the two swap roles; the first layer of a residual block writes
     // t into Tb and keeps x in X; the second reads t, adds x and overwrites x
@@ -409,8 +454,9 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         g.m_dev = d_n;
         g.m_host = n;
         g.m_cap = m_cap;
-        g.N = L.N_pad;
+        g.N = L.N_pad * L.groups;
         g.K = L.K_pad;
+        if (L.groups > 1) { g.group_n = L.N_pad; g.group_k = L.K_pad; }
         g.lda = m->width_cap;
         g.ldb = L.K_pad;
         g.ldc = m->width_cap;
@@ -421,8 +467,8 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         pi = prof_begin(m, 1, s);
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());
-        prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N, s);
-        if (cap) launch_absmax((const float*)g.C, n, L.N, m->width_cap, w->absmax + L.out_act, s);
+        prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N * L.groups, s);
+        if (cap) launch_absmax((const float*)g.C, n, L.N_pad * L.groups, m->width_cap, w->absmax + L.out_act, s);
         if (!L.res_in_place && !res_first) std::swap(X, Tb);
     }
     HeadArgs H{};
@@ -441,6 +487,8 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     H.q = m->opts.q;
     H.offset = m->opts.offset;
     H.combine_md = m->opts.combine_md;
+    H.members = m->members;
+    H.ens_rule = m->ens_rule;
     H.h_out = d_h;
     H.raw = d_raw;
     pi = prof_begin(m, 2, s);
@@ -490,7 +538,7 @@ hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n) {
     hb_model_opts o = m->opts;
     o.prec = HB_FP32;
     hb_model* f = nullptr;
-    hb_status st = model_load(m->path.c_str(), o, &f);
+    hb_status st = model_load_members(m->paths, m->ens_rule, o, &f);
     if (st != HB_OK) return st;
     std::vector<float> mx(f->n_act, 0.f);
     CalibCapture cap{&mx};
@@ -628,7 +676,7 @@ static std::string model_signature(const hb_model* m) {
     std::string sig = "d" + std::to_string(m->spec.domain) + " in" + std::to_string(m->spec.n_in) + " dims";
     for (int d : m->spec.dims) sig += "_" + std::to_string(d);
     sig += " res" + std::to_string(m->spec.n_res) + " out" + std::to_string(m->spec.n_out) + " prec" +
-           std::to_string((int)m->opts.prec);
+           std::to_string((int)m->opts.prec) + " members" + std::to_string(m->members);
     return sig;
 }
 

@@ -20,12 +20,13 @@ struct NetSpec {
 bool read_weight_file(const char* path, NetSpec* out, const char** why);
 
 struct MatLayer {
-    void* Wt = nullptr;         // [N_pad][K_pad] in the operand type
+    void* Wt = nullptr;         // [groups * N_pad][K_pad] in the operand type (ensembles: members stacked)
     float* bias = nullptr;      // [N_pad]
     float* colscale = nullptr;  // [N_pad] fp8 only
     int K = 0, N = 0, K_pad = 0, N_pad = 0;
     int in_act = 0, out_act = 0, res_act = -1;  // activation tensor ids
     bool res_in_place = false;
+    int groups = 1;             // ensemble members evaluated by this layer's one launch
 };
 
 struct Workspace {
@@ -44,8 +45,11 @@ struct CalibCapture {
 struct hb_model {
     int device = 0;
     hb_model_opts opts{};
-    hb::NetSpec spec;
-    std::string path;
+    hb::NetSpec spec;                 // member 0's (all members share the architecture)
+    std::string path;                 // member 0's weight file
+    std::vector<std::string> paths;   // every member's weight file
+    int members = 1;                  // ensemble size
+    int ens_rule = 0;                 // 0 min, 1 sum of the members' outputs
     int P = 0, S = 0, table_rows = 0;
     void* l1_table = nullptr;
     float* l1_bias = nullptr;
@@ -77,6 +81,7 @@ struct hb_model {
 namespace hb {
 
 hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out);
+hb_status model_load_members(const std::vector<std::string>& paths, int rule, const hb_model_opts& o, hb_model** out);
 void model_free(hb_model* m);
 hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n,
                      int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile = -1);

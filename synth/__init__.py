@@ -210,11 +210,20 @@ def net_tensor_shapes(n_in, dims, n_res, n_out):
     return shapes
 
 
-def make_weights(net: str, seed: int, head_bias=0.0, scale=1.0):
+def widened(net: str, width: int) -> dict:
+    """The architecture of `net` with every hidden layer `width` wide (same depth):
+    the model-size sweep varies the width only."""
+    spec = dict(NETS[net])
+    spec["dims"] = [width] * len(spec["dims"])
+    return spec
+
+
+def make_weights(net: str, seed: int, head_bias=0.0, scale=1.0, spec=None):
     """Seeded He-uniform weights U(+-sqrt(6/fan_in)) drawn in double precision
     and rounded to float32; hidden biases zero; output bias `head_bias`.
-    Tensor t uses the splitmix64 stream seeded (seed << 20) + t."""
-    spec = NETS[net]
+    Tensor t uses the splitmix64 stream seeded (seed << 20) + t.  `spec`
+    overrides the architecture of `net` (see widened)."""
+    spec = NETS[net] if spec is None else spec
     tensors = []
     for t, (name, rows, cols) in enumerate(net_tensor_shapes(spec["n_in"], spec["dims"],
                                                               spec["n_res"], spec["n_out"])):
@@ -240,7 +249,7 @@ def make_weights(net: str, seed: int, head_bias=0.0, scale=1.0):
     return spec, tensors
 
 
-def write_weights(path: str, net: str, seed: int, head_bias=0.0, scale=1.0) -> dict:
+def write_weights(path: str, net: str, seed: int, head_bias=0.0, scale=1.0, spec=None) -> dict:
     """Write the binary weight file.
 
     Layout (little-endian): u32 magic "HBW1", u32 version=1, u32 domain,
@@ -248,7 +257,7 @@ def write_weights(path: str, net: str, seed: int, head_bias=0.0, scale=1.0) -> d
     u32 head_kind (0 regression, 1 classifier), then float32 tensors in the
     order of net_tensor_shapes: W [in][out] row-major, then b [out].
     """
-    spec, tensors = make_weights(net, seed, head_bias, scale)
+    spec, tensors = make_weights(net, seed, head_bias, scale, spec)
     with open(path, "wb") as f:
         hdr = [HBW_MAGIC, 1, spec["domain"], spec["n_in"], len(spec["dims"])] + list(spec["dims"]) + \
               [spec["n_res"], spec["n_out"], spec["head_kind"]]

@@ -304,3 +304,18 @@ def test_autotuner_table_and_tuning_cache(net_files, tmp_path):
     np.testing.assert_array_equal(out[1], ref[1])
     with pytest.raises(hb.HBError, match="another network or precision"):
         hb.Model(path, prec=hb.HB_FP32, max_batch=2048).load_tuning(f)
+
+
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16])
+def test_ragged_width_parity(tmp_path, prec):
+    """A hidden width that is not a multiple of the tile (320, padded to 384 on
+    the device), as in the model-size sweep, against the oracle."""
+    path = str(tmp_path / "w320.hbw")
+    synth.write_weights(path, "stp4_res", spec=synth.widened("stp4_res", 320), seed=22, head_bias=40.0)
+    st = synth.stp_walks(4, synth.throughput_seeds(300, 808), lengths=200)
+    net = O.Net(path)
+    m = hb.Model(path, prec=prec, combine_md=True)
+    h, y = _eval(m, hb.hb_encode(1, st), 1)
+    y_ref = net.forward(st, mode=int(prec))[:, 0]
+    y_exact = net.forward(st)[:, 0] if prec != hb.HB_FP32 else y_ref
+    _check_rows(y, y_ref[:, None], y_exact[:, None], TOL[prec], 0.0 if prec == hb.HB_FP32 else 0.15)

@@ -177,3 +177,46 @@ def test_network_shapes(net_files):
         net = O.Net(net_files[name])
         assert net.dims == spec["dims"] and net.n_res == spec["n_res"] and net.n_out == spec["n_out"]
         assert net.n_in == spec["n_in"]
+
+
+def _md_net_one_output(path, n, shift):
+    """The closed-form network with only its second output, shifted: y = 2 MD - 2 + shift."""
+    ts = [np.asarray(t, dtype=np.float64) for t in nets.md_net_tensors(n)]
+    ts[-2] = ts[-2][:, 1:2]
+    ts[-1] = np.asarray(ts[-1]).reshape(-1)[1:2] + shift
+    synth.write_weights_arrays(path, 0 if n == 3 else 1, n ** 4, [2, 3], 1, 1, 0, ts)
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_ensemble_forward_closed_form(n, tmp_path):
+    """Minimum and sum over members with known outputs 2 MD - 2 + shift."""
+    shifts = [0.0, 3.0, -1.5]
+    paths = []
+    for i, sh in enumerate(shifts):
+        paths.append(str(tmp_path / f"m{i}.hbw"))
+        _md_net_one_output(paths[-1], n, sh)
+    members = [O.Net(p) for p in paths]
+    st = synth.stp_walks(n, range(200), lengths=41)
+    md = O.manhattan(n - 3, st).astype(np.float64)
+    np.testing.assert_array_equal(O.ensemble_forward(members[:1], st, O.ENS_MIN), 2 * md - 2)
+    np.testing.assert_array_equal(O.ensemble_forward(members, st, O.ENS_MIN), 2 * md - 2 - 1.5)
+    np.testing.assert_array_equal(O.ensemble_forward(members, st, O.ENS_SUM), 3 * (2 * md - 2) + 1.5)
+
+
+def test_combined_regression_rule():
+    md = np.array([5, 5, 5, 9, 9, 0])
+    y = np.array([2.7, -1.0, np.nan, 12.7, 3.0, 0.999999])
+    np.testing.assert_array_equal(O.h_regression(y, md, combine=3), [7, 5, 5, 21, 12, 0])
+    np.testing.assert_array_equal(O.h_regression(y, md, combine=2), [5, 5, 5, 12, 9, 0])
+    np.testing.assert_array_equal(O.h_regression(y, md, combine=1), [2, 0, 5, 9, 3, 0])
+    np.testing.assert_array_equal(O.h_regression(np.array([12.7]), None, offset=2.2), [10])
+    np.testing.assert_array_equal(O.h_regression(np.array([2.5, 3.5]), None, mode=1), [2, 4])
+    # the written-out rule agrees with the C rule on a sweep (classic = min)
+    f = O.lib().orc_h_regression
+    f.argtypes = [O.C.c_double, O.C.c_int, O.C.c_double, O.C.c_int]
+    rng = np.random.default_rng(3)
+    ys = np.concatenate([rng.uniform(-5, 60, 500), np.arange(-3, 50) + 0.0, np.arange(-3, 50) + 0.5])
+    cl = rng.integers(0, 50, ys.size)
+    for mode in (0, 1):
+        ref = [f(float(a), mode, 0.7, int(c)) for a, c in zip(ys, cl)]
+        np.testing.assert_array_equal(O.h_regression(ys, cl, combine=1, offset=0.7, mode=mode), ref)
