@@ -46,6 +46,11 @@ class Iter(C.Structure):
                 ("complete", C.c_int32), ("found", C.c_int32), ("limit", C.c_int64)]
 
 
+class IterReal(C.Structure):
+    _fields_ = [("bound", C.c_double), ("expanded", C.c_int64), ("generated", C.c_int64),
+                ("complete", C.c_int32), ("found", C.c_int32), ("limit", C.c_int64)]
+
+
 def _declare(L):
     vp = C.c_void_p
     L.orc_apply_seq_batch.argtypes = [C.c_int, vp, C.c_int64, C.c_int, vp]
@@ -82,6 +87,10 @@ def _declare(L):
     L.orc_bts.argtypes = [C.c_int, vp, C.POINTER(HSpec), C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                           C.c_int64, C.POINTER(Iter), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp,
                           C.POINTER(C.c_int)]
+    L.orc_ida_real.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int64, C.POINTER(IterReal), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
+    L.orc_bts_real.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
+                               C.POINTER(IterReal), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
     L.orc_train_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_double, vp, vp]
     L.orc_train_grad.restype = C.c_double
     L.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -358,3 +367,35 @@ def bts(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, b0=10000, c1=
     del keep
     return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
                 iters=_iters(arr, n.value))
+
+
+# ------------------------------------------------ real-valued heuristics
+def _iters_real(arr, n):
+    return [dict(bound=a.bound, expanded=a.expanded, generated=a.generated, complete=a.complete,
+                 found=a.found, limit=a.limit) for a in arr[:n]]
+
+
+def ida_real(start, table8f, complete_final=False, max_iters=5000, node_limit=-1):
+    """Serial IDA* on the 8-puzzle with real-valued h (float32 table by rank)."""
+    t = np.ascontiguousarray(table8f, dtype=np.float32)
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (IterReal * max_iters)()
+    n, cost, plen = C.c_int(0), C.c_int32(-1), C.c_int(0)
+    path = np.zeros(512, dtype=np.int8)
+    rc = lib().orc_ida_real(s.ctypes.data, t.ctypes.data, int(complete_final), max_iters, node_limit, arr,
+                            C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters_real(arr, n.value))
+
+
+def bts_real(start, table8f, b0=10000, c1=2, c2=8, plus_one=True, max_iters=2000, max_total=-1):
+    """Serial BTS on the 8-puzzle with real-valued h (float32 table by rank)."""
+    t = np.ascontiguousarray(table8f, dtype=np.float32)
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (IterReal * max_iters)()
+    n, cost, plen = C.c_int(0), C.c_int32(-1), C.c_int(0)
+    path = np.zeros(512, dtype=np.int8)
+    rc = lib().orc_bts_real(s.ctypes.data, t.ctypes.data, b0, c1, c2, int(plus_one), max_iters, max_total, arr,
+                            C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters_real(arr, n.value))

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["domain.c", "mlp.c", "search.c", "train.c"]
+SOURCES = ["domain.c", "mlp.c", "search.c", "search_real.c", "train.c"]
 OUT = os.path.join(HERE, "_build", "liboracle.so")
 
 

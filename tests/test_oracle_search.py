@@ -106,3 +106,54 @@ def test_bts_accepted_iterations_grow_geometrically():
                 assert i["expanded"] == i["limit"]
         ida = O.ida(O.STP4, s, hkind=O.H_MD)
         assert r["cost"] == ida["cost"]
+
+
+def _table8(values_by_state):
+    allst = O.all8()
+    ranks = np.array([O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data) for s in allst])
+    t = np.zeros(362880, dtype=np.float32)
+    t[ranks] = values_by_state
+    return t, ranks
+
+
+def test_real_valued_search_reduces_to_integer_search():
+    """With integer values in the real-valued table, the real-valued IDA* takes
+    exactly the integer search's iterations, and BTS reaches the same cost."""
+    allst = O.all8()
+    md = O.manhattan(0, allst)
+    tf, ranks = _table8(md.astype(np.float32))
+    ti = np.zeros(362880, dtype=np.int32)
+    ti[ranks] = md
+    for s in synth.stp3_instances(20):
+        a = O.ida_real(s, tf, complete_final=True)
+        b = O.ida(0, s, hkind=O.H_TABLE8, table8=ti, complete_final=True)
+        assert a["cost"] == b["cost"]
+        assert [(i["bound"], i["expanded"], i["generated"]) for i in a["iters"]] == \
+               [(float(i["bound"]), i["expanded"], i["generated"]) for i in b["iters"]]
+        # BTS bisects over real bounds (midpoints need not be integers), so only
+        # the outcome and the counts at integer probes are shared
+        c = O.bts_real(s, tf, b0=50)
+        d = O.bts(0, s, hkind=O.H_TABLE8, table8=ti, b0=50)
+        assert c["cost"] == d["cost"]
+        at_int = {i["bound"]: i["expanded"] for i in d["iters"] if i["complete"]}
+        for i in c["iters"]:
+            if i["complete"] and i["bound"] == int(i["bound"]) and i["bound"] in at_int:
+                assert i["expanded"] == at_int[i["bound"]]
+
+
+def test_real_valued_admissible_heuristic_is_optimal():
+    """h = max(0, MD/2 - 1/4) is admissible and not integer: IDA* and BTS find
+    the breadth-first distance; IDA*'s bounds rise strictly and need more
+    iterations than with Manhattan distance."""
+    allst = O.all8()
+    md = O.manhattan(0, allst)
+    tf, _ = _table8(np.maximum(0.0, 0.5 * md - 0.25).astype(np.float32))
+    bfs, _ = O.bfs8()
+    for s in synth.stp3_instances(20):
+        opt = bfs[O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data)]
+        a = O.ida_real(s, tf)
+        assert a["cost"] == opt
+        bounds = [i["bound"] for i in a["iters"]]
+        assert all(x < y for x, y in zip(bounds, bounds[1:]))
+        assert len(bounds) > len(O.ida(0, s, hkind=O.H_MD)["iters"])
+        assert O.bts_real(s, tf, b0=100)["cost"] == opt
