@@ -271,6 +271,31 @@ def main():
         pdb.close()
         search["cube"] = cube
 
+        # real-valued regression heuristic (the paper's regression experiment):
+        # the 8-puzzle network's y - 2.2 used without rounding, Batch IDA* against
+        # Batch BTS on ten starts (node limit 2M each)
+        rpath = os.path.join(tmp, "stp3_small.hbw")
+        synth.write_weights(rpath, "stp3_small", **netcfg.DEFAULTS["stp3_small"])
+        rm = hb.Model(rpath, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=2.2, max_batch=4096)
+        real = {"workload": "8-puzzle, regression net 81-128-128-1, h = max(0, y - 2.2) unrounded, 10 starts "
+                            "(30-60 move walks), 8 threads, batch 64, node limit 500K per start"}
+        for algo_name, algo in (("ida", hb.HB_IDA), ("bts", hb.HB_BTS)):
+            tot = {"iterations": 0, "expanded": 0, "wall_s": 0.0, "solved": 0}
+            for s0 in synth.stp3_instances(10):
+                p = hb.default_params(batch_size=64, work_num=4, node_limit=500_000, time_limit_s=5.0,
+                                      bts_b0=1000)
+                r = hb.cbdfs_solve(hb.HB_STP3, s0, model=rm, combine=hb.HB_H_NN_REAL, algo=algo, threads=8,
+                                   params=p, raise_on_error=False)
+                tot["iterations"] += len(r["iters"])
+                tot["expanded"] += r["expanded"]
+                tot["wall_s"] += r["wall_s"]
+                tot["solved"] += int(r["status"] == hb.HB_OK)
+            real[algo_name] = tot
+            log(f"[bench] real-valued h, {algo_name}: {tot['iterations']} iterations, {tot['expanded']} expanded, "
+                f"{tot['wall_s']:.2f} s, {tot['solved']}/10 solved")
+        rm.close()
+        search["real_valued_8puzzle"] = real
+
     # training step of the learned heuristic: same network shape, BF16 operands,
     # FP32 master weights and Adam, batch 8192 (labels: walk lengths)
     training = None

@@ -296,9 +296,15 @@ typedef enum { HB_IDA = 0, HB_BTS = 1 } hb_algo;
  *                    classic heuristic's (Fixed-Tree Evaluation).
  *  HB_H_CLASSIC:     classic h only, computed at generation (no network).
  *  HB_H_CLASSIC_BATCHED: classic h computed by the batch thread on the host,
- *                    through the same batching machinery (no GPU needed). */
+ *                    through the same batching machinery (no GPU needed).
+ *  HB_H_NN_REAL:     real-valued h = max(0, y - offset) of a regression model in
+ *                    the HB_OUT_REG_REAL mode, unrounded (Regression-Based Neural
+ *                    Heuristics experiment): f = g + h and the cost bounds are
+ *                    real; IDA*'s next bound is the smallest pruned f and BTS
+ *                    bisects over real bounds (cbdfs_iter.bound_real). */
 typedef enum {
-    HB_H_NN = 0, HB_H_MIN_NN_CLASSIC = 1, HB_H_FIXED_TREE = 2, HB_H_CLASSIC = 3, HB_H_CLASSIC_BATCHED = 4
+    HB_H_NN = 0, HB_H_MIN_NN_CLASSIC = 1, HB_H_FIXED_TREE = 2, HB_H_CLASSIC = 3, HB_H_CLASSIC_BATCHED = 4,
+    HB_H_NN_REAL = 5
 } hb_combine;
 
 typedef enum { HB_CLASSIC_ZERO = 0, HB_CLASSIC_MD = 1, HB_CLASSIC_PDB = 2 } hb_classic;
@@ -340,6 +346,7 @@ typedef struct {
     int64_t expanded, generated;
     int32_t complete;      /* 1: the iteration ran to completion */
     int32_t found;
+    double bound_real;     /* the bound (bound = its floor; equal for integer heuristics) */
 } cbdfs_iter;
 
 typedef struct {

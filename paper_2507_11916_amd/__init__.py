@@ -22,7 +22,7 @@ HB_STP3, HB_STP4, HB_RUBIK3 = 0, 1, 2
 HB_FP32, HB_BF16, HB_FP8_E4M3 = 0, 1, 2
 HB_OUT_REG_FLOOR, HB_OUT_REG_ROUND, HB_OUT_REG_REAL, HB_OUT_CLS_QUANTILE, HB_OUT_CLS_ARGMAX = 0, 1, 2, 3, 4
 HB_IDA, HB_BTS = 0, 1
-HB_H_NN, HB_H_MIN_NN_CLASSIC, HB_H_FIXED_TREE, HB_H_CLASSIC, HB_H_CLASSIC_BATCHED = 0, 1, 2, 3, 4
+HB_H_NN, HB_H_MIN_NN_CLASSIC, HB_H_FIXED_TREE, HB_H_CLASSIC, HB_H_CLASSIC_BATCHED, HB_H_NN_REAL = 0, 1, 2, 3, 4, 5
 HB_CLASSIC_ZERO, HB_CLASSIC_MD, HB_CLASSIC_PDB = 0, 1, 2
 HB_ENSEMBLE_MIN, HB_ENSEMBLE_SUM = 0, 1
 
@@ -68,7 +68,7 @@ class Params(C.Structure):
 
 class Iter(C.Structure):
     _fields_ = [("bound", C.c_int32), ("limit", C.c_int64), ("expanded", C.c_int64), ("generated", C.c_int64),
-                ("complete", C.c_int32), ("found", C.c_int32)]
+                ("complete", C.c_int32), ("found", C.c_int32), ("bound_real", C.c_double)]
 
 
 class Result(C.Structure):
@@ -385,7 +385,8 @@ def cbdfs_solve(domain, start, model=None, combine=HB_H_NN, classic=HB_CLASSIC_M
         raise HBError(st, lib().hb_last_error().decode())
     out = dict(status=st, cost=r.cost, path=[r.path[i] for i in range(r.path_len)] if r.path else [],
                iters=[dict(bound=r.iters[i].bound, limit=r.iters[i].limit, expanded=r.iters[i].expanded,
-                           generated=r.iters[i].generated, complete=r.iters[i].complete, found=r.iters[i].found)
+                           generated=r.iters[i].generated, complete=r.iters[i].complete, found=r.iters[i].found,
+                           bound_real=r.iters[i].bound_real)
                       for i in range(r.n_iter)],
                evals=r.evals, batches=r.batches, mean_batch=r.mean_batch, wall_s=r.wall_s,
                gpu_busy_s=r.gpu_busy_s, expanded=r.expanded, generated=r.generated, frontier=r.frontier,

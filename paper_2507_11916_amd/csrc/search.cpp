@@ -26,6 +26,11 @@
 //    root whose own f test happens inside the subtree search.  Hence per
 //    iteration (expanded, generated) equal the serial search's whenever the
 //    heuristic values are the same.
+// Real-valued heuristics (HB_H_NN_REAL): a node record holds the float bits of
+// h = max(0, y - offset); f = g + h and the bounds are doubles (exact, as g is
+// an integer and h a float), IDA*'s next bound is the smallest pruned f and BTS
+// bisects over real bounds.  Integer heuristics run the same code with
+// integer-valued doubles.
 // Readings of the pseudo-code: the expansion test is f = g + h <= T (the proof's
 // expansion condition), pruned nodes are popped and their f feeds the next
 // bound, the round-robin counter wraps modulo workNum, and `miss` counts the
@@ -34,6 +39,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <climits>
 #include <condition_variable>
@@ -173,6 +179,7 @@ private:
     int32_t* h_stage_ = nullptr;  // pinned, cap
     uint8_t* d_stage_ = nullptr;  // device, kHdr + cap * pb
     int32_t* d_h_ = nullptr;
+    float* d_raw_ = nullptr;      // device, cap: the network's y - offset (real-valued h)
     hipStream_t stream_ = nullptr;
     std::vector<int> buckets_;              // ascending batch capacities, the last is cap
     std::vector<hipGraphExec_t> execs_;     // per bucket, null until captured
@@ -187,8 +194,23 @@ struct Shared {
     hb_model* model = nullptr;
     bool uses_batches = false;
     bool uses_gpu = false;
+    bool real = false;  // h values are float bits (HB_H_NN_REAL)
     int classic_h(const uint8_t* s) const;
+    double hval(int32_t bits) const {
+        if (!real) return (double)bits;
+        float f;
+        std::memcpy(&f, &bits, 4);
+        return (double)f;
+    }
 };
+
+// Float bits of a real-valued heuristic value max(0, v) (+0.0 for v <= 0 or NaN).
+static int32_t real_bits(float v) {
+    const float h = v > 0.f ? v : 0.f;
+    int32_t b;
+    std::memcpy(&b, &h, 4);
+    return b;
+}
 
 int Shared::classic_h(const uint8_t* s) const {
     switch (classic) {
@@ -222,6 +244,7 @@ hb_status Batcher::init() {
         HB_HIP(hipHostMalloc((void**)&h_stage_, (size_t)cap_ * 4, hipHostMallocDefault));
         HB_HIP(hipMalloc((void**)&d_stage_, kHdr + (size_t)cap_ * pb));
         HB_HIP(hipMalloc((void**)&d_h_, (size_t)cap_ * 4));
+        if (sh_->real) HB_HIP(hipMalloc((void**)&d_raw_, (size_t)cap_ * 4));
         hb_status st = model_prepare(sh_->model, stream_);  // workspace exists before any capture
         if (st != HB_OK) return st;
         for (int b = 32; b < cap_; b *= 2) buckets_.push_back(b);
@@ -250,6 +273,7 @@ Batcher::~Batcher() {
         (void)hipHostFree(h_stage_);
         (void)hipFree(d_stage_);
         (void)hipFree(d_h_);
+        (void)hipFree(d_raw_);
         if (stream_) (void)hipStreamDestroy(stream_);
     }
 }
@@ -300,10 +324,11 @@ hb_status Batcher::capture(int bi) {
     HB_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)B * pb, hipMemcpyHostToDevice, stream_);
     hb_status st = e == hipSuccess ? model_eval(sh_->model, d_stage_ + kHdr, 0, reinterpret_cast<const int32_t*>(d_stage_),
-                                                B, d_h_, nullptr, stream_, nullptr)
+                                                B, d_h_, d_raw_, stream_, nullptr)
                                    : fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
     if (st == HB_OK) {
-        e = hipMemcpyAsync(h_stage_, d_h_, (size_t)B * 4, hipMemcpyDeviceToHost, stream_);
+        const void* src = sh_->real ? (const void*)d_raw_ : (const void*)d_h_;
+        e = hipMemcpyAsync(h_stage_, src, (size_t)B * 4, hipMemcpyDeviceToHost, stream_);
         if (e != hipSuccess) st = fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
     }
     const hipError_t ee = hipStreamEndCapture(stream_, &g);
@@ -340,12 +365,18 @@ hb_status Batcher::gpu_eval(const uint8_t* packed, int n, int32_t* h_out) {
     }
     if (!launched) {
         HB_HIP(hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)n * pb, hipMemcpyHostToDevice, stream_));
-        hb_status st = model_eval(sh_->model, d_stage_ + kHdr, n, nullptr, 0, d_h_, nullptr, stream_, nullptr);
+        hb_status st = model_eval(sh_->model, d_stage_ + kHdr, n, nullptr, 0, d_h_, d_raw_, stream_, nullptr);
         if (st != HB_OK) return st;
-        HB_HIP(hipMemcpyAsync(h_stage_, d_h_, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
+        const void* src = sh_->real ? (const void*)d_raw_ : (const void*)d_h_;
+        HB_HIP(hipMemcpyAsync(h_stage_, src, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
     }
     HB_HIP(hipStreamSynchronize(stream_));
-    std::memcpy(h_out, h_stage_, (size_t)n * 4);
+    if (sh_->real) {
+        const float* v = reinterpret_cast<const float*>(h_stage_);
+        for (int i = 0; i < n; i++) h_out[i] = real_bits(v[i]);
+    } else {
+        std::memcpy(h_out, h_stage_, (size_t)n * 4);
+    }
     gpu_busy += now_s() - t0;
     return HB_OK;
 }
@@ -463,8 +494,8 @@ struct PNode {
     int16_t g;
     int8_t move;
     uint8_t goal;
-    int32_t h;       // pruning value
-    int32_t h_eval;  // network / batched value (for the record of a subtree root)
+    double h;        // pruning value
+    int32_t h_eval;  // network / batched value as stored in a node record
     int32_t hc;
     int32_t n_children;
 };
@@ -474,7 +505,7 @@ struct Solver;
 // --------------------------------------------------------------- one search
 struct IterOut {
     int64_t expanded = 0, generated = 0;
-    int32_t next = INT32_MAX;
+    double next = INFINITY;
     bool found = false, exceeded = false, aborted = false, timed_out = false;
     std::vector<int8_t> path;
 };
@@ -503,19 +534,19 @@ struct Solver {
     double deadline = 0;  // wall-clock stop (now_s() scale), 0 = none
     int64_t limit = -1;
     bool stop_at_goal = true;
-    int32_t bound = 0;
+    double bound = 0;
     std::mutex sol_mu;
     std::vector<int8_t> sol_path;
     bool budget_hit = false;
 
-    int prune_h(const NodeRec& r) const {
+    double prune_h(const NodeRec& r) const {
         switch (sh.combine) {
-            case HB_H_FIXED_TREE: case HB_H_CLASSIC: return r.hc;
-            default: return r.h.load(std::memory_order_relaxed);
+            case HB_H_FIXED_TREE: case HB_H_CLASSIC: return (double)r.hc;
+            default: return sh.hval(r.h.load(std::memory_order_relaxed));
         }
     }
     hb_status build_tree(const uint8_t* start);
-    IterOut run(int32_t T, int64_t lim, bool stop_goal);
+    IterOut run(double T, int64_t lim, bool stop_goal);
     void thread_main(int tid, IterOut* out, int64_t* peak);
 };
 
@@ -564,7 +595,7 @@ hb_status Solver::build_tree(const uint8_t* start) {
     // Heuristic values of every node of the initial tree (one bulk evaluation).
     for (auto& n : tree) {
         n.goal = is_goal(D, n.s);
-        n.hc = (sh.combine == HB_H_NN) ? 0 : sh.classic_h(n.s);
+        n.hc = (sh.combine == HB_H_NN || sh.combine == HB_H_NN_REAL) ? 0 : sh.classic_h(n.s);
     }
     if (sh.uses_batches) {
         std::vector<uint8_t> packed(tree.size() * D.packed_bytes);
@@ -580,7 +611,7 @@ hb_status Solver::build_tree(const uint8_t* start) {
     } else {
         for (auto& n : tree) n.h_eval = n.hc;
     }
-    for (auto& n : tree) n.h = (sh.combine == HB_H_FIXED_TREE || sh.combine == HB_H_CLASSIC) ? n.hc : n.h_eval;
+    for (auto& n : tree) n.h = (sh.combine == HB_H_FIXED_TREE || sh.combine == HB_H_CLASSIC) ? (double)n.hc : sh.hval(n.h_eval);
     return HB_OK;
 }
 
@@ -594,7 +625,7 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
     std::vector<char> terminated(W, 0);
     std::vector<char> has_work(W, 0);
     int64_t expanded = 0, generated = 0, flushed = 0;
-    int32_t next = INT32_MAX;
+    double next = INFINITY;
     int64_t local_peak = 0;
     int miss = 0;
     bool idle = false;
@@ -648,7 +679,7 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
             if (r.expanded) { top[w]--; continue; }
             const int32_t hv = r.h.load(std::memory_order_acquire);
             if (hv == kPending) return 0;  // heuristic not ready: switch subtree
-            const int32_t f = r.g + prune_h(r);
+            const double f = (double)r.g + prune_h(r);
             if (f > bound) {
                 next = std::min(next, f);
                 top[w]--;
@@ -702,7 +733,7 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
                 c.move = (int8_t)a;
                 c.parent = parent;
                 c.expanded = 0;
-                c.hc = (sh.combine == HB_H_NN) ? 0 : sh.classic_h(c.s);
+                c.hc = (sh.combine == HB_H_NN || sh.combine == HB_H_NN_REAL) ? 0 : sh.classic_h(c.s);
                 if (sh.uses_batches) c.h.store(kPending, std::memory_order_relaxed);
                 else c.h.store(c.hc, std::memory_order_relaxed);
                 kids[nk++] = top[w];
@@ -777,7 +808,7 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
     *peak += local_peak;
 }
 
-IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
+IterOut Solver::run(double T, int64_t lim, bool stop_goal) {
     IterOut out;
     bound = T;
     limit = lim;
@@ -805,7 +836,7 @@ IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
         if (!reach[i]) continue;
         const PNode& n = tree[i];
         if (i >= first_frontier) { work.push_back(i); continue; }
-        const int32_t f = n.g + n.h;
+        const double f = (double)n.g + n.h;
         if (f > T) { out.next = std::min(out.next, f); continue; }
         if (n.goal) {
             if (!found_flag.load()) {
@@ -827,7 +858,8 @@ IterOut Solver::run(int32_t T, int64_t lim, bool stop_goal) {
     }
     // A path never holds more than T + 1 expanded nodes (h >= 0), each leaving
     // at most n_actions children on the stack.
-    stack_cap = (std::min<int32_t>(std::max<int32_t>(T, 0), kMaxDepth) + 2) * sh.D->n_actions + 2;
+    const int depth_cap = T <= 0 ? 0 : T >= kMaxDepth ? kMaxDepth : (int)std::floor(T);
+    stack_cap = (depth_cap + 2) * sh.D->n_actions + 2;
     work_next.store(0);
     int64_t peak = 0;
     if (!stop.load() && !exceeded_flag.load() && !work.empty()) {
@@ -913,14 +945,19 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     S->sh.classic = h->classic;
     S->sh.pdb = h->pdb;
     S->sh.model = h->model;
-    if ((int)h->combine < 0 || (int)h->combine > 4) return fail(HB_E_INVAL, "unknown combine mode");
+    if ((int)h->combine < 0 || (int)h->combine > 5) return fail(HB_E_INVAL, "unknown combine mode");
     if (h->classic == HB_CLASSIC_MD && d == HB_RUBIK3) return fail(HB_E_INVAL, "Manhattan distance needs a sliding tile");
     if (h->classic == HB_CLASSIC_PDB && (!h->pdb || d != HB_RUBIK3)) return fail(HB_E_INVAL, "PDB heuristic needs a cube and a pdb");
-    const bool nn = h->combine == HB_H_NN || h->combine == HB_H_MIN_NN_CLASSIC || h->combine == HB_H_FIXED_TREE;
+    const bool nn = h->combine == HB_H_NN || h->combine == HB_H_MIN_NN_CLASSIC || h->combine == HB_H_FIXED_TREE ||
+                    h->combine == HB_H_NN_REAL;
     if (nn) {
         if (!h->model) return fail(HB_E_INVAL, "this combine mode needs a model");
         if (h->model->spec.domain != (int)d) return fail(HB_E_INVAL, "model domain does not match");
     }
+    if (h->combine == HB_H_NN_REAL &&
+        (h->model->opts.out != HB_OUT_REG_REAL || h->model->spec.n_out != 1))
+        return fail(HB_E_INVAL, "a real-valued heuristic needs a regression model in the REAL output mode");
+    S->sh.real = h->combine == HB_H_NN_REAL;
     S->sh.uses_gpu = nn;
     S->sh.uses_batches = nn || h->combine == HB_H_CLASSIC_BATCHED;
     S->P = &P;
@@ -943,13 +980,15 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     std::vector<int8_t> path;
     hb_status result = HB_E_BUDGET;
     int32_t cost = -1;
-    const int32_t h_root = S->tree[0].h;
+    const double h_root = S->tree[0].h;
+    const bool real = S->sh.real;
     auto over_time = [&] { return P.time_limit_s > 0 && now_s() - S->t_start > P.time_limit_s; };
     auto over_nodes = [&] { return P.node_limit > 0 && S->total_expanded >= P.node_limit; };
     auto remaining = [&]() -> int64_t { return P.node_limit > 0 ? std::max<int64_t>(0, P.node_limit - S->total_expanded) : -1; };
-    auto push_iter = [&](int32_t b, int64_t lim, const IterOut& o, bool complete) {
+    auto push_iter = [&](double b, int64_t lim, const IterOut& o, bool complete) {
         cbdfs_iter it{};
-        it.bound = b;
+        it.bound = (int32_t)std::floor(b);
+        it.bound_real = b;
         it.limit = lim;
         it.expanded = o.expanded;
         it.generated = o.generated;
@@ -959,7 +998,7 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     };
 
     if (algo == HB_IDA) {
-        int32_t bound = P.start_bound >= 0 ? P.start_bound : h_root;
+        double bound = P.start_bound >= 0 ? (double)P.start_bound : h_root;
         for (int k = 0; k < P.max_iters; k++) {
             const int64_t lim = remaining();
             const bool stop_goal = !P.complete_final_iter;
@@ -974,20 +1013,21 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
                 break;
             }
             if (o.timed_out || o.exceeded || over_nodes() || over_time()) { result = HB_E_BUDGET; break; }
-            if (o.next == INT32_MAX) { result = HB_E_NOSOLUTION; break; }
+            if (std::isinf(o.next)) { result = HB_E_NOSOLUTION; break; }
             bound = o.next;
         }
     } else {
         // Budgeted Tree Search (reading stated in the oracle and the design notes).
         int64_t b = P.bts_b0;
-        int32_t lo_next = h_root;
-        int32_t probe = P.start_bound >= 0 ? P.start_bound : h_root + (P.bts_root_plus_one ? 1 : 0);
-        int32_t hi = INT32_MAX;
-        int32_t step = 1;
+        // Integer heuristics bisect over integers; real-valued ones over reals.
+        double lo_next = h_root;
+        double probe = P.start_bound >= 0 ? (double)P.start_bound : h_root + (P.bts_root_plus_one ? 1 : 0);
+        double hi = INFINITY;
+        double step = 1;
         for (int k = 0; k < P.max_iters; k++) {
             if (over_nodes() || over_time()) { result = HB_E_BUDGET; break; }
             bool unlimited = false;
-            if (hi != INT32_MAX && lo_next >= hi) { probe = hi; unlimited = true; }
+            if (!std::isinf(hi) && lo_next >= hi) { probe = hi; unlimited = true; }
             int64_t lim = unlimited ? -1 : (int64_t)P.bts_c2 * b;
             const int64_t rem = remaining();
             const bool budget_cut = rem >= 0 && (lim < 0 || rem < lim);
@@ -1010,16 +1050,16 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
                     break;
                 }
             } else if (!o.exceeded) {
-                if (o.next == INT32_MAX) { result = HB_E_NOSOLUTION; break; }
+                if (std::isinf(o.next)) { result = HB_E_NOSOLUTION; break; }
                 lo_next = o.next;
                 if (unlimited || o.expanded >= (int64_t)P.bts_c1 * b) {
                     if (o.expanded > b) b = o.expanded;
-                    hi = INT32_MAX;
+                    hi = INFINITY;
                     step = 1;
                     probe = lo_next;
                     continue;
                 }
-                if (hi == INT32_MAX) {
+                if (std::isinf(hi)) {
                     probe = lo_next + step - 1;
                     if (probe < lo_next) probe = lo_next;
                     step *= 2;
@@ -1028,7 +1068,8 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
             } else {
                 hi = probe;
             }
-            if (hi != INT32_MAX && lo_next < hi) probe = lo_next + (hi - lo_next) / 2;
+            if (!std::isinf(hi) && lo_next < hi)
+                probe = real ? lo_next + (hi - lo_next) / 2 : lo_next + std::floor((hi - lo_next) / 2);
         }
     }
     std::string err_text = S->batcher ? S->batcher->error_text : "";

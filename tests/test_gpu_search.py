@@ -97,3 +97,50 @@ def test_cube_fixed_tree_bts_matches_oracle(net_files):
         assert [(i["bound"], i["limit"], i["complete"]) for i in r["iters"]] == \
                [(i["bound"], i["limit"], i["complete"]) for i in o["iters"]]
         assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
+
+
+def _real_md_net(path):
+    """Closed-form 8-puzzle network with y = MD/2 - 1/2 off the goal (the
+    hand-built 2 MD - 2 network with its head scaled by 1/4): exact in float32
+    and float64."""
+    from tests import nets
+    ts = [np.asarray(t, dtype=np.float64) for t in nets.md_net_tensors(3)]
+    ts[-2] = ts[-2][:, 1:2] * 0.25
+    ts[-1] = np.asarray(ts[-1]).reshape(-1)[1:2] * 0.25
+    synth.write_weights_arrays(path, 0, 81, [2, 3], 1, 1, 0, ts)
+
+
+def test_real_valued_search_matches_oracle(tmp_path):
+    """Real-valued h = max(0, y + 1/4) = max(0, MD/2 - 1/4) from the GPU: Batch
+    IDA* and Batch BTS take the serial real-valued oracle's iterations (bounds,
+    limits and counts) exactly, and find optimal costs."""
+    path = str(tmp_path / "real.hbw")
+    _real_md_net(path)
+    allst = O.all8()
+    md = O.manhattan(0, allst)
+    y = O.Net(path).forward(allst)[:, 0]
+    away = md >= 1  # the closed form holds off the goal (a ReLU clips at MD = 0)
+    np.testing.assert_array_equal(y[away], 0.5 * md[away] - 0.5)
+    ranks = np.array([O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data) for s in allst])
+    table = np.zeros(362880, dtype=np.float32)
+    table[ranks] = np.maximum(0.0, y + 0.25)
+    m = hb.Model(path, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=-0.25, max_batch=4096)
+    bfs, _ = O.bfs8()
+    for i, s in enumerate(synth.stp3_instances(10)):
+        threads = 1 if i % 2 == 0 else 4
+        opt = bfs[O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data)]
+        p = hb.default_params(batch_size=64, work_num=4, complete_final_iter=1)
+        r = hb.cbdfs_solve(0, s, model=m, combine=hb.HB_H_NN_REAL, threads=threads, params=p)
+        o = O.ida_real(s, table, complete_final=True)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"] == opt
+        assert [(it["bound_real"], it["expanded"], it["generated"]) for it in r["iters"]] == \
+               [(it["bound"], it["expanded"], it["generated"]) for it in o["iters"]]
+        assert np.array_equal(_follow(0, s, r["path"]), O.goal(0))
+        p = hb.default_params(batch_size=64, work_num=4, bts_b0=50)
+        r = hb.cbdfs_solve(0, s, model=m, combine=hb.HB_H_NN_REAL, algo=hb.HB_BTS, threads=threads, params=p)
+        o = O.bts_real(s, table, b0=50)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"] == opt
+        assert [(it["bound_real"], it["limit"], it["complete"]) for it in r["iters"]] == \
+               [(it["bound"], it["limit"], it["complete"]) for it in o["iters"]]
+        assert _complete_counts(r["iters"]) == [(int(np.floor(it["bound"])), it["expanded"], it["generated"])
+                                                for it in o["iters"] if it["complete"]]
