@@ -75,12 +75,24 @@ struct Dec<2> {  // cube
     }
 };
 
+// s_waitcnt vmcnt(N) with the expcnt and lgkmcnt fields at their maxima (no
+// wait on them); vmcnt is split over bits 3:0 and 15:14.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
 // ------------------------------------------------------------ layer 1
 // Gather-sum over a column slice.  A block owns GCOLS columns of the table for
 // GROWS consecutive states: it copies the table's column slice (all
 // P * S rows, a few tens of KiB) and the states' packed records into LDS once,
 // then each thread forms 4 columns of one state at a time by summing the
-// state's P rows out of LDS.
+// state's P rows out of LDS.  The slice is copied with global_load_lds_dwordx4
+// (16 bytes per lane straight into LDS at the instruction's base + 16 * lane):
+// the slice is row-major with 16-byte pieces in order, so the 64 pieces of one
+// instruction are 1 KiB of consecutive LDS, and every piece of the slice is in
+// flight at once instead of one register round trip per piece.
 // Reading the slice once per block instead of once per state cuts the
 // gathered L2 traffic by about GROWS / S.  Sum order per output: bias, then
 // the cells in order.  Rows in [n, m_rows) are written as zeros.
@@ -101,17 +113,23 @@ __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restri
     const int r0 = blockIdx.y * GROWS;
     const int n = min(n_dev ? *n_dev : n_host, m_rows);
 
-    // table slice -> LDS, 16-byte pieces
+    // table slice -> LDS, 16-byte pieces; wave w issues pieces [64 j, 64 j + 64)
+    // for j = w, w + 4, ...  (lanes past the last piece are masked off)
     const int pieces = t_rows * (ROWB / 16);
-    for (int i = tid; i < pieces; i += 256) {
-        const int r = i / (ROWB / 16), q = i % (ROWB / 16);
-        const uint8_t* src = reinterpret_cast<const uint8_t*>(table) + ((size_t)r * N + c0) * TB + q * 16;
-        *reinterpret_cast<uint4*>(smem + r * ROWB + q * 16) = *reinterpret_cast<const uint4*>(src);
+    const int lane = tid & 63;
+    for (int i0 = (tid >> 6) * 64; i0 < pieces; i0 += 256) {
+        const int i = i0 + lane;
+        if (i < pieces) {
+            const int r = i / (ROWB / 16), q = i % (ROWB / 16);
+            const uint8_t* src = reinterpret_cast<const uint8_t*>(table) + ((size_t)r * N + c0) * TB + q * 16;
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(smem + i0 * 16), 16, 0, 0);
+        }
     }
     for (int i = tid; i < GROWS * D::WORDS; i += 256) {
         const int r = r0 + i / D::WORDS;
         recs[i] = r < n ? packed[(size_t)r0 * D::WORDS + i] : 0;
     }
+    wait_vmcnt<0>();
     __syncthreads();
 
     // 16 lanes per state, 4 columns per lane: a 16-lane group reads one
@@ -120,41 +138,65 @@ __global__ __launch_bounds__(256) void gather_l1_kernel(const uint64_t* __restri
     const int col = c0 + 4 * chunk;
     float b[4];
     _Pragma("unroll") for (int j = 0; j < 4; j++) b[j] = bias[col + j];
-    for (int rr = tid >> 4; rr < GROWS; rr += 16) {
-        const int r = r0 + rr;
-        if (r >= m_rows) break;
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        if (r < n) {
-            uint64_t w[D::WORDS];
-            _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[i] = recs[rr * D::WORDS + i];
-            _Pragma("unroll") for (int j = 0; j < 4; j++) acc[j] = b[j];
-            _Pragma("unroll 16") for (int p = 0; p < D::P; p++) {
-                const uint8_t* src = smem + D::row(w, p) * ROWB + chunk * 4 * TB;
-                if (WT == 0) {
-                    const float4 v = *reinterpret_cast<const float4*>(src);
-                    acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w;
-                } else {
-                    const uint2 v = *reinterpret_cast<const uint2*>(src);
-                    acc[0] += bf16_to_f32((uint16_t)(v.x & 0xFFFF));
-                    acc[1] += bf16_to_f32((uint16_t)(v.x >> 16));
-                    acc[2] += bf16_to_f32((uint16_t)(v.y & 0xFFFF));
-                    acc[3] += bf16_to_f32((uint16_t)(v.y >> 16));
-                }
-            }
-            _Pragma("unroll") for (int j = 0; j < 4; j++) acc[j] = fmaxf(acc[j], 0.f);
+    // Two states per pass (rr and rr + 16), rows in chunks of CH: the 2 * CH
+    // LDS reads of a chunk are issued before it is summed (per state in cell
+    // order), so one LDS latency is paid per chunk.  States past n have zero
+    // records (valid row indices) and are written as zeros.
+    constexpr int CH = D::P < 16 ? D::P : 16;
+    static_assert(D::P % CH == 0, "cells per chunk");
+    for (int rr = tid >> 4; rr < GROWS; rr += 32) {
+        if (r0 + rr >= m_rows) break;
+        uint64_t w[2][D::WORDS];
+        float acc[2][4];
+        _Pragma("unroll") for (int u = 0; u < 2; u++) {
+            _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[u][i] = recs[(rr + 16 * u) * D::WORDS + i];
+            _Pragma("unroll") for (int j = 0; j < 4; j++) acc[u][j] = b[j];
         }
-        const size_t o = (size_t)r * ld_out + col;
-        if (OUT == 0) {
-            *reinterpret_cast<float4*>((float*)out + o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        } else if (OUT == 1) {
-            uint2 v;
-            v.x = (uint32_t)f32_to_bf16(acc[0]) | ((uint32_t)f32_to_bf16(acc[1]) << 16);
-            v.y = (uint32_t)f32_to_bf16(acc[2]) | ((uint32_t)f32_to_bf16(acc[3]) << 16);
-            *reinterpret_cast<uint2*>((uint16_t*)out + o) = v;
-        } else {
-            *reinterpret_cast<uint32_t*>((uint8_t*)out + o) =
-                f32x2_to_fp8x2(acc[0] * out_inv_scale, acc[1] * out_inv_scale) |
-                (f32x2_to_fp8x2(acc[2] * out_inv_scale, acc[3] * out_inv_scale) << 16);
+        _Pragma("unroll") for (int p0 = 0; p0 < D::P; p0 += CH) {
+            if (WT == 0) {
+                float4 v[2][CH];
+                _Pragma("unroll") for (int u = 0; u < 2; u++)
+                    _Pragma("unroll") for (int k = 0; k < CH; k++)
+                        v[u][k] = *reinterpret_cast<const float4*>(smem + D::row(w[u], p0 + k) * ROWB + chunk * 16);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 * CH, 0);
+                _Pragma("unroll") for (int u = 0; u < 2; u++)
+                    _Pragma("unroll") for (int k = 0; k < CH; k++) {
+                        acc[u][0] += v[u][k].x; acc[u][1] += v[u][k].y;
+                        acc[u][2] += v[u][k].z; acc[u][3] += v[u][k].w;
+                    }
+            } else {
+                uint2 v[2][CH];
+                _Pragma("unroll") for (int u = 0; u < 2; u++)
+                    _Pragma("unroll") for (int k = 0; k < CH; k++)
+                        v[u][k] = *reinterpret_cast<const uint2*>(smem + D::row(w[u], p0 + k) * ROWB + chunk * 8);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 * CH, 0);
+                _Pragma("unroll") for (int u = 0; u < 2; u++)
+                    _Pragma("unroll") for (int k = 0; k < CH; k++) {
+                        acc[u][0] += bf16_to_f32((uint16_t)(v[u][k].x & 0xFFFF));
+                        acc[u][1] += bf16_to_f32((uint16_t)(v[u][k].x >> 16));
+                        acc[u][2] += bf16_to_f32((uint16_t)(v[u][k].y & 0xFFFF));
+                        acc[u][3] += bf16_to_f32((uint16_t)(v[u][k].y >> 16));
+                    }
+            }
+        }
+        _Pragma("unroll") for (int u = 0; u < 2; u++) {
+            const int r = r0 + rr + 16 * u;
+            if (r >= m_rows) break;
+            float a[4];
+            _Pragma("unroll") for (int j = 0; j < 4; j++) a[j] = r < n ? fmaxf(acc[u][j], 0.f) : 0.f;
+            const size_t o = (size_t)r * ld_out + col;
+            if (OUT == 0) {
+                *reinterpret_cast<float4*>((float*)out + o) = make_float4(a[0], a[1], a[2], a[3]);
+            } else if (OUT == 1) {
+                uint2 v;
+                v.x = (uint32_t)f32_to_bf16(a[0]) | ((uint32_t)f32_to_bf16(a[1]) << 16);
+                v.y = (uint32_t)f32_to_bf16(a[2]) | ((uint32_t)f32_to_bf16(a[3]) << 16);
+                *reinterpret_cast<uint2*>((uint16_t*)out + o) = v;
+            } else {
+                *reinterpret_cast<uint32_t*>((uint8_t*)out + o) =
+                    f32x2_to_fp8x2(a[0] * out_inv_scale, a[1] * out_inv_scale) |
+                    (f32x2_to_fp8x2(a[2] * out_inv_scale, a[3] * out_inv_scale) << 16);
+            }
         }
     }
 }
@@ -428,14 +470,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // most (stages issued after k) * LD of its loads are outstanding; the barrier
 // that follows makes every wave's part of stage k visible and frees the slot
 // that stage k - 1 was read from, which the next issue refills.
-// s_waitcnt vmcnt(N) with the expcnt and lgkmcnt fields at their maxima (no
-// wait on them); vmcnt is split over bits 3:0 and 15:14.
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
-
 template <int PREC, int OUTT, int BM, int BN, int NS>
 __global__ __launch_bounds__(256) void gemm_ring_kernel(GemmArgs g) {
     constexpr int EB = Ty<PREC>::EB;
