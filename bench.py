@@ -44,16 +44,16 @@ TILE_KERNELS = {1: "gemm_kernel<0, 0, 128, 128>", 2: "gemm_kernel<0, 0, 128, 256
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    when the summary covers another kernel or the kernel source has changed since."""
+    when the summary has no row for it or the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "gemm_f32_stp4res_b8000_hbm_bytes.md")
     try:
         fields = dict(l.strip().split(": ", 1) for l in open(path) if l.startswith("    ") and ": " in l)
         src = os.path.join(ROOT, "paper_2507_11916_amd", "csrc", "kernels.hip")
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if fields.get("traffic_kernel") != kernel or fields.get("kernels_hip_sha256_16") != sha:
+        if fields.get("kernels_hip_sha256_16") != sha:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[f"traffic {kernel}"])
     except (OSError, ValueError, KeyError):
         return None
 
@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the benchmark line: evals/s and fixed-tree search nodes/s of the 15-puzzle "
                          "net at several hidden widths (same depth) and each precision; prints its own JSON line")
+    ap.add_argument("--all-tiles", action="store_true",
+                    help="with --profile-only: after the tuned loop, run a few steps with every GEMM tile forced "
+                         "(so one profiler run covers each tile's kernel at the benchmark shape)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --profile-only: also copy a buffer of this many MiB five times (the known-size "
                          "copy kernel that scales hardware byte counters)")
@@ -173,6 +176,12 @@ def main():
         models[name] = m
 
     if args.profile_only:
+        if args.all_tiles:
+            m = models[args.prec]
+            for t in sorted(TILE_KERNELS):
+                m.set_tile(t)
+                us = timed_loop(m, max(3, args.steps // 5), 1) * 1e3
+                log(f"[bench] {args.prec} tile {t}: {us:.1f} us/step")
         if args.copy_mib > 0:
             src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
             dst = torch.empty_like(src)
