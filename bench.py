@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the benchmark line: evals/s and fixed-tree search nodes/s of the 15-puzzle "
                          "net at several hidden widths (same depth) and each precision; prints its own JSON line")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
+                         "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
     ap.add_argument("--all-tiles", action="store_true",
                     help="with --profile-only: after the tuned loop, run a few steps with every GEMM tile forced "
                          "(so one profiler run covers each tile's kernel at the benchmark shape)")
@@ -84,6 +87,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.library_gemm:
+        library_gemm(args, torch)
+        return
     import paper_2507_11916_amd as hb
     import synth
     from synth import netcfg
@@ -384,6 +390,40 @@ def main():
         "training": training,
     }
     print(json.dumps(line))
+
+
+def library_gemm(args, torch):
+    """The vendor GEMM on one dense layer's shape, without bias, residual or ReLU:
+    a reference point for the hand-written kernels (which fuse that epilogue)."""
+    M, K, N = args.batch, 1024, 1024
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    out = {}
+
+    def timed(fn, reps=100):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3  # us
+
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.randn(M, K, device="cuda", dtype=dt, generator=gen)
+        w = torch.randn(N, K, device="cuda", dtype=dt, generator=gen)  # [N][K], as the layers store weights
+        us = timed(lambda: a @ w.t())
+        out[name] = {"us": us, "tflops": 2 * M * K * N / us / 1e6}
+    a8 = torch.randn(M, K, device="cuda", generator=gen).to(torch.float8_e4m3fn)
+    w8 = torch.randn(N, K, device="cuda", generator=gen).to(torch.float8_e4m3fn)
+    one = torch.tensor(1.0, device="cuda")
+    us = timed(lambda: torch._scaled_mm(a8, w8.t(), scale_a=one, scale_b=one, out_dtype=torch.bfloat16))
+    out["fp8"] = {"us": us, "tflops": 2 * M * K * N / us / 1e6}
+    for k, v in out.items():
+        log(f"[bench] library {k}: {v['us']:.1f} us  {v['tflops']:.1f} TFLOP/s")
+    print(json.dumps({"library_gemm": out, "shape": {"M": M, "K": K, "N": N}}))
 
 
 def size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp):
