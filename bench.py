@@ -229,16 +229,18 @@ def main():
 
     # search nodes/s: Batch IDA* on a 15-puzzle start (200-move walk), fixed-tree
     # mode (network evaluated on every generated state, Manhattan pruning), at
-    # each precision; a budget of 1M expansions each
+    # each precision; a budget of 1M expansions each.  workNum (subtrees per
+    # thread) 64: the 15-puzzle's low branching factor leaves batches of about
+    # 120 states at workNum 8, where a forward pass costs the same as at 1000.
     search = None
     if not args.no_search:
         start = synth.stp4_instances(1)[0]
         threads = min(32, max(4, len(os.sched_getaffinity(0))))
         search = {"workload": "15-puzzle start (200-move walk), fixed-tree Batch IDA*, Manhattan pruning, "
-                              "work_num 8, 1M expansions", "threads": threads,
+                              "work_num 64, 1M expansions", "threads": threads,
                   "host_cores": len(os.sched_getaffinity(0))}
         for name in ("f32", "bf16", "fp8"):
-            p = hb.default_params(batch_size=8000, work_num=8, node_limit=1_000_000, time_limit_s=20.0)
+            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0)
             r = hb.cbdfs_solve(hb.HB_STP4, start, model=models[name], combine=hb.HB_H_FIXED_TREE,
                                classic=hb.HB_CLASSIC_MD, threads=threads, params=p, raise_on_error=False)
             search[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
@@ -254,7 +256,8 @@ def main():
             search["f32"]["per_iteration"][:-1] == search["bf16"]["per_iteration"][:-1] == search["fp8"]["per_iteration"][:-1])
 
         # cube: classifier network (324 -> 2000 -> 1000 -> 4 residual blocks -> 21, quantile 0.99),
-        # Batch BTS in fixed-tree mode pruning with the 8-corner PDB, batch 4000, 300K expansions
+        # Batch BTS in fixed-tree mode pruning with the 8-corner PDB, batch 4000, workNum 32,
+        # 300K expansions
         cpath = os.path.join(tmp, "rc_cls.hbw")
         synth.write_weights(cpath, "rc_cls", **netcfg.DEFAULTS["rc_cls"])
         t0 = time.time()
@@ -265,13 +268,13 @@ def main():
                                                                         length_base=20, length_span=11))
         d_ccal = torch.from_numpy(hb.hb_encode(hb.HB_RUBIK3, ccal)).cuda()
         cube = {"workload": "cube start (config-3 walk), classifier net 324-2000-1000-4x(1000,1000)-21, "
-                            "fixed-tree Batch BTS with the 8-corner PDB, batch 4000, work_num 8, 300K expansions",
+                            "fixed-tree Batch BTS with the 8-corner PDB, batch 4000, work_num 32, 300K expansions",
                 "pdb_build_s": pdb_s}
         for name, prec in (("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)):
             cm = hb.Model(cpath, prec=prec, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4000)
             if prec == hb.HB_FP8_E4M3:
                 cm.calibrate(d_ccal)
-            p = hb.default_params(batch_size=4000, work_num=8, node_limit=300_000, time_limit_s=20.0)
+            p = hb.default_params(batch_size=4000, work_num=32, node_limit=300_000, time_limit_s=20.0)
             r = hb.cbdfs_solve(hb.HB_RUBIK3, cstart, model=cm, combine=hb.HB_H_FIXED_TREE,
                                classic=hb.HB_CLASSIC_PDB, pdb=pdb, algo=hb.HB_BTS, threads=threads, params=p,
                                raise_on_error=False)
