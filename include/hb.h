@@ -92,6 +92,15 @@ hb_status hb_manhattan(hb_domain d, const uint8_t* states, int64_t n, int32_t* o
 typedef struct hb_pdb hb_pdb;
 hb_status hb_pdb_build_corner(int k, int threads, hb_pdb** out);
 hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out); /* host */
+/* Distribution of the table's values (the Discussion's objective for a learned
+ * heuristic is its mean value at bounded size; this gives the same statistic
+ * for the PDB): counts[v] = number of reachable entries equal to v for
+ * v < n_counts (host int64 [n_counts], caller-owned; larger values are not
+ * counted) and *max_value (nullable) = the largest value.  Indices no cube
+ * state maps to are left out (for k = 8 the table indexes all 3^8 twists, of
+ * which a third occur).  HB_E_INVAL on a null pdb, n_counts < 1 or a null
+ * counts. */
+hb_status hb_pdb_value_counts(const hb_pdb* pdb, int64_t* counts, int32_t n_counts, int32_t* max_value);
 void hb_pdb_free(hb_pdb* pdb); /* NULL-safe */
 
 /* --------------------------------------------------------------- model */

@@ -104,6 +104,7 @@ def lib():
             "hb_manhattan": ([C.c_int, vp, i64, vp], C.c_int),
             "hb_pdb_build_corner": ([C.c_int, C.c_int, C.POINTER(vp)], C.c_int),
             "hb_pdb_lookup": ([vp, vp, i64, vp], C.c_int),
+            "hb_pdb_value_counts": ([vp, vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "hb_pdb_free": ([vp], None),
             "hb_model_load": ([C.c_char_p, C.POINTER(ModelOpts), C.POINTER(vp)], C.c_int),
             "hb_model_load_ensemble": ([C.POINTER(C.c_char_p), C.c_int, C.c_int, C.POINTER(ModelOpts), C.POINTER(vp)],
@@ -214,6 +215,13 @@ class Pdb:
         out = np.zeros(s.shape[0], dtype=np.int32)
         _check(lib().hb_pdb_lookup(self.handle, _np_ptr(s), s.shape[0], _np_ptr(out)))
         return out
+
+    def value_counts(self, n=32):
+        """(counts of the entries holding each value 0..n-1, largest value)."""
+        counts = np.zeros(n, dtype=np.int64)
+        vmax = C.c_int32(0)
+        _check(lib().hb_pdb_value_counts(self.handle, _np_ptr(counts), n, C.byref(vmax)))
+        return counts, vmax.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1,4 +1,5 @@
 // C ABI entry points (include/hb.h): argument checks, error text, dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -119,6 +120,20 @@ hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int
         if (!valid_state(*D, states + i * 54, &why)) return fail(HB_E_INVAL, "state %lld: %s", (long long)i, why);
         out[i] = pdb->corner.lookup(states + i * 54);
     }
+    return HB_OK;
+}
+
+hb_status hb_pdb_value_counts(const hb_pdb* pdb, int64_t* counts, int32_t n_counts, int32_t* max_value) {
+    if (!pdb) return fail(HB_E_INVAL, "null pdb");
+    if (n_counts < 1 || !counts) return fail(HB_E_INVAL, "bad counts buffer");
+    std::fill(counts, counts + n_counts, int64_t{0});
+    int vmax = 0;
+    for (uint8_t v : pdb->corner.table) {
+        if (v == 255) continue;  // unreachable index (for k = 8 the last twist is implied)
+        if (v < n_counts) counts[v]++;
+        vmax = std::max(vmax, (int)v);
+    }
+    if (max_value) *max_value = vmax;
     return HB_OK;
 }
 

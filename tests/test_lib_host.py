@@ -133,3 +133,51 @@ def test_model_load_rejects_bad_files(tmp_path):
     p.write_bytes(b"XXXX" + bytes(40))
     with pytest.raises(hb.HBError, match="magic"):
         hb.Model(str(p))
+
+
+def _golden(name):
+    """key value pairs of a fixture under tests/golden (comments after '#')."""
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+def test_corner_pdb_statistics_match_published_values():
+    """The library's 8-corner PDB against the published entry count, largest
+    value and mean; a wrong move table or corner index changes all three."""
+    g = _golden("corner_pdb_8.txt")
+    pdb = hb.Pdb(8)
+    counts, vmax = pdb.value_counts(16)
+    pdb.close()
+    assert counts.sum() == g["entries"]
+    assert vmax == g["max_value"]
+    mean = (counts * np.arange(16)).sum() / counts.sum()
+    assert round(mean, 3) == g["mean_value"]
+    assert counts[0] == 1 and counts[1] == 18  # the goal; one entry per face turn
+
+
+def test_corner_pdb_distribution_matches_oracle_table():
+    """4-corner PDB: the library's value distribution equals the oracle's table."""
+    tab, reached = O.corner_pdb(4)
+    pdb = hb.Pdb(4)
+    counts, vmax = pdb.value_counts(16)
+    pdb.close()
+    ref = np.bincount(tab[tab != 255].astype(np.int64), minlength=16)
+    np.testing.assert_array_equal(counts, ref[:16])
+    assert counts.sum() == reached and vmax == int(tab[tab != 255].max())
+
+
+def test_defaults_follow_paper_settings():
+    g = _golden("paper_settings.txt")
+    p = hb.default_params()
+    assert p.timeout_us == g["batch_timeout_us"]
+    assert p.batch_size == g["target_batch_cube"]
+    pdb = hb.Pdb(int(g["classic_cube_pdb_corners"]))  # the largest corner PDB the library builds
+    pdb.close()
+    with pytest.raises(hb.HBError):
+        hb.Pdb(int(g["classic_cube_pdb_corners"]) + 1)
