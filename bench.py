@@ -255,6 +255,27 @@ def main():
         search["counts_equal_across_precisions"] = (
             search["f32"]["per_iteration"][:-1] == search["bf16"]["per_iteration"][:-1] == search["fp8"]["per_iteration"][:-1])
 
+        # the same start, pruned by an additive PDB (the paper's classic sliding-tile
+        # heuristic, here the 6-6-3 split of tiles 1-6, 7-12, 13-15)
+        t0 = time.time()
+        apdb = hb.Pdb(groups=[range(1, 7), range(7, 13), range(13, 16)])
+        apdb_s = time.time() - t0
+        sp = {"workload": "same start, fixed-tree Batch IDA* pruned by the 6-6-3 additive PDB, work_num 64, "
+                          "1M expansions", "pdb_build_s": apdb_s}
+        for name in ("f32", "bf16", "fp8"):
+            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0)
+            r = hb.cbdfs_solve(hb.HB_STP4, start, model=models[name], combine=hb.HB_H_FIXED_TREE,
+                               classic=hb.HB_CLASSIC_PDB, pdb=apdb, threads=threads, params=p, raise_on_error=False)
+            sp[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
+                        "expanded": r["expanded"], "wall_s": r["wall_s"], "mean_batch": r["mean_batch"],
+                        "gpu_us_per_batch": r["gpu_busy_s"] / max(1, r["batches"]) * 1e6, "status": r["status"],
+                        "cost": r["cost"],
+                        "per_iteration": [[i["bound"], i["expanded"], i["generated"]] for i in r["iters"]]}
+            log(f"[bench] search (6-6-3 PDB) {name}: {sp[name]['nodes_per_s']:.3e} nodes/s, mean batch "
+                f"{r['mean_batch']:.0f}, status {r['status']}, cost {r['cost']}")
+        apdb.close()
+        search["additive_pdb"] = sp
+
         # cube: classifier network (324 -> 2000 -> 1000 -> 4 residual blocks -> 21, quantile 0.99),
         # Batch BTS in fixed-tree mode pruning with the 8-corner PDB, batch 4000, workNum 32,
         # 300K expansions

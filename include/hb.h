@@ -91,6 +91,19 @@ hb_status hb_manhattan(hb_domain d, const uint8_t* states, int64_t n, int32_t* o
  * the host with `threads` threads (<= 0: all cores).  Owned by the library. */
 typedef struct hb_pdb hb_pdb;
 hb_status hb_pdb_build_corner(int k, int threads, hb_pdb** out);
+/* Additive pattern database of the 15-puzzle (the paper's classic sliding-tile
+ * heuristic is the sum of the 1-7 and 8-15 tile PDBs, Experimental Setup):
+ * group_of_tile[t] (host int32 [16]; t = 1..15, entry 0 ignored) puts tile t
+ * into one of n disjoint groups 0..n-1 of 1..8 tiles.  Group g's table holds,
+ * for every placement of its tiles, the fewest moves of those tiles that bring
+ * them to their goal cells when the other tiles move for free, minimised over
+ * the blank's cell; h(s) = sum over the groups (admissible and of the
+ * Manhattan distance's parity).  Host memory while building the largest group
+ * of k tiles: 16!/(16-k)! x 17 bytes (8 tiles: 8.8 GB).  HB_E_INVAL on a bad
+ * grouping. */
+hb_status hb_pdb_build_stp_additive(const int32_t* group_of_tile, int threads, hb_pdb** out);
+/* h of n states (host in, host int32 out): cube states for a corner PDB,
+ * 15-puzzle states for an additive PDB. */
 hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out); /* host */
 /* Distribution of the table's values (the Discussion's objective for a learned
  * heuristic is its mean value at bounded size; this gives the same statistic
@@ -98,8 +111,8 @@ hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int
  * v < n_counts (host int64 [n_counts], caller-owned; larger values are not
  * counted) and *max_value (nullable) = the largest value.  Indices no cube
  * state maps to are left out (for k = 8 the table indexes all 3^8 twists, of
- * which a third occur).  HB_E_INVAL on a null pdb, n_counts < 1 or a null
- * counts. */
+ * which a third occur).  For an additive PDB the counts run over the entries of
+ * all group tables.  HB_E_INVAL on a null pdb, n_counts < 1 or a null counts. */
 hb_status hb_pdb_value_counts(const hb_pdb* pdb, int64_t* counts, int32_t n_counts, int32_t* max_value);
 void hb_pdb_free(hb_pdb* pdb); /* NULL-safe */
 
@@ -322,7 +335,7 @@ typedef struct {
     hb_model* model;       /* required unless combine is CLASSIC or CLASSIC_BATCHED */
     hb_combine combine;
     hb_classic classic;
-    const hb_pdb* pdb;     /* for HB_CLASSIC_PDB */
+    const hb_pdb* pdb;     /* for HB_CLASSIC_PDB: a corner PDB (cube) or an additive PDB (15-puzzle) */
 } hb_heuristic;
 
 typedef struct {

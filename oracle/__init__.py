@@ -38,7 +38,8 @@ def _p(a, t):
 
 class HSpec(C.Structure):
     _fields_ = [("kind", C.c_int), ("table8", C.POINTER(C.c_int32)), ("pdb_k", C.c_int),
-                ("pdb", C.POINTER(C.c_uint8))]
+                ("pdb", C.POINTER(C.c_uint8)), ("apdb_groups", C.c_int), ("apdb_tiles", C.POINTER(C.c_int32)),
+                ("apdb_tables", C.POINTER(C.c_uint8))]
 
 
 class Iter(C.Structure):
@@ -67,6 +68,8 @@ def _declare(L):
     L.orc_corner_k_size.argtypes = [C.c_int]
     L.orc_corner_k_size.restype = C.c_int64
     L.orc_corner_k_index_batch.argtypes = [vp, C.c_int64, C.c_int, vp]
+    L.orc_apdb_group.argtypes = [C.c_int, vp, vp]
+    L.orc_apdb_h_batch.argtypes = [vp, C.c_int64, C.c_int, vp, vp, vp]
     L.orc_bf16_round_array.argtypes = [vp, C.c_int64, vp]
     L.orc_e4m3_round_array.argtypes = [vp, C.c_int64, vp]
     L.orc_e4m3_decode.argtypes = [C.c_int]
@@ -156,6 +159,33 @@ def corner_pdb(k):
     t = np.zeros(size, dtype=np.uint8)
     reached = lib().orc_corner_pdb(k, t.ctypes.data)
     return t, reached
+
+
+def apdb(groups):
+    """Additive 15-puzzle PDB (groups of at most 4 tiles): (tiles [G][4] with -1
+    padding, tables [G][65536]) for apdb_h and the searches."""
+    G = len(groups)
+    tiles = np.full((G, 4), -1, dtype=np.int32)
+    tables = np.full((G, 65536), 255, dtype=np.uint8)
+    for g, ts in enumerate(groups):
+        ts = sorted(int(t) for t in ts)
+        if not 1 <= len(ts) <= 4:
+            raise ValueError("groups of 1 to 4 tiles")
+        tiles[g, :len(ts)] = ts
+        t = np.zeros(16 ** len(ts), dtype=np.uint8)
+        if not lib().orc_apdb_group(len(ts), tiles[g].ctypes.data, t.ctypes.data):
+            raise ValueError("bad group")
+        tables[g, :t.size] = t
+    return tiles, tables
+
+
+def apdb_h(states, spec):
+    tiles, tables = spec
+    s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 16)
+    out = np.zeros(s.shape[0], dtype=np.int32)
+    lib().orc_apdb_h_batch(s.ctypes.data, s.shape[0], tiles.shape[0], tiles.ctypes.data, tables.ctypes.data,
+                           out.ctypes.data)
+    return out
 
 
 def corner_index(states, k):
@@ -314,13 +344,19 @@ def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 
 # ----------------------------------------------------------------- search
-H_ZERO, H_MD, H_TABLE8, H_PDB = 0, 1, 2, 3
+H_ZERO, H_MD, H_TABLE8, H_PDB, H_APDB = 0, 1, 2, 3, 4
 
 
-def _hspec(kind, table8=None, pdb=None, pdb_k=0):
+def _hspec(kind, table8=None, pdb=None, pdb_k=0, apdb=None):
     hs = HSpec()
     hs.kind = kind
     keep = []
+    if apdb is not None:
+        tiles, tables = apdb
+        keep += [tiles, tables]
+        hs.apdb_groups = tiles.shape[0]
+        hs.apdb_tiles = _p(tiles, C.c_int32)
+        hs.apdb_tables = _p(tables, C.c_uint8)
     if table8 is not None:
         t = np.ascontiguousarray(table8, dtype=np.int32)
         keep.append(t)
@@ -338,8 +374,8 @@ def _iters(arr, n):
 
 
 def ida(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, complete_final=False,
-        max_iters=200, node_limit=-1):
-    hs, keep = _hspec(hkind, table8, pdb, pdb_k)
+        max_iters=200, node_limit=-1, apdb=None):
+    hs, keep = _hspec(hkind, table8, pdb, pdb_k, apdb)
     s = np.ascontiguousarray(start, dtype=np.uint8)
     arr = (Iter * max_iters)()
     n = C.c_int(0)
@@ -354,8 +390,8 @@ def ida(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, complete_fina
 
 
 def bts(domain, start, hkind=H_MD, table8=None, pdb=None, pdb_k=0, b0=10000, c1=2, c2=8, plus_one=True,
-        max_iters=400, max_total=-1):
-    hs, keep = _hspec(hkind, table8, pdb, pdb_k)
+        max_iters=400, max_total=-1, apdb=None):
+    hs, keep = _hspec(hkind, table8, pdb, pdb_k, apdb)
     s = np.ascontiguousarray(start, dtype=np.uint8)
     arr = (Iter * max_iters)()
     n = C.c_int(0)

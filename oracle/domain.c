@@ -374,3 +374,97 @@ int orc_corner_k_index_batch(const uint8_t* s, int64_t n, int k, int64_t* out) {
     for (int64_t i = 0; i < n; i++) if (!orc_corner_k_index(s + i * 54, k, out + i)) return 0;
     return 1;
 }
+
+/* ------------------------------------------------------------------------
+ * Additive pattern database of the 15-puzzle (the paper's classic
+ * sliding-tile heuristic, Experimental Setup), for test-sized groups of at
+ * most 4 tiles.  A group's abstract state is the cells of its tiles plus the
+ * blank's cell, coded densely as digits base 16 (tile i's cell is digit i, the
+ * blank the top digit).  Moving the blank into a cell that holds none of the
+ * group's tiles costs 0; sliding one of the group's tiles into the blank costs
+ * 1.  Distances from the goal come from a 0-1 breadth-first search with one
+ * bucket per distance; the table keeps, per placement of the tiles, the least
+ * distance over the blank's cells (255 where two tiles share a cell).
+ * ---------------------------------------------------------------------- */
+int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
+    if (k < 1 || k > 4) return 0;
+    int64_t n_place = 1;
+    for (int i = 0; i < k; i++) n_place *= 16;
+    const int64_t n_state = n_place * 16;
+    uint8_t* dist = (uint8_t*)malloc((size_t)n_state);
+    memset(dist, 255, (size_t)n_state);
+    /* buckets[d] = states first reached at distance d (a state may appear in
+       a later bucket too; stale copies are skipped) */
+    int64_t* bucket[256];
+    int64_t fill[256], cap[256];
+    for (int d = 0; d < 256; d++) { bucket[d] = NULL; fill[d] = 0; cap[d] = 0; }
+    int64_t goal = 0, mul = 1;
+    for (int i = 0; i < k; i++) { goal += (int64_t)tiles[i] * mul; mul *= 16; }
+    goal += 0 * n_place; /* blank at cell 0 */
+    dist[goal] = 0;
+    cap[0] = 1024; bucket[0] = (int64_t*)malloc(sizeof(int64_t) * 1024); bucket[0][fill[0]++] = goal;
+    for (int d = 0; d < 255; d++) {
+        for (int64_t q = 0; q < fill[d]; q++) {
+            const int64_t st = bucket[d][q];
+            if (dist[st] != d) continue;
+            int cell[4];
+            int64_t rest = st;
+            for (int i = 0; i < k; i++) { cell[i] = (int)(rest % 16); rest /= 16; }
+            const int blank = (int)rest;
+            const int br = blank / 4, bc = blank % 4;
+            const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+            for (int m = 0; m < 4; m++) {
+                const int r = br + dr[m], c = bc + dc[m];
+                if (r < 0 || r > 3 || c < 0 || c > 3) continue;
+                const int nb = r * 4 + c;
+                int who = -1;
+                for (int i = 0; i < k; i++) if (cell[i] == nb) who = i;
+                int ncell[4];
+                for (int i = 0; i < k; i++) ncell[i] = cell[i];
+                int step = 0;
+                if (who >= 0) { ncell[who] = blank; step = 1; }
+                int64_t ns = 0, mm = 1;
+                for (int i = 0; i < k; i++) { ns += (int64_t)ncell[i] * mm; mm *= 16; }
+                ns += (int64_t)nb * n_place;
+                const int nd = d + step;
+                if (dist[ns] <= nd) continue;
+                dist[ns] = (uint8_t)nd;
+                if (fill[nd] == cap[nd]) {
+                    cap[nd] = cap[nd] ? 2 * cap[nd] : 1024;
+                    bucket[nd] = (int64_t*)realloc(bucket[nd], sizeof(int64_t) * (size_t)cap[nd]);
+                }
+                bucket[nd][fill[nd]++] = ns;
+            }
+        }
+        free(bucket[d]);
+        bucket[d] = NULL;
+    }
+    for (int64_t p = 0; p < n_place; p++) {
+        uint8_t best = 255;
+        for (int b = 0; b < 16; b++) if (dist[p + (int64_t)b * n_place] < best) best = dist[p + (int64_t)b * n_place];
+        table[p] = best;
+    }
+    free(dist);
+    return 1;
+}
+
+/* h of a 15-puzzle state under an additive PDB: groups of at most 4 tiles,
+ * tiles[g*4 + i] (-1 past the group's end), tables[g * 65536 + code] with
+ * code = sum over the group's tiles of cell * 16^i. */
+int orc_apdb_h(const uint8_t* s, int n_groups, const int32_t* tiles, const uint8_t* tables) {
+    int where[16];
+    for (int c = 0; c < 16; c++) where[s[c]] = c;
+    int h = 0;
+    for (int g = 0; g < n_groups; g++) {
+        int64_t code = 0, mul = 1;
+        for (int i = 0; i < 4 && tiles[g * 4 + i] >= 0; i++) { code += (int64_t)where[tiles[g * 4 + i]] * mul; mul *= 16; }
+        h += tables[(int64_t)g * 65536 + code];
+    }
+    return h;
+}
+
+int orc_apdb_h_batch(const uint8_t* s, int64_t n, int n_groups, const int32_t* tiles, const uint8_t* tables,
+                     int32_t* out) {
+    for (int64_t i = 0; i < n; i++) out[i] = orc_apdb_h(s + i * 16, n_groups, tiles, tables);
+    return 1;
+}

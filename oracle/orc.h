@@ -21,6 +21,7 @@ void orc_goal(int domain, uint8_t* out);
 int orc_manhattan(int domain, const uint8_t* s);
 int64_t orc_perm9_rank(const uint8_t* s);
 int orc_corner_k_index(const uint8_t* s, int k, int64_t* idx);
+int orc_apdb_h(const uint8_t* s, int n_groups, const int32_t* tiles, const uint8_t* tables);
 
 /* mlp.c */
 #define ORC_MAXT 64

@@ -35,10 +35,14 @@
 #include "orc.h"
 
 typedef struct {
-    int kind;                /* 0 zero, 1 Manhattan, 2 table over 8-puzzle ranks, 3 corner PDB */
+    int kind;                /* 0 zero, 1 Manhattan, 2 table over 8-puzzle ranks, 3 corner PDB,
+                                4 additive 15-puzzle PDB */
     const int32_t* table8;   /* kind 2: h by perm9 rank */
     int pdb_k;               /* kind 3 */
     const uint8_t* pdb;
+    int apdb_groups;         /* kind 4: groups of at most 4 tiles (see orc_apdb_h) */
+    const int32_t* apdb_tiles;
+    const uint8_t* apdb_tables;
 } orc_hspec;
 
 typedef struct {
@@ -54,6 +58,7 @@ static int h_of(int d, const orc_hspec* h, const uint8_t* s) {
     case 1: return orc_manhattan(d, s);
     case 2: return h->table8[orc_perm9_rank(s)];
     case 3: { int64_t i; orc_corner_k_index(s, h->pdb_k, &i); return h->pdb[i]; }
+    case 4: return orc_apdb_h(s, h->apdb_groups, h->apdb_tiles, h->apdb_tables);
     default: return 0;
     }
 }

@@ -105,6 +105,7 @@ def lib():
             "hb_pdb_build_corner": ([C.c_int, C.c_int, C.POINTER(vp)], C.c_int),
             "hb_pdb_lookup": ([vp, vp, i64, vp], C.c_int),
             "hb_pdb_value_counts": ([vp, vp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+            "hb_pdb_build_stp_additive": ([vp, C.c_int, C.POINTER(vp)], C.c_int),
             "hb_pdb_free": ([vp], None),
             "hb_model_load": ([C.c_char_p, C.POINTER(ModelOpts), C.POINTER(vp)], C.c_int),
             "hb_model_load_ensemble": ([C.POINTER(C.c_char_p), C.c_int, C.c_int, C.POINTER(ModelOpts), C.POINTER(vp)],
@@ -202,16 +203,27 @@ def hb_manhattan(domain, states):
 
 
 class Pdb:
-    """Corner pattern database built by the library (host memory)."""
+    """Pattern database built by the library (host memory): the cube's k-corner
+    PDB, or (groups=...) an additive 15-puzzle PDB."""
 
-    def __init__(self, k, threads=0):
+    def __init__(self, k=None, threads=0, groups=None):
+        """k: corners of a cube PDB; groups: tile groups of an additive 15-puzzle
+        PDB, e.g. [range(1, 8), range(8, 16)] for the 7-8 split."""
         h = C.c_void_p()
-        _check(lib().hb_pdb_build_corner(k, threads, C.byref(h)))
+        if groups is not None:
+            g = np.full(16, -1, dtype=np.int32)
+            for i, tiles in enumerate(groups):
+                for t in tiles:
+                    g[int(t)] = i
+            _check(lib().hb_pdb_build_stp_additive(_np_ptr(g), threads, C.byref(h)))
+        else:
+            _check(lib().hb_pdb_build_corner(k, threads, C.byref(h)))
         self.handle = h
         self.k = k
+        self.groups = groups
 
     def lookup(self, states):
-        s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 54)
+        s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 16 if self.groups is not None else 54)
         out = np.zeros(s.shape[0], dtype=np.int32)
         _check(lib().hb_pdb_lookup(self.handle, _np_ptr(s), s.shape[0], _np_ptr(out)))
         return out

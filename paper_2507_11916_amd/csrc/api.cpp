@@ -111,14 +111,34 @@ hb_status hb_pdb_build_corner(int k, int threads, hb_pdb** out) {
     return HB_OK;
 }
 
+hb_status hb_pdb_build_stp_additive(const int32_t* group_of_tile, int threads, hb_pdb** out) {
+    if (!out) return fail(HB_E_INVAL, "null output");
+    if (!group_of_tile) return fail(HB_E_INVAL, "null grouping");
+    hb_pdb* p = new (std::nothrow) hb_pdb;
+    if (!p) return fail(HB_E_NOMEM, "pdb");
+    p->kind = 1;
+    try {
+        if (!stp_apdb_build(group_of_tile, threads, &p->stp)) {
+            delete p;
+            return fail(HB_E_INVAL, "tiles 1..15 must form groups 0..n-1 of 1 to 8 tiles");
+        }
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(HB_E_NOMEM, "pattern database table");
+    }
+    *out = p;
+    return HB_OK;
+}
+
 hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out) {
     if (!pdb) return fail(HB_E_INVAL, "null pdb");
     if (n < 0 || (n > 0 && (!states || !out))) return fail(HB_E_INVAL, "bad buffers or count");
-    const Domain* D = domain_of(HB_RUBIK3);
+    const Domain* D = domain_of(pdb->kind == 0 ? HB_RUBIK3 : HB_STP4);
+    const int sb = D->state_bytes;
     for (int64_t i = 0; i < n; i++) {
         const char* why = "";
-        if (!valid_state(*D, states + i * 54, &why)) return fail(HB_E_INVAL, "state %lld: %s", (long long)i, why);
-        out[i] = pdb->corner.lookup(states + i * 54);
+        if (!valid_state(*D, states + i * sb, &why)) return fail(HB_E_INVAL, "state %lld: %s", (long long)i, why);
+        out[i] = pdb->kind == 0 ? pdb->corner.lookup(states + i * sb) : pdb->stp.lookup(states + i * sb);
     }
     return HB_OK;
 }
@@ -128,11 +148,16 @@ hb_status hb_pdb_value_counts(const hb_pdb* pdb, int64_t* counts, int32_t n_coun
     if (n_counts < 1 || !counts) return fail(HB_E_INVAL, "bad counts buffer");
     std::fill(counts, counts + n_counts, int64_t{0});
     int vmax = 0;
-    for (uint8_t v : pdb->corner.table) {
-        if (v == 255) continue;  // unreachable index (for k = 8 the last twist is implied)
-        if (v < n_counts) counts[v]++;
-        vmax = std::max(vmax, (int)v);
-    }
+    auto add = [&](const std::vector<uint8_t>& table) {
+        for (uint8_t v : table) {
+            if (v == 255) continue;  // unreachable index (for k = 8 corners the last twist is implied)
+            if (v < n_counts) counts[v]++;
+            vmax = std::max(vmax, (int)v);
+        }
+    };
+    if (pdb->kind == 0) add(pdb->corner.table);
+    else
+        for (const auto& t : pdb->stp.tables) add(t);
     if (max_value) *max_value = vmax;
     return HB_OK;
 }

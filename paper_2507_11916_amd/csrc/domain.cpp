@@ -406,4 +406,188 @@ bool corner_pdb_build(int k, int threads, CornerPdb* out) {
     return true;
 }
 
+// ------------------------------------------------------------ 15-puzzle additive PDB
+// Placement of k tiles: digit i is tile i's cell counted among the cells not
+// taken by tiles 0..i-1 (mixed radix 16, 15, ...), rank = digits in that radix.
+static int64_t placement_count(int k) {
+    int64_t n = 1;
+    for (int i = 0; i < k; i++) n *= 16 - i;
+    return n;
+}
+
+static int64_t placement_rank(int k, const int* cell) {
+    int64_t r = 0;
+    uint32_t used = 0;
+    for (int i = 0; i < k; i++) {
+        const int d = cell[i] - __builtin_popcount(used & ((1u << cell[i]) - 1));
+        r = r * (16 - i) + d;
+        used |= 1u << cell[i];
+    }
+    return r;
+}
+
+static void placement_unrank(int k, int64_t r, int* cell) {
+    int d[8];
+    for (int i = k - 1; i >= 0; i--) {
+        d[i] = (int)(r % (16 - i));
+        r /= 16 - i;
+    }
+    uint32_t used = 0;
+    for (int i = 0; i < k; i++) {
+        int c = 0, left = d[i];
+        for (;; c++) {
+            if (used & (1u << c)) continue;
+            if (left-- == 0) break;
+        }
+        cell[i] = c;
+        used |= 1u << c;
+    }
+}
+
+static inline bool lower_to(uint8_t* p, uint8_t v) {  // atomic min; true if the cell was unset
+    uint8_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (cur > v) {
+        if (__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) return cur == 255;
+    }
+    return false;
+}
+
+// Breadth-first over (placement, blank cell) in levels of pattern-tile moves.
+// A level-c pass takes each placement with a cell at distance c, spreads c
+// over the blank's region of free cells (blank moves into free cells cost
+// nothing) and gives c + 1 to the placements one tile move away.  Distances
+// only decrease to their final values, with atomic minima between threads.
+static void build_group(const std::vector<int>& tiles, int threads, std::vector<uint8_t>* table) {
+    const int k = (int)tiles.size();
+    const int64_t n = placement_count(k);
+    std::vector<uint8_t> dist((size_t)n * 16, 255);
+    uint8_t* D = dist.data();
+    {
+        int cell[8];
+        for (int i = 0; i < k; i++) cell[i] = tiles[i];  // tile t's home is cell t
+        const int64_t r = placement_rank(k, cell);
+        // the blank's region from cell 0 in the goal placement
+        uint32_t occ = 0;
+        for (int i = 0; i < k; i++) occ |= 1u << cell[i];
+        uint32_t region = 1u, frontier = 1u;
+        while (frontier) {
+            uint32_t next = 0;
+            for (int b = 0; b < 16; b++) {
+                if (!(frontier & (1u << b))) continue;
+                const int row = b >> 2, col = b & 3;
+                if (row > 0) next |= 1u << (b - 4);
+                if (row < 3) next |= 1u << (b + 4);
+                if (col > 0) next |= 1u << (b - 1);
+                if (col < 3) next |= 1u << (b + 1);
+            }
+            next &= ~occ & ~region;
+            region |= next;
+            frontier = next;
+        }
+        for (int b = 0; b < 16; b++)
+            if (region & (1u << b)) D[r * 16 + b] = 0;
+    }
+    for (int c = 0; c < 254; c++) {
+        std::atomic<int64_t> added{0};
+        auto work = [&](int64_t lo, int64_t hi) {
+            int64_t local = 0;
+            int cell[8];
+            for (int64_t r = lo; r < hi; r++) {
+                uint8_t* row = D + r * 16;
+                uint32_t at_c = 0;
+                for (int b = 0; b < 16; b++)
+                    if (__atomic_load_n(&row[b], __ATOMIC_RELAXED) == c) at_c |= 1u << b;
+                if (!at_c) continue;
+                placement_unrank(k, r, cell);
+                uint32_t occ = 0;
+                int tile_at[16];
+                for (int b = 0; b < 16; b++) tile_at[b] = -1;
+                for (int i = 0; i < k; i++) {
+                    occ |= 1u << cell[i];
+                    tile_at[cell[i]] = i;
+                }
+                // spread c over the free cells reachable from the level-c cells
+                uint32_t region = at_c & ~occ, frontier = region;
+                while (frontier) {
+                    uint32_t next = 0;
+                    for (int b = 0; b < 16; b++) {
+                        if (!(frontier & (1u << b))) continue;
+                        const int rr = b >> 2, cc = b & 3;
+                        if (rr > 0) next |= 1u << (b - 4);
+                        if (rr < 3) next |= 1u << (b + 4);
+                        if (cc > 0) next |= 1u << (b - 1);
+                        if (cc < 3) next |= 1u << (b + 1);
+                    }
+                    next &= ~occ & ~region;
+                    region |= next;
+                    frontier = next;
+                }
+                for (int b = 0; b < 16; b++)
+                    if ((region & (1u << b)) && lower_to(&row[b], (uint8_t)c)) local++;
+                // one pattern-tile move: the tile next to the blank slides into it
+                for (int b = 0; b < 16; b++) {
+                    if (!(region & (1u << b))) continue;
+                    const int rr = b >> 2, cc = b & 3;
+                    const int nb4[4] = {rr > 0 ? b - 4 : -1, rr < 3 ? b + 4 : -1, cc > 0 ? b - 1 : -1,
+                                        cc < 3 ? b + 1 : -1};
+                    for (int e = 0; e < 4; e++) {
+                        const int t = nb4[e] < 0 ? -1 : tile_at[nb4[e]];
+                        if (t < 0) continue;
+                        int moved[8];
+                        for (int i = 0; i < k; i++) moved[i] = cell[i];
+                        moved[t] = b;  // the tile takes the blank's cell, the blank takes the tile's
+                        const int64_t nr = placement_rank(k, moved);
+                        if (lower_to(&D[nr * 16 + nb4[e]], (uint8_t)(c + 1))) local++;
+                    }
+                }
+            }
+            added += local;
+        };
+        std::vector<std::thread> pool;
+        const int64_t chunk = (n + threads - 1) / threads;
+        for (int t = 0; t < threads; t++) {
+            const int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+            if (lo < hi) pool.emplace_back(work, lo, hi);
+        }
+        for (auto& th : pool) th.join();
+        if (added.load() == 0) break;
+    }
+    table->assign((size_t)n, 255);
+    for (int64_t r = 0; r < n; r++) {
+        uint8_t m = 255;
+        for (int b = 0; b < 16; b++) m = std::min(m, D[r * 16 + b]);
+        (*table)[r] = m;
+    }
+}
+
+bool stp_apdb_build(const int32_t* group_of_tile, int threads, StpApdb* out) {
+    if (!group_of_tile) return false;
+    int n_groups = 0;
+    for (int t = 1; t < 16; t++) {
+        if (group_of_tile[t] < 0 || group_of_tile[t] > 14) return false;
+        n_groups = std::max(n_groups, group_of_tile[t] + 1);
+    }
+    out->tiles.assign(n_groups, {});
+    for (int t = 1; t < 16; t++) out->tiles[group_of_tile[t]].push_back(t);
+    for (auto& g : out->tiles)
+        if (g.empty() || g.size() > 8) return false;
+    if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    out->tables.assign(n_groups, {});
+    for (int g = 0; g < n_groups; g++) build_group(out->tiles[g], threads, &out->tables[g]);
+    return true;
+}
+
+int StpApdb::lookup(const uint8_t* s) const {
+    int where[16];
+    for (int c = 0; c < 16; c++) where[s[c]] = c;
+    int h = 0;
+    for (size_t g = 0; g < tiles.size(); g++) {
+        int cell[8];
+        const int k = (int)tiles[g].size();
+        for (int i = 0; i < k; i++) cell[i] = where[tiles[g][i]];
+        h += tables[g][placement_rank(k, cell)];
+    }
+    return h;
+}
+
 }  // namespace hb

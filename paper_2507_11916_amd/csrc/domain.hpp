@@ -49,9 +49,24 @@ struct CornerPdb {
 };
 bool corner_pdb_build(int k, int threads, CornerPdb* out);
 
+// Additive (disjoint) pattern database of the 15-puzzle: tiles split into
+// groups; table g holds, per placement of group g's tiles, the fewest moves of
+// those tiles that bring them home (other tiles' moves free), minimised over
+// the blank's cell.  h = sum over the groups.
+struct StpApdb {
+    std::vector<std::vector<int>> tiles;        // tiles of each group, ascending
+    std::vector<std::vector<uint8_t>> tables;   // per group, indexed by placement rank
+    int lookup(const uint8_t* s) const;
+};
+// group_of_tile[t] for t = 1..15 (entry 0 ignored): group 0..n-1, every group
+// non-empty and at most 8 tiles.  Returns false on a bad grouping.
+bool stp_apdb_build(const int32_t* group_of_tile, int threads, StpApdb* out);
+
 }  // namespace hb
 
 // Opaque handle of include/hb.h.
 struct hb_pdb {
+    int kind = 0;  // 0 cube corners, 1 15-puzzle additive
     hb::CornerPdb corner;
+    hb::StpApdb stp;
 };

@@ -215,7 +215,7 @@ static int32_t real_bits(float v) {
 int Shared::classic_h(const uint8_t* s) const {
     switch (classic) {
         case HB_CLASSIC_MD: return manhattan(*D, s);
-        case HB_CLASSIC_PDB: return pdb->corner.lookup(s);
+        case HB_CLASSIC_PDB: return pdb->kind == 0 ? pdb->corner.lookup(s) : pdb->stp.lookup(s);
         default: return 0;
     }
 }
@@ -947,7 +947,9 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     S->sh.model = h->model;
     if ((int)h->combine < 0 || (int)h->combine > 5) return fail(HB_E_INVAL, "unknown combine mode");
     if (h->classic == HB_CLASSIC_MD && d == HB_RUBIK3) return fail(HB_E_INVAL, "Manhattan distance needs a sliding tile");
-    if (h->classic == HB_CLASSIC_PDB && (!h->pdb || d != HB_RUBIK3)) return fail(HB_E_INVAL, "PDB heuristic needs a cube and a pdb");
+    if (h->classic == HB_CLASSIC_PDB &&
+        (!h->pdb || !((h->pdb->kind == 0 && d == HB_RUBIK3) || (h->pdb->kind == 1 && d == HB_STP4))))
+        return fail(HB_E_INVAL, "PDB heuristic needs a corner PDB for the cube or an additive PDB for the 15-puzzle");
     const bool nn = h->combine == HB_H_NN || h->combine == HB_H_MIN_NN_CLASSIC || h->combine == HB_H_FIXED_TREE ||
                     h->combine == HB_H_NN_REAL;
     if (nn) {

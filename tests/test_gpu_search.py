@@ -73,6 +73,28 @@ def test_stp4_fixed_tree_matches_oracle(net_files, prec):
         assert np.array_equal(_follow(1, s, r["path"]), O.goal(1))
 
 
+@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16])
+def test_stp4_fixed_tree_additive_pdb_matches_oracle(net_files, prec):
+    """The paper's fixed-tree setting for the sliding tile: the network is
+    evaluated on every generated state while the additive PDB prunes; counts
+    per completed iteration equal the oracle's IDA* with its own table."""
+    groups = [range(1, 5), range(5, 9), range(9, 13), range(13, 16)]
+    pdb = hb.Pdb(groups=groups)
+    spec = O.apdb(groups)
+    m = hb.Model(net_files["stp4_res"], prec=prec, combine_md=True, max_batch=8000)
+    for s in synth.stp_walks(4, synth.config_seeds(2, 3), lengths=60):
+        p = hb.default_params(batch_size=1000, work_num=32)
+        r = hb.cbdfs_solve(1, s, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                           threads=16, params=p)
+        o = O.ida(1, s, hkind=O.H_APDB, apdb=spec)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"][:-1])
+        assert r["evals"] >= r["generated"] - 10 ** 5
+        assert np.array_equal(_follow(1, s, r["path"]), O.goal(1))
+    m.close()
+    pdb.close()
+
+
 def test_stp4_min_nn_manhattan_is_optimal(net_files):
     m = hb.Model(net_files["stp4_res"], prec=hb.HB_BF16, combine_md=True)
     for s in synth.stp_walks(4, synth.config_seeds(2, 3), lengths=40):

@@ -181,3 +181,23 @@ def test_defaults_follow_paper_settings():
     pdb.close()
     with pytest.raises(hb.HBError):
         hb.Pdb(int(g["classic_cube_pdb_corners"]) + 1)
+
+
+def test_additive_stp_pdb_matches_oracle():
+    """The library's additive 15-puzzle PDB (its own ranking and level-parallel
+    build) equals the oracle's (dense codes, 0-1 breadth-first search)."""
+    groups = [range(1, 5), range(5, 9), range(9, 13), range(13, 16)]
+    spec = O.apdb(groups)
+    st = synth.stp_walks(4, synth.throughput_seeds(3000, 31), lengths=200)
+    pdb = hb.Pdb(groups=groups)
+    np.testing.assert_array_equal(pdb.lookup(st), O.apdb_h(st, spec))
+    counts, vmax = pdb.value_counts(64)
+    assert counts.sum() == 3 * 16 * 15 * 14 * 13 + 16 * 15 * 14  # placements of 4-4-4-3 tiles
+    pdb.close()
+
+
+def test_additive_stp_pdb_rejects_bad_groupings():
+    with pytest.raises(hb.HBError):
+        hb.Pdb(groups=[range(1, 10), range(10, 16)])  # a group of 9 tiles
+    with pytest.raises(hb.HBError):
+        hb.Pdb(groups=[range(1, 8)])  # tiles 8..15 in no group

@@ -182,3 +182,53 @@ def test_permutation_rank_is_a_bijection_on_small_sample():
     for p in itertools.islice(itertools.permutations(range(9)), 5000):
         seen.add(O.lib().orc_perm9_rank(np.array(p, dtype=np.uint8).ctypes.data))
     assert len(seen) == 5000 and max(seen) < 362880
+
+
+# ------------------------------------------------ 15-puzzle additive PDB
+def test_additive_pdb_of_single_tiles_is_manhattan_distance():
+    """A one-tile pattern with free blank moves costs exactly the tile's
+    Manhattan distance, so fifteen singleton groups give MD itself."""
+    spec = O.apdb([[t] for t in range(1, 16)])
+    st = synth.stp_walks(4, synth.config_seeds(8, 300), lengths=200)
+    np.testing.assert_array_equal(O.apdb_h(st, spec), O.manhattan(O.STP4, st))
+
+
+def test_additive_pdb_counts_a_linear_conflict():
+    """Tiles 1 and 2 swapped in their goal row: each is one step from home, but
+    one must leave the row and come back, so the two-tile pattern costs MD + 2."""
+    g = O.goal(O.STP4).copy()
+    g[1], g[2] = g[2], g[1]
+    spec = O.apdb([[1, 2]])
+    assert O.manhattan(O.STP4, g[None])[0] == 2
+    assert O.apdb_h(g[None], spec)[0] == 4
+
+
+def test_additive_pdb_dominates_md_and_keeps_its_parity():
+    """Each pattern's cost counts its own tiles' moves, each of which changes
+    those tiles' Manhattan distance by one: h >= MD, h = MD (mod 2), and one move
+    changes h by an odd amount.  (Minimised over the blank's cell the table is
+    admissible but not consistent: a move can change it by 3.)"""
+    spec = O.apdb([range(1, 5), range(5, 9), range(9, 13), range(13, 16)])
+    st = synth.stp_walks(4, synth.config_seeds(8, 200), lengths=200)
+    h, md = O.apdb_h(st, spec), O.manhattan(O.STP4, st)
+    assert np.all(h >= md) and np.all((h - md) % 2 == 0)
+    assert O.apdb_h(O.goal(O.STP4)[None], spec)[0] == 0
+    for s in st[:60]:
+        hs = O.apdb_h(s[None], spec)[0]
+        for m in range(4):
+            c = O.apply(O.STP4, s, m)
+            if c is not None:
+                assert (int(O.apdb_h(c[None], spec)[0]) - int(hs)) % 2 == 1
+
+
+def test_additive_pdb_is_admissible_and_keeps_ida_optimal():
+    """On short walks: h <= the optimal cost (IDA* with Manhattan distance), and
+    IDA* with the additive PDB finds the same cost expanding no more nodes."""
+    spec = O.apdb([range(1, 5), range(5, 9), range(9, 13), range(13, 16)])
+    for s in synth.stp_walks(4, synth.config_seeds(8, 12), lengths=36):
+        r_md = O.ida(O.STP4, s, hkind=O.H_MD)
+        r_pd = O.ida(O.STP4, s, hkind=O.H_APDB, apdb=spec)
+        assert r_md["status"] == 1 and r_pd["status"] == 1
+        assert O.apdb_h(s[None], spec)[0] <= r_md["cost"]
+        assert r_pd["cost"] == r_md["cost"]
+        assert sum(i["expanded"] for i in r_pd["iters"]) <= sum(i["expanded"] for i in r_md["iters"])

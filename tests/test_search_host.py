@@ -76,6 +76,39 @@ def test_cube_pdb_ida_matches_oracle():
         assert r["generated"] / max(1, r["expanded"]) < 18
 
 
+def test_stp4_additive_pdb_ida_and_bts_match_oracle():
+    """Batch IDA* and Batch BTS pruning with the additive 15-puzzle PDB (the
+    paper's classic sliding-tile heuristic) against the oracle's searches with
+    its own table of the same tile groups: costs and per-iteration counts."""
+    groups = [range(1, 5), range(5, 9), range(9, 13), range(13, 16)]
+    pdb = hb.Pdb(groups=groups, threads=4)
+    spec = O.apdb(groups)
+    for s in synth.stp_walks(4, synth.config_seeds(2, 5), lengths=60):
+        p = hb.default_params(batch_size=1000, work_num=8, complete_final_iter=1)
+        r = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_PDB, pdb=pdb, threads=8,
+                           params=p)
+        o = O.ida(1, s, hkind=O.H_APDB, apdb=spec, complete_final=True)
+        assert r["cost"] == o["cost"]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
+        assert np.array_equal(_follow(1, s, r["path"]), O.goal(1))
+        p = hb.default_params(batch_size=1000, work_num=8, bts_b0=500)
+        rb = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                            algo=hb.HB_BTS, threads=8, params=p)
+        ob = O.bts(1, s, hkind=O.H_APDB, apdb=spec, b0=500)
+        assert rb["cost"] == ob["cost"] == o["cost"]
+        assert [(i["bound"], i["limit"], i["complete"]) for i in rb["iters"]] == \
+               [(i["bound"], i["limit"], i["complete"]) for i in ob["iters"]]
+    pdb.close()
+
+
+def test_pdb_kind_must_match_domain():
+    pdb = hb.Pdb(groups=[range(1, 5), range(5, 9), range(9, 13), range(13, 16)], threads=4)
+    r = hb.cbdfs_solve(2, O.goal(2), combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                       threads=2, raise_on_error=False)
+    assert r["status"] == hb.HB_E_INVAL
+    pdb.close()
+
+
 @pytest.mark.parametrize("b0", [1, 100, 10000])
 def test_bts_matches_oracle_search_sequence(bfs, b0):
     for s in synth.stp3_instances(12):
