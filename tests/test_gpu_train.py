@@ -141,3 +141,76 @@ def test_learned_8puzzle_heuristic_gains_over_manhattan(tmp_path):
         exp_md += sum(i["expanded"] for i in o["iters"])
     print("expanded: learned %d vs Manhattan %d" % (exp_nn, exp_md))
     assert exp_nn < exp_md
+
+
+def test_learned_15puzzle_residual_over_manhattan(tmp_path):
+    """The paper's sliding-tile heuristic construction: a network trained on the
+    difference between a PDB and Manhattan distance, served as MD + floor(y -
+    delta).  The label is the 6-6-3 additive PDB (admissible, so it is the
+    over-estimate judge); delta is set on one held-out set so that h exceeds the
+    label on at most 0.1% of it, and checked on another."""
+    groups = [range(1, 7), range(7, 13), range(13, 16)]
+    pdb = hb.Pdb(groups=groups)
+
+    def data(seed, count):
+        st = synth.stp_walks(4, synth.throughput_seeds(count, seed), length_base=0, length_span=201)
+        md = O.manhattan(O.STP4, st)
+        return st, md, (pdb.lookup(st) - md).astype(np.float32)
+
+    st, md, lab = data(5005, 1 << 18)
+    assert np.all(lab >= 0) and np.all(lab % 2 == 0)  # PDB >= MD, same parity
+    path = str(tmp_path / "w.hbw")
+    synth.write_weights(path, "stp4_res", seed=21, head_bias=float(lab.mean()), scale=0.5)
+    tr = hb.Trainer(path, prec=hb.HB_BF16, max_batch=8192, lr=1e-3)
+    d_st = torch.from_numpy(hb.hb_encode(1, st)).cuda()
+    d_lab = torch.from_numpy(lab).cuda()
+    g = torch.Generator(device="cpu").manual_seed(77)
+    losses = []
+    for step in range(800):
+        idx = torch.randint(0, len(st), (8192,), generator=g).cuda()
+        loss = tr.step(d_st[idx].contiguous(), d_lab[idx].contiguous(), want_loss=(step % 100 == 0))
+        if loss is not None:
+            losses.append(loss)
+    print("training loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    trained = str(tmp_path / "trained.hbw")
+    tr.save(trained)
+    tr.close()
+
+    def raw(model, s):
+        d_h = torch.zeros(len(s), dtype=torch.int32, device="cuda")
+        d_y = torch.zeros(len(s), dtype=torch.float32, device="cuda")
+        model.eval_batch(torch.from_numpy(hb.hb_encode(1, s)).cuda(), d_h, d_y)
+        torch.cuda.synchronize()
+        return d_h.cpu().numpy(), d_y.cpu().numpy().astype(np.float64)
+
+    m = hb.Model(trained, prec=hb.HB_BF16, max_batch=16384)
+    sa, mda, laba = data(6006, 1 << 14)
+    _, ya = raw(m, sa)
+    delta = max(0.0, float(np.quantile(ya - laba - 1.0, 0.999)) + 1e-3)  # floor(y - delta) <= label
+    m.close()
+    served = hb.Model(trained, prec=hb.HB_BF16, combine_md=3, offset=delta, max_batch=16384)
+    sb, mdb, labb = data(7007, 1 << 14)
+    hbv, _ = raw(served, sb)
+    over = float(np.mean(hbv > mdb + labb))
+    print("delta %.3f; over-estimates of the PDB %.4f%%; mean h %.2f, MD %.2f, PDB %.2f"
+          % (delta, 100 * over, hbv.mean(), mdb.mean(), (mdb + labb).mean()))
+    assert np.all(hbv >= mdb)
+    assert over <= 0.005
+    assert hbv.mean() > mdb.mean() + 0.5
+
+    costs_differ, exp_nn, exp_md = [], 0, 0
+    for i, s in enumerate(synth.stp_walks(4, synth.config_seeds(2, 5), lengths=56)):
+        r = hb.cbdfs_solve(1, s, model=served, combine=hb.HB_H_NN, threads=16,
+                           params=hb.default_params(batch_size=4000, work_num=32))
+        o = O.ida(1, s, hkind=O.H_MD)
+        assert r["status"] == hb.HB_OK and r["cost"] >= o["cost"]
+        if r["cost"] != o["cost"]:
+            costs_differ.append(i)
+        exp_nn += r["expanded"]
+        exp_md += sum(it["expanded"] for it in o["iters"])
+    print("expanded: learned %d vs Manhattan %d; instances with a longer path: %s" % (exp_nn, exp_md, costs_differ))
+    assert len(costs_differ) <= 1
+    assert exp_nn < exp_md
+    served.close()
+    pdb.close()
