@@ -227,6 +227,12 @@ def main():
         results[name]["h_agree_fp64"] = agree[name]
         results[name]["max_abs_dy_fp64"] = float(np.abs(results[name]["_y"][sample] - y64).max())
 
+    # the other configurations' networks: evals/s of the cube classifier at batch
+    # 8000 per precision (with h agreement against the FP64 oracle on a sample),
+    # and the 8-puzzle network at the serial search's batch of 64 and over all
+    # 181,440 states
+    other = other_configs(args, hb, synth, netcfg, O, torch, stream, tmp)
+
     # search nodes/s: Batch IDA* on a 15-puzzle start (200-move walk), fixed-tree
     # mode (network evaluated on every generated state, Manhattan pruning), at
     # each precision; a budget of 1M expansions each.  workNum (subtrees per
@@ -410,10 +416,85 @@ def main():
         "precisions": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
         "mfma_frac": {k: results[k]["evals_per_s"] * flops_eval / 1e12 / PEAK_TFLOPS[k] for k in results},
         "end_to_end_evals_per_s_pcie": B / e2e_ms * 1e3,
+        "other_configs": other,
         "search": search,
         "training": training,
     }
     print(json.dumps(line))
+
+
+def puzzle8_states():
+    """The 181,440 solvable 8-puzzle states in lexicographic (rank) order: the
+    permutations of 0..8 whose tiles (blank excluded) have an even number of
+    inversions."""
+    import itertools
+    perms = np.array(list(itertools.permutations(range(9))), dtype=np.uint8)
+    inv = np.zeros(len(perms), dtype=np.int64)
+    for i in range(9):
+        for j in range(i + 1, 9):
+            inv += (perms[:, i] > perms[:, j]) & (perms[:, j] != 0)
+    return perms[inv % 2 == 0]
+
+
+def other_configs(args, hb, synth, netcfg, O, torch, stream, tmp):
+    def time_eval(m, d_in, d_out, steps):
+        for _ in range(5):
+            m.eval_batch(d_in, d_out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            m.eval_batch(d_in, d_out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps  # ms
+
+    out = {}
+    # cube: classifier 324 -> 2000 -> 1000 -> 4 residual blocks -> 21, quantile 0.99,
+    # 8000 states from walks of 20-30 turns
+    CB = 8000
+    cpath = os.path.join(tmp, "rc_cls.hbw")
+    synth.write_weights(cpath, "rc_cls", **netcfg.DEFAULTS["rc_cls"])
+    cst = hb.hb_apply_moves(hb.HB_RUBIK3, synth.rc_walk_moves_array(synth.throughput_seeds(CB), length_base=20,
+                                                                    length_span=11))
+    ccal = hb.hb_apply_moves(hb.HB_RUBIK3, synth.rc_walk_moves_array(synth.throughput_seeds(4096, 4243),
+                                                                     length_base=20, length_span=11))
+    d_c = torch.from_numpy(hb.hb_encode(hb.HB_RUBIK3, cst)).cuda()
+    d_ch = torch.zeros(CB, dtype=torch.int32, device="cuda")
+    sample = np.arange(0, CB, CB // 256)[:256]
+    cnet = O.Net(cpath)
+    h64 = cnet.h(cnet.forward(cst[sample]), hb.HB_OUT_CLS_QUANTILE, q=0.99)
+    cube = {"workload": "cube classifier 324-2000-1000-4x(1000,1000)-21, quantile 0.99, batch 8000, "
+                        "states from 20-30 turn walks"}
+    for name, prec in (("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)):
+        m = hb.Model(cpath, prec=prec, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=CB)
+        if prec == hb.HB_FP8_E4M3:
+            m.calibrate(torch.from_numpy(hb.hb_encode(hb.HB_RUBIK3, ccal)).cuda())
+        m.tune(d_c)
+        ms = time_eval(m, d_c, d_ch, max(20, args.steps // 4))
+        h = d_ch.cpu().numpy()
+        cube[name] = {"ms_per_step": ms, "evals_per_s": CB / ms * 1e3,
+                      "mfma_frac": CB / ms * 1e3 * m.flops_per_eval / 1e12 / PEAK_TFLOPS[name],
+                      "h_agree_fp64": float((h[sample] == h64).mean()), "tile": m.tile_for(CB)}
+        log(f"[bench] cube net {name}: {cube[name]['evals_per_s']:.3e} evals/s, MFMA "
+            f"{cube[name]['mfma_frac']:.3f}, h agreement {cube[name]['h_agree_fp64']:.3f}")
+        m.close()
+    out["cube_classifier"] = cube
+    # 8-puzzle: 81 -> 128 -> 128 -> 1, h = min(floor(y), MD), FP32
+    spath = os.path.join(tmp, "stp3_small.hbw")
+    synth.write_weights(spath, "stp3_small", **netcfg.DEFAULTS["stp3_small"])
+    allst = puzzle8_states()
+    d_all = torch.from_numpy(hb.hb_encode(hb.HB_STP3, allst)).cuda()
+    d_ah = torch.zeros(len(allst), dtype=torch.int32, device="cuda")
+    m = hb.Model(spath, prec=hb.HB_FP32, combine_md=True, max_batch=len(allst))
+    us64 = time_eval(m, d_all[:64], d_ah[:64], 200) * 1e3
+    ms_all = time_eval(m, d_all, d_ah, 20)
+    out["puzzle8"] = {"workload": "8-puzzle net 81-128-128-1, FP32, min(floor(y), MD)",
+                      "us_per_batch_64": us64, "evals_per_s_all_181440": len(allst) / ms_all * 1e3}
+    log(f"[bench] 8-puzzle net: {us64:.1f} us per batch of 64, {len(allst) / ms_all * 1e3:.3e} evals/s "
+        f"over all 181,440 states")
+    m.close()
+    return out
 
 
 def library_gemm(args, torch):
