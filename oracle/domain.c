@@ -392,6 +392,7 @@ int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
     for (int i = 0; i < k; i++) n_place *= 16;
     const int64_t n_state = n_place * 16;
     uint8_t* dist = (uint8_t*)malloc((size_t)n_state);
+    if (!dist) return 0;
     memset(dist, 255, (size_t)n_state);
     /* buckets[d] = states first reached at distance d (a state may appear in
        a later bucket too; stale copies are skipped) */
@@ -402,7 +403,9 @@ int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
     for (int i = 0; i < k; i++) { goal += (int64_t)tiles[i] * mul; mul *= 16; }
     goal += 0 * n_place; /* blank at cell 0 */
     dist[goal] = 0;
-    cap[0] = 1024; bucket[0] = (int64_t*)malloc(sizeof(int64_t) * 1024); bucket[0][fill[0]++] = goal;
+    cap[0] = 1024; bucket[0] = (int64_t*)malloc(sizeof(int64_t) * 1024);
+    if (!bucket[0]) { free(dist); return 0; }
+    bucket[0][fill[0]++] = goal;
     for (int d = 0; d < 255; d++) {
         for (int64_t q = 0; q < fill[d]; q++) {
             const int64_t st = bucket[d][q];
@@ -431,7 +434,13 @@ int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
                 dist[ns] = (uint8_t)nd;
                 if (fill[nd] == cap[nd]) {
                     cap[nd] = cap[nd] ? 2 * cap[nd] : 1024;
-                    bucket[nd] = (int64_t*)realloc(bucket[nd], sizeof(int64_t) * (size_t)cap[nd]);
+                    int64_t* grown = (int64_t*)realloc(bucket[nd], sizeof(int64_t) * (size_t)cap[nd]);
+                    if (!grown) {
+                        for (int e = 0; e < 256; e++) free(bucket[e]);
+                        free(dist);
+                        return 0;
+                    }
+                    bucket[nd] = grown;
                 }
                 bucket[nd][fill[nd]++] = ns;
             }

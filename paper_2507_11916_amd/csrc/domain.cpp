@@ -363,6 +363,7 @@ int CornerPdb::lookup(const uint8_t* s) const {
 bool corner_pdb_build(int k, int threads, CornerPdb* out) {
     if (k < 1 || k > 8) return false;
     if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    threads = std::min(threads, 256);
     out->k = k;
     out->size = corner_size(k);
     out->table.assign((size_t)out->size, 255);
@@ -572,6 +573,7 @@ bool stp_apdb_build(const int32_t* group_of_tile, int threads, StpApdb* out) {
     for (auto& g : out->tiles)
         if (g.empty() || g.size() > 8) return false;
     if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    threads = std::min(threads, 256);
     out->tables.assign(n_groups, {});
     for (int g = 0; g < n_groups; g++) build_group(out->tiles[g], threads, &out->tables[g]);
     return true;
