@@ -377,7 +377,8 @@ bool corner_pdb_build(int k, int threads, CornerPdb* out) {
             int64_t local = 0;
             int pos[8], tw[8], np[8], nt[8];
             for (int64_t r = lo; r < hi; r++) {
-                if (T[r] != depth) continue;
+                // other threads fill level depth + 1 meanwhile: read atomically
+                if (__atomic_load_n(&T[r], __ATOMIC_RELAXED) != depth) continue;
                 corner_unrank(k, r, pos, tw);
                 for (int m = 0; m < 18; m++) {
                     for (int j = 0; j < k; j++) {
