@@ -345,7 +345,10 @@ typedef struct {
                               with at least 1024*threads*work_num work units, capped near 3M tree nodes) */
     int timeout_us;        /* partial-batch flush timeout (default 4000, the paper's 4 ms) */
     int n_slabs;           /* batch buffers kept in host memory (default 4) */
-    int flush_when_idle;   /* also flush as soon as every search thread waits on h (default 1) */
+    int flush_when_idle;   /* 1 (default): also flush as soon as every search thread waits on h;
+                              2: also flush whenever the batch thread is free (a batch then holds
+                              what arrived while the previous one was evaluated); 0: only a full
+                              slab or the timeout */
     int64_t node_limit;    /* total expansions (<= 0: none) */
     double time_limit_s;   /* wall limit (<= 0: none) */
     int64_t bts_b0;        /* BTS first budget (default 10000) */

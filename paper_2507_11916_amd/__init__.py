@@ -219,6 +219,7 @@ class Pdb:
         else:
             _check(lib().hb_pdb_build_corner(k, threads, C.byref(h)))
         self.handle = h
+        self._free = lib().hb_pdb_free
         self.k = k
         self.groups = groups
 
@@ -236,8 +237,10 @@ class Pdb:
         return counts, vmax.value
 
     def close(self):
+        # the free function is bound at creation: at interpreter exit the
+        # module's globals may already be gone when __del__ runs
         if getattr(self, "handle", None):
-            lib().hb_pdb_free(self.handle)
+            self._free(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -261,6 +264,7 @@ class Model:
         else:
             _check(lib().hb_model_load(os.fsencode(path), C.byref(o), C.byref(h)))
         self.handle = h
+        self._free = lib().hb_model_free
         self.opts = o
         info = ModelInfo()
         _check(lib().hb_model_get_info(h, C.byref(info)))
@@ -270,8 +274,10 @@ class Model:
         self.n_act = info.n_act
 
     def close(self):
+        # the free function is bound at creation: at interpreter exit the
+        # module's globals may already be gone when __del__ runs
         if getattr(self, "handle", None):
-            lib().hb_model_free(self.handle)
+            self._free(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -348,11 +354,14 @@ class Trainer:
         h = C.c_void_p()
         _check(lib().hb_trainer_create(path.encode(), C.byref(o), C.byref(h)))
         self.handle = h
+        self._free = lib().hb_trainer_free
         self.n_params = lib().hb_trainer_n_params(h)
 
     def close(self):
+        # the free function is bound at creation: at interpreter exit the
+        # module's globals may already be gone when __del__ runs
         if getattr(self, "handle", None):
-            lib().hb_trainer_free(self.handle)
+            self._free(self.handle)
             self.handle = None
 
     def __del__(self):

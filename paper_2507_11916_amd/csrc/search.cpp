@@ -89,8 +89,11 @@ struct Shared;
 
 class Batcher {
 public:
-    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, bool idle_flush, bool graphs)
-        : sh_(sh), cap_(cap), timeout_(timeout_s), idle_flush_(idle_flush), use_graphs_(graphs), n_slabs_(n_slabs) {}
+    // flush_mode: 0 full slab or timeout; 1 also when every search thread
+    // waits on h; 2 also whenever the batch thread is free (eager).
+    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, int flush_mode, bool graphs)
+        : sh_(sh), cap_(cap), timeout_(timeout_s), idle_flush_(flush_mode >= 1), eager_(flush_mode >= 2),
+          use_graphs_(graphs), n_slabs_(n_slabs) {}
     hb_status init();
     void start();
     void stop();
@@ -144,7 +147,7 @@ private:
     Shared* sh_;
     int cap_;
     double timeout_;
-    bool idle_flush_;
+    bool idle_flush_, eager_;
     bool use_graphs_;
     int n_slabs_;
     std::vector<std::unique_ptr<Slab>> slabs_;
@@ -417,7 +420,9 @@ void Batcher::loop() {
                 const bool full = cur_->reserved == cap_;
                 const double left = cur_->t_first + timeout_ - now_s();
                 const bool idle = idle_flush_ && all_idle();
-                if (full || left <= 0 || idle || draining_) break;
+                // eager: the GPU is free now, so whatever arrived while it
+                // evaluated the previous batch goes at once
+                if (full || left <= 0 || idle || eager_ || draining_) break;
                 // Poll briefly first (a sleeping batch thread adds a wake-up
                 // to every round trip), then sleep until notified by reserve()
                 // (full slab), mark_idle() or thread_done(), or the timeout.
@@ -934,7 +939,8 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     cbdfs_params P;
     cbdfs_params_default(&P);
     if (p_in) P = *p_in;
-    if (P.batch_size < 1 || P.work_num < 1 || P.n_slabs < 2 || P.timeout_us < 0 || P.max_iters < 1)
+    if (P.batch_size < 1 || P.work_num < 1 || P.n_slabs < 2 || P.timeout_us < 0 || P.max_iters < 1 ||
+        P.flush_when_idle < 0 || P.flush_when_idle > 2)
         return fail(HB_E_INVAL, "bad parameters");
     if (algo == HB_BTS && (P.bts_b0 < 1 || P.bts_c1 < 1 || P.bts_c2 <= P.bts_c1))
         return fail(HB_E_INVAL, "bad BTS parameters (need b0 >= 1, c2 > c1 >= 1)");
@@ -969,7 +975,7 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     if (S->sh.uses_batches) {
         int cap = P.batch_size;
         if (nn) cap = std::min(cap, h->model->opts.max_batch);
-        S->batcher = std::make_unique<Batcher>(&S->sh, cap, P.n_slabs, P.timeout_us * 1e-6, P.flush_when_idle != 0,
+        S->batcher = std::make_unique<Batcher>(&S->sh, cap, P.n_slabs, P.timeout_us * 1e-6, P.flush_when_idle,
                                                P.use_graphs != 0);
         hb_status st = S->batcher->init();
         if (st != HB_OK) return st;

@@ -46,11 +46,14 @@ def test_8puzzle_ida_matches_oracle(bfs, mode):
         assert np.array_equal(_follow(0, s, r["path"]), O.goal(0))
 
 
-@pytest.mark.parametrize("threads,work_num,d_init,batch", [(1, 1, 0, 1), (3, 2, 2, 7), (8, 8, -1, 500), (16, 3, 6, 64)])
-def test_stp4_counts_independent_of_parallel_shape(threads, work_num, d_init, batch):
+@pytest.mark.parametrize("threads,work_num,d_init,batch,flush", [(1, 1, 0, 1, 1), (3, 2, 2, 7, 1), (8, 8, -1, 500, 1),
+                                                                  (16, 3, 6, 64, 1), (8, 8, -1, 500, 2),
+                                                                  (4, 4, -1, 100, 0)])
+def test_stp4_counts_independent_of_parallel_shape(threads, work_num, d_init, batch, flush):
     st = synth.stp_walks(4, [11, 12, 13], lengths=44)
     for s in st:
-        p = hb.default_params(batch_size=batch, work_num=work_num, d_init=d_init, timeout_us=1000)
+        p = hb.default_params(batch_size=batch, work_num=work_num, d_init=d_init, timeout_us=1000,
+                              flush_when_idle=flush)
         r = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_MD, threads=threads, params=p)
         o = O.ida(1, s, hkind=O.H_MD)
         assert r["cost"] == o["cost"]
@@ -99,6 +102,13 @@ def test_stp4_additive_pdb_ida_and_bts_match_oracle():
         assert [(i["bound"], i["limit"], i["complete"]) for i in rb["iters"]] == \
                [(i["bound"], i["limit"], i["complete"]) for i in ob["iters"]]
     pdb.close()
+
+
+def test_flush_mode_out_of_range_is_rejected():
+    s = synth.stp_walks(4, [11], lengths=20)[0]
+    r = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_MD, threads=2,
+                       params=hb.default_params(flush_when_idle=3), raise_on_error=False)
+    assert r["status"] == hb.HB_E_INVAL
 
 
 def test_pdb_kind_must_match_domain():
