@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the benchmark line: evals/s and fixed-tree search nodes/s of the 15-puzzle "
                          "net at several hidden widths (same depth) and each precision; prints its own JSON line")
+    ap.add_argument("--stp-pdb", default="663", choices=["663", "78"],
+                    help="additive PDB of the 15-puzzle search leg: the 6-6-3 split (seconds to build) or the "
+                         "paper's 7-8 split (minutes and about 9 GB of host memory to build)")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -262,11 +265,15 @@ def main():
             search["f32"]["per_iteration"][:-1] == search["bf16"]["per_iteration"][:-1] == search["fp8"]["per_iteration"][:-1])
 
         # the same start, pruned by an additive PDB (the paper's classic sliding-tile
-        # heuristic, here the 6-6-3 split of tiles 1-6, 7-12, 13-15)
+        # heuristic: by default the 6-6-3 split of tiles 1-6, 7-12, 13-15; --stp-pdb 78
+        # for the paper's 1-7 / 8-15 split)
+        split = {"663": [range(1, 7), range(7, 13), range(13, 16)], "78": [range(1, 8), range(8, 16)]}[args.stp_pdb]
         t0 = time.time()
-        apdb = hb.Pdb(groups=[range(1, 7), range(7, 13), range(13, 16)])
+        apdb = hb.Pdb(groups=split)
         apdb_s = time.time() - t0
-        sp = {"workload": "same start, fixed-tree Batch IDA* pruned by the 6-6-3 additive PDB, work_num 64, "
+        label = "6-6-3" if args.stp_pdb == "663" else "7-8"
+        log(f"[bench] {label} additive PDB built in {apdb_s:.1f} s")
+        sp = {"workload": f"same start, fixed-tree Batch IDA* pruned by the {label} additive PDB, work_num 64, "
                           "1M expansions", "pdb_build_s": apdb_s}
         for name in ("f32", "bf16", "fp8"):
             p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0)
@@ -277,7 +284,7 @@ def main():
                         "gpu_us_per_batch": r["gpu_busy_s"] / max(1, r["batches"]) * 1e6, "status": r["status"],
                         "cost": r["cost"],
                         "per_iteration": [[i["bound"], i["expanded"], i["generated"]] for i in r["iters"]]}
-            log(f"[bench] search (6-6-3 PDB) {name}: {sp[name]['nodes_per_s']:.3e} nodes/s, mean batch "
+            log(f"[bench] search ({label} PDB) {name}: {sp[name]['nodes_per_s']:.3e} nodes/s, mean batch "
                 f"{r['mean_batch']:.0f}, status {r['status']}, cost {r['cost']}")
         apdb.close()
         search["additive_pdb"] = sp
