@@ -201,3 +201,31 @@ def test_additive_stp_pdb_rejects_bad_groupings():
         hb.Pdb(groups=[range(1, 10), range(10, 16)])  # a group of 9 tiles
     with pytest.raises(hb.HBError):
         hb.Pdb(groups=[range(1, 8)])  # tiles 8..15 in no group
+
+
+def test_pdb_entry_points_reject_bad_arguments():
+    """Error statuses of the PDB calls, through the C ABI with raw arguments."""
+    import ctypes as C
+    L = hb.lib()
+    out = C.c_void_p()
+    assert L.hb_pdb_build_stp_additive(None, 1, C.byref(out)) == hb.HB_E_INVAL
+    g = np.full(16, -1, dtype=np.int32)
+    g[1:] = 0  # fifteen tiles in one group: more than 8
+    assert L.hb_pdb_build_stp_additive(g.ctypes.data, 1, C.byref(out)) == hb.HB_E_INVAL
+    assert "groups" in L.hb_last_error().decode()
+    counts = np.zeros(4, dtype=np.int64)
+    assert L.hb_pdb_value_counts(None, counts.ctypes.data, 4, None) == hb.HB_E_INVAL
+    pdb = hb.Pdb(3, threads=2)
+    assert L.hb_pdb_value_counts(pdb.handle, counts.ctypes.data, 0, None) == hb.HB_E_INVAL
+    assert L.hb_pdb_value_counts(pdb.handle, None, 4, None) == hb.HB_E_INVAL
+    # a short buffer counts only the values that fit
+    assert L.hb_pdb_value_counts(pdb.handle, counts.ctypes.data, 4, None) == hb.HB_OK
+    full, vmax = pdb.value_counts(32)
+    np.testing.assert_array_equal(counts, full[:4])
+    assert vmax >= 4 and full.sum() == 8 * 7 * 6 * 27
+    # lookups of states that are not 15-puzzle permutations are rejected
+    apdb = hb.Pdb(groups=[range(1, 5), range(5, 9), range(9, 13), range(13, 16)], threads=2)
+    with pytest.raises(hb.HBError):
+        apdb.lookup(np.zeros((1, 16), dtype=np.uint8))
+    apdb.close()
+    pdb.close()
