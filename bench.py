@@ -75,6 +75,10 @@ def main():
     ap.add_argument("--stp-pdb", default="663", choices=["663", "78"],
                     help="additive PDB of the 15-puzzle search leg: the 6-6-3 split (seconds to build) or the "
                          "paper's 7-8 split (minutes and about 9 GB of host memory to build)")
+    ap.add_argument("--search-batches", default=None, choices=["f32", "bf16", "fp8"],
+                    help="instead of the benchmark line: only a short 15-puzzle search (fixed tree, Manhattan "
+                         "pruning, work_num 8, 100K expansions) at this precision, for a profiler's timeline of "
+                         "the batches")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -143,6 +147,21 @@ def main():
 
     if args.size_sweep:
         size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp)
+        return
+    if args.search_batches:
+        prec = {"f32": hb.HB_FP32, "bf16": hb.HB_BF16, "fp8": hb.HB_FP8_E4M3}[args.search_batches]
+        m = hb.Model(wpath, prec=prec, combine_md=True, max_batch=16384)
+        if prec == hb.HB_FP8_E4M3:
+            m.calibrate(torch.from_numpy(hb.hb_encode(hb.HB_STP4, synth.stp_walks(
+                4, synth.throughput_seeds(4096, 4242), lengths=200))).cuda())
+        p = hb.default_params(batch_size=8000, work_num=8, node_limit=100_000, time_limit_s=20.0)
+        r = hb.cbdfs_solve(hb.HB_STP4, synth.stp4_instances(1)[0], model=m, combine=hb.HB_H_FIXED_TREE,
+                           classic=hb.HB_CLASSIC_MD, threads=min(32, max(4, len(os.sched_getaffinity(0)))),
+                           params=p, raise_on_error=False)
+        print(json.dumps({"search_batches": args.search_batches, "batches": r["batches"], "mean_batch": r["mean_batch"],
+                          "gpu_us_per_batch": r["gpu_busy_s"] / max(1, r["batches"]) * 1e6,
+                          "wall_us_per_batch": r["wall_s"] / max(1, r["batches"]) * 1e6}))
+        m.close()
         return
 
     results = {}
