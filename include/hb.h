@@ -105,9 +105,9 @@ hb_status hb_pdb_build_stp_additive(const int32_t* group_of_tile, int threads, h
 /* h of n states (host in, host int32 out): cube states for a corner PDB,
  * 15-puzzle states for an additive PDB. */
 hb_status hb_pdb_lookup(const hb_pdb* pdb, const uint8_t* states, int64_t n, int32_t* out); /* host */
-/* Distribution of the table's values (the Discussion's objective for a learned
- * heuristic is its mean value at bounded size; this gives the same statistic
- * for the PDB): counts[v] = number of reachable entries equal to v for
+/* Distribution of the table's values (the appendix comparing Batch IDA* with
+ * AIDA* states the objective for a learned heuristic as the largest mean value
+ * at bounded size; this gives the same statistic for the PDB): counts[v] = number of reachable entries equal to v for
  * v < n_counts (host int64 [n_counts], caller-owned; larger values are not
  * counted) and *max_value (nullable) = the largest value.  Indices no cube
  * state maps to are left out (for k = 8 the table indexes all 3^8 twists, of
