@@ -214,3 +214,86 @@ def test_learned_15puzzle_residual_over_manhattan(tmp_path):
     assert exp_nn < exp_md
     served.close()
     pdb.close()
+
+
+def test_sliding_tile_heuristic_as_group_residual_ensemble(tmp_path):
+    """The paper's sliding-tile heuristic: Manhattan distance plus one learned
+    residual per tile group of an additive PDB (there 1-7 and 8-15; here the
+    6-6-3 split), the members summed.  Member g is trained on PDB_g - MD_g (a
+    PDB of group g with one-tile groups for the other tiles, which contribute
+    exactly their Manhattan distance); the three are served fused as
+    MD + floor(y_1 + y_2 + y_3 - delta)."""
+    split = [range(1, 7), range(7, 13), range(13, 16)]
+    member_pdbs = []
+    for g in split:
+        others = [[t] for t in range(1, 16) if t not in g]
+        member_pdbs.append(hb.Pdb(groups=[g] + others))
+    total = hb.Pdb(groups=split)
+
+    def data(seed, count):
+        st = synth.stp_walks(4, synth.throughput_seeds(count, seed), length_base=0, length_span=201)
+        md = O.manhattan(O.STP4, st)
+        res = [(p.lookup(st) - md).astype(np.float32) for p in member_pdbs]
+        return st, md, res, (total.lookup(st) - md).astype(np.float32)
+
+    st, md, res, tot = data(5005, 1 << 18)
+    np.testing.assert_array_equal(sum(res), tot)  # the residuals of the groups add up to the whole PDB's
+    d_st = torch.from_numpy(hb.hb_encode(1, st)).cuda()
+    g = torch.Generator(device="cpu").manual_seed(91)
+    paths = []
+    for i, lab in enumerate(res):
+        path = str(tmp_path / f"m{i}.hbw")
+        synth.write_weights(path, "stp4_res", seed=40 + i, head_bias=float(lab.mean()), scale=0.5)
+        tr = hb.Trainer(path, prec=hb.HB_BF16, max_batch=8192, lr=1e-3)
+        d_lab = torch.from_numpy(lab).cuda()
+        first = last = None
+        for step in range(600):
+            idx = torch.randint(0, len(st), (8192,), generator=g).cuda()
+            loss = tr.step(d_st[idx].contiguous(), d_lab[idx].contiguous(), want_loss=(step % 100 == 0))
+            if loss is not None:
+                first = loss if first is None else first
+                last = loss
+        print("member", i, "loss", first, "->", last)
+        assert last < 0.5 * first
+        trained = str(tmp_path / f"t{i}.hbw")
+        tr.save(trained)
+        tr.close()
+        paths.append(trained)
+
+    def run(model, s):
+        d_h = torch.zeros(len(s), dtype=torch.int32, device="cuda")
+        d_y = torch.zeros(len(s), dtype=torch.float32, device="cuda")
+        model.eval_batch(torch.from_numpy(hb.hb_encode(1, s)).cuda(), d_h, d_y)
+        torch.cuda.synchronize()
+        return d_h.cpu().numpy(), d_y.cpu().numpy().astype(np.float64)
+
+    raw = hb.Model(paths, prec=hb.HB_BF16, ensemble_rule=hb.HB_ENSEMBLE_SUM, max_batch=16384)
+    sa, _, _, tota = data(6006, 1 << 14)
+    _, ya = run(raw, sa)
+    raw.close()
+    delta = max(0.0, float(np.quantile(ya - tota - 1.0, 0.999)) + 1e-3)
+    served = hb.Model(paths, prec=hb.HB_BF16, ensemble_rule=hb.HB_ENSEMBLE_SUM, combine_md=3, offset=delta,
+                      max_batch=16384)
+    sb, mdb, _, totb = data(7007, 1 << 14)
+    hb_, _ = run(served, sb)
+    over = float(np.mean(hb_ > mdb + totb))
+    print("delta %.3f; over-estimates of the PDB %.4f%%; mean h %.2f, MD %.2f, PDB %.2f"
+          % (delta, 100 * over, hb_.mean(), mdb.mean(), (mdb + totb).mean()))
+    assert np.all(hb_ >= mdb) and over <= 0.005
+    assert hb_.mean() > mdb.mean() + 0.5
+    exp_nn = exp_md = 0
+    longer = []
+    for i, s in enumerate(synth.stp_walks(4, synth.config_seeds(2, 4), lengths=56)):
+        r = hb.cbdfs_solve(1, s, model=served, combine=hb.HB_H_NN, threads=16,
+                           params=hb.default_params(batch_size=4000, work_num=32))
+        o = O.ida(1, s, hkind=O.H_MD)
+        assert r["status"] == hb.HB_OK and r["cost"] >= o["cost"]
+        if r["cost"] != o["cost"]:
+            longer.append(i)
+        exp_nn += r["expanded"]
+        exp_md += sum(it["expanded"] for it in o["iters"])
+    print("expanded: ensemble %d vs Manhattan %d; instances with a longer path: %s" % (exp_nn, exp_md, longer))
+    assert len(longer) <= 1 and exp_nn < exp_md
+    served.close()
+    for p in member_pdbs + [total]:
+        p.close()
