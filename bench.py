@@ -274,6 +274,8 @@ def main():
             search[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
                             "expanded": r["expanded"], "wall_s": r["wall_s"], "evals": r["evals"],
                             "batches": r["batches"], "mean_batch": r["mean_batch"],
+                            "batches_per_iteration": [[i["bound"], i["batches"],
+                                                       round(i["evals"] / max(1, i["batches"]), 1)] for i in r["iters"]],
                             "gpu_us_per_batch": r["gpu_busy_s"] / max(1, r["batches"]) * 1e6,
                             "status": r["status"], "iterations": len(r["iters"]),
                             "per_iteration": [(i["bound"], i["expanded"], i["generated"]) for i in r["iters"]]}

@@ -372,6 +372,9 @@ typedef struct {
     int32_t complete;      /* 1: the iteration ran to completion */
     int32_t found;
     double bound_real;     /* the bound (bound = its floor; equal for integer heuristics) */
+    int64_t batches, evals; /* batches sent and states evaluated during this iteration (the
+                               runtime batch statistics of the appendix on batch sizes in
+                               practice); the initial tree's evaluation counts only in the totals */
 } cbdfs_iter;
 
 typedef struct {

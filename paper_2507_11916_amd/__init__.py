@@ -68,7 +68,8 @@ class Params(C.Structure):
 
 class Iter(C.Structure):
     _fields_ = [("bound", C.c_int32), ("limit", C.c_int64), ("expanded", C.c_int64), ("generated", C.c_int64),
-                ("complete", C.c_int32), ("found", C.c_int32), ("bound_real", C.c_double)]
+                ("complete", C.c_int32), ("found", C.c_int32), ("bound_real", C.c_double),
+                ("batches", C.c_int64), ("evals", C.c_int64)]
 
 
 class Result(C.Structure):
@@ -415,7 +416,8 @@ def cbdfs_solve(domain, start, model=None, combine=HB_H_NN, classic=HB_CLASSIC_M
     out = dict(status=st, cost=r.cost, path=[r.path[i] for i in range(r.path_len)] if r.path else [],
                iters=[dict(bound=r.iters[i].bound, limit=r.iters[i].limit, expanded=r.iters[i].expanded,
                            generated=r.iters[i].generated, complete=r.iters[i].complete, found=r.iters[i].found,
-                           bound_real=r.iters[i].bound_real)
+                           bound_real=r.iters[i].bound_real, batches=r.iters[i].batches,
+                           evals=r.iters[i].evals)
                       for i in range(r.n_iter)],
                evals=r.evals, batches=r.batches, mean_batch=r.mean_batch, wall_s=r.wall_s,
                gpu_busy_s=r.gpu_busy_s, expanded=r.expanded, generated=r.generated, frontier=r.frontier,

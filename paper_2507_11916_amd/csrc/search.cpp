@@ -510,6 +510,7 @@ struct Solver;
 // --------------------------------------------------------------- one search
 struct IterOut {
     int64_t expanded = 0, generated = 0;
+    int64_t batches = 0, evals = 0;  // batches and states evaluated during the iteration
     double next = INFINITY;
     bool found = false, exceeded = false, aborted = false, timed_out = false;
     std::vector<int8_t> path;
@@ -815,6 +816,8 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
 
 IterOut Solver::run(double T, int64_t lim, bool stop_goal) {
     IterOut out;
+    const int64_t batches0 = batcher ? batcher->batches.load() : 0;
+    const int64_t evals0 = batcher ? batcher->evals.load() : 0;
     bound = T;
     limit = lim;
     stop_at_goal = stop_goal;
@@ -882,6 +885,10 @@ IterOut Solver::run(double T, int64_t lim, bool stop_goal) {
     if (batcher && batcher->error != HB_OK) out.aborted = true;
     out.found = found_flag.load();
     out.path = sol_path;
+    if (batcher) {
+        out.batches = batcher->batches.load() - batches0;
+        out.evals = batcher->evals.load() - evals0;
+    }
     total_expanded += out.expanded;
     total_generated += out.generated;
     return out;
@@ -1002,6 +1009,8 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
         it.generated = o.generated;
         it.complete = complete;
         it.found = o.found;
+        it.batches = o.batches;
+        it.evals = o.evals;
         iters.push_back(it);
     };
 

@@ -104,6 +104,21 @@ def test_stp4_additive_pdb_ida_and_bts_match_oracle():
     pdb.close()
 
 
+def test_per_iteration_batch_statistics():
+    """Batches and evaluations per iteration: within the totals (the initial
+    tree's evaluation counts only there), each batch within the batch size,
+    and no more states evaluated in an iteration than it generated."""
+    s = synth.stp_walks(4, [11], lengths=44)[0]
+    p = hb.default_params(batch_size=500, work_num=8)
+    r = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_MD, threads=4, params=p)
+    its = r["iters"]
+    assert sum(i["batches"] for i in its) <= r["batches"] and sum(i["evals"] for i in its) <= r["evals"]
+    for i in its:
+        assert 0 <= i["evals"] <= i["generated"]
+        assert i["batches"] * 500 >= i["evals"] and (i["evals"] > 0) == (i["batches"] > 0)
+    assert its[-1]["batches"] > 0
+
+
 def test_flush_mode_out_of_range_is_rejected():
     s = synth.stp_walks(4, [11], lengths=20)[0]
     r = hb.cbdfs_solve(1, s, combine=hb.HB_H_CLASSIC_BATCHED, classic=hb.HB_CLASSIC_MD, threads=2,
