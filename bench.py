@@ -79,6 +79,10 @@ def main():
                     help="instead of the benchmark line: only a short 15-puzzle search (fixed tree, Manhattan "
                          "pruning, work_num 8, 100K expansions) at this precision, for a profiler's timeline of "
                          "the batches")
+    ap.add_argument("--search-sweep", action="store_true",
+                    help="instead of the benchmark line: search nodes/s over subtrees per thread (work_num) and "
+                         "batch caps, FP32 and BF16, on the 15-puzzle (fixed tree, Manhattan) and the cube (fixed-tree "
+                         "BTS, 8-corner PDB); prints its own JSON line")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -147,6 +151,9 @@ def main():
 
     if args.size_sweep:
         size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp)
+        return
+    if args.search_sweep:
+        search_sweep(hb, synth, netcfg, torch, wpath, tmp)
         return
     if args.search_batches:
         prec = {"f32": hb.HB_FP32, "bf16": hb.HB_BF16, "fp8": hb.HB_FP8_E4M3}[args.search_batches]
@@ -523,6 +530,44 @@ def other_configs(args, hb, synth, netcfg, O, torch, stream, tmp):
         f"over all 181,440 states")
     m.close()
     return out
+
+
+def search_sweep(hb, synth, netcfg, torch, wpath, tmp):
+    """The search hyperparameters (work_num, batch cap): generated nodes/s and
+    mean batch of the benchmark's two fixed-tree searches."""
+    threads = min(32, max(4, len(os.sched_getaffinity(0))))
+    start = synth.stp4_instances(1)[0]
+    cpath = os.path.join(tmp, "rc_cls.hbw")
+    synth.write_weights(cpath, "rc_cls", **netcfg.DEFAULTS["rc_cls"])
+    cstart = hb.hb_apply_moves(hb.HB_RUBIK3, np.asarray(synth.rc_instance_moves(1)[0], dtype=np.int8))[0]
+    pdb = hb.Pdb(8)
+    rows = []
+    for name, prec in (("f32", hb.HB_FP32), ("bf16", hb.HB_BF16)):
+        m = hb.Model(wpath, prec=prec, combine_md=True, max_batch=16384)
+        cm = hb.Model(cpath, prec=prec, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=8000)
+        for wn in (8, 16, 32, 64, 128):
+            for cap in (800, 8000):
+                p = hb.default_params(batch_size=cap, work_num=wn, node_limit=1_000_000, time_limit_s=20.0)
+                r = hb.cbdfs_solve(hb.HB_STP4, start, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_MD,
+                                   threads=threads, params=p, raise_on_error=False)
+                rows.append({"domain": "stp4", "prec": name, "work_num": wn, "batch_cap": cap,
+                             "nodes_per_s": r["generated"] / r["wall_s"], "mean_batch": r["mean_batch"]})
+                log(f"[bench] sweep stp4 {name} work_num {wn} cap {cap}: {rows[-1]['nodes_per_s']:.3e} nodes/s, "
+                    f"mean batch {r['mean_batch']:.0f}")
+            if wn <= 32:
+                for cap in (4000, 8000):
+                    p = hb.default_params(batch_size=cap, work_num=wn, node_limit=300_000, time_limit_s=20.0)
+                    r = hb.cbdfs_solve(hb.HB_RUBIK3, cstart, model=cm, combine=hb.HB_H_FIXED_TREE,
+                                       classic=hb.HB_CLASSIC_PDB, pdb=pdb, algo=hb.HB_BTS, threads=threads, params=p,
+                                       raise_on_error=False)
+                    rows.append({"domain": "cube", "prec": name, "work_num": wn, "batch_cap": cap,
+                                 "nodes_per_s": r["generated"] / r["wall_s"], "mean_batch": r["mean_batch"]})
+                    log(f"[bench] sweep cube {name} work_num {wn} cap {cap}: {rows[-1]['nodes_per_s']:.3e} nodes/s, "
+                        f"mean batch {r['mean_batch']:.0f}")
+        m.close()
+        cm.close()
+    pdb.close()
+    print(json.dumps({"search_sweep": rows, "threads": threads}))
 
 
 def library_gemm(args, torch):
