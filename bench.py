@@ -529,6 +529,46 @@ def other_configs(args, hb, synth, netcfg, O, torch, stream, tmp):
     log(f"[bench] 8-puzzle net: {us64:.1f} us per batch of 64, {len(allst) / ms_all * 1e3:.3e} evals/s "
         f"over all 181,440 states")
     m.close()
+    # precision drift, exact on the 8-puzzle: each precision's h over every state
+    # against the FP64 oracle's, and Batch IDA* node counts on the 100 starts with
+    # each precision's h against the oracle's IDA* on the FP64 h table
+    onet = O.Net(spath)
+    md_all = hb.hb_manhattan(hb.HB_STP3, allst)
+    h64 = onet.h(onet.forward(allst), 0, classic=md_all)
+    rank = np.zeros(len(allst), dtype=np.int64)
+    fact = [40320, 5040, 720, 120, 24, 6, 2, 1, 1]
+    for i in range(9):  # Lehmer rank, the oracle table's index
+        rank += (allst[:, i + 1:] < allst[:, i:i + 1]).sum(axis=1) * fact[i]
+    table = np.zeros(362880, dtype=np.int32)
+    table[rank] = h64
+    starts = synth.stp3_instances(100)
+    ref = [O.ida(O.STP3, s0, hkind=O.H_TABLE8, table8=table, complete_final=True) for s0 in starts]
+    drift = {}
+    for name, prec in (("f32", hb.HB_FP32), ("bf16", hb.HB_BF16), ("fp8", hb.HB_FP8_E4M3)):
+        m = hb.Model(spath, prec=prec, combine_md=True, max_batch=len(allst))
+        if prec == hb.HB_FP8_E4M3:
+            m.calibrate(d_all[::44].contiguous())
+        m.eval_batch(d_all, d_ah)
+        torch.cuda.synchronize()
+        hp = d_ah.cpu().numpy()
+        exp_p = exp_r = 0
+        diff = 0
+        costs_equal = True
+        for s0, o in zip(starts, ref):
+            r = hb.cbdfs_solve(hb.HB_STP3, s0, model=m, combine=hb.HB_H_NN, threads=4,
+                               params=hb.default_params(batch_size=64, work_num=4, complete_final_iter=1))
+            e_r = sum(i["expanded"] for i in o["iters"])
+            exp_p += r["expanded"]
+            exp_r += e_r
+            diff += abs(r["expanded"] - e_r)
+            costs_equal &= r["cost"] == o["cost"]
+        drift[name] = {"h_mismatch_fp64": float(np.mean(hp != h64)), "expanded": exp_p, "expanded_fp64": exp_r,
+                       "node_count_drift": diff / max(1, exp_r), "costs_equal_fp64": bool(costs_equal)}
+        log(f"[bench] 8-puzzle {name}: h differs from FP64 on {100 * drift[name]['h_mismatch_fp64']:.3f}% of "
+            f"181,440 states; expansions {exp_p} vs {exp_r} (drift {100 * drift[name]['node_count_drift']:.2f}%), "
+            f"costs equal {costs_equal}")
+        m.close()
+    out["puzzle8"]["precision_drift"] = drift
     return out
 
 
