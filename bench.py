@@ -39,7 +39,8 @@ def log(*a):
 TILE_KERNELS = {1: "gemm_kernel<0, 0, 128, 128>", 2: "gemm_kernel<0, 0, 128, 256>", 3: "gemm_kernel<0, 0, 64, 128>",
                 4: "gemm_kernel<0, 0, 256, 128>", 5: "gemm_small_kernel<0, 0>",
                 6: "gemm_ring_kernel<0, 0, 256, 128, 3>", 7: "gemm_ring_kernel<0, 0, 128, 128, 3>",
-                8: "gemm_ring_kernel<0, 0, 128, 256, 3>", 9: "gemm_ring_kernel<0, 0, 64, 128, 4>"}
+                8: "gemm_ring_kernel<0, 0, 128, 256, 3>", 9: "gemm_ring_kernel<0, 0, 64, 128, 4>",
+                10: "gemm_w8_kernel<0, 0>"}
 
 
 def measured_traffic(kernel):

@@ -458,6 +458,90 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #undef SA
 #undef SB
 
+// ------------------------------------------------------------ GEMM, 8 waves
+// 256 x 128 tile with 8 waves in a 4 x 2 grid, each wave 64 x 64: one block per
+// CU holds as many waves as two 128 x 128 blocks but moves a quarter fewer
+// operand bytes per MFMA through L2 and LDS.  Each pair of wave rows runs the
+// same per-stage MFMA routine on its 128-row half of the A tile (the swizzle
+// key of a row is unchanged by the 128-row offset), so results are bitwise
+// equal to the other tiles.  LDS double buffer filled through registers.
+template <int PREC, int OUTT>
+__global__ __launch_bounds__(512) void gemm_w8_kernel(GemmArgs g) {
+    constexpr int BM = 256, BN = 128;
+    constexpr int EB = Ty<PREC>::EB;
+    constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128;
+    constexpr int A_LD = BM * 8 / 512, B_LD = BN * 8 / 512;
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int STAGE = A_BYTES + B_BYTES;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + BM - 1) / BM, g.m_tiles_cap);
+    const int n_tiles = g.N / BN;
+    const int total = m_tiles * n_tiles;
+    const int kb = g.K * EB;
+    const int ktiles = kb / 128;
+    const int grid = gridDim.x;
+    const int grid8 = grid & ~7;
+    int first = blockIdx.x;
+    if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
+    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+        const int tm = t / n_tiles, tn = t % n_tiles;
+        const int m0 = tm * BM, n0 = tn * BN;
+        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
+        const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
+        floatx16 acc[2][2];
+        _Pragma("unroll") for (int i = 0; i < 2; i++)
+            _Pragma("unroll") for (int j = 0; j < 2; j++)
+                _Pragma("unroll") for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
+        u32x4 ra[A_LD], rb[B_LD];
+        auto gload = [&](int kt_) {
+            const int kbyte = kt_ * 128;
+            _Pragma("unroll") for (int i = 0; i < A_LD; i++) {
+                const int id = i * 512 + tid, row = id >> 3, ch = id & 7;
+                ra[i] = *reinterpret_cast<const u32x4*>(Ag + (size_t)row * g.lda * EB + kbyte + ch * 16);
+            }
+            _Pragma("unroll") for (int i = 0; i < B_LD; i++) {
+                const int id = i * 512 + tid, row = id >> 3, ch = id & 7;
+                rb[i] = *reinterpret_cast<const u32x4*>(Bg + (size_t)row * g.ldb * EB + kbyte + ch * 16);
+            }
+        };
+        auto sstore = [&](int buf) {
+            uint8_t* sa = smem + buf * STAGE;
+            uint8_t* sb = sa + A_BYTES;
+            _Pragma("unroll") for (int i = 0; i < A_LD; i++) {
+                const int id = i * 512 + tid, row = id >> 3, ch = id & 7;
+                *reinterpret_cast<u32x4*>(sa + swz(row, ch)) = ra[i];
+            }
+            _Pragma("unroll") for (int i = 0; i < B_LD; i++) {
+                const int id = i * 512 + tid, row = id >> 3, ch = id & 7;
+                *reinterpret_cast<u32x4*>(sb + swz(row, ch)) = rb[i];
+            }
+        };
+        gload(0);
+        __syncthreads();
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt < ktiles; kt++) {
+            const int cur = kt & 1;
+            if (kt + 1 < ktiles) gload(kt + 1);
+            const uint8_t* sa = smem + cur * STAGE;
+            mma_stage<PREC, 128, 128>(sa + (wm >> 1) * 128 * 128, sa + A_BYTES, acc, wm & 1, wn, lane);
+            if (kt + 1 < ktiles) sstore(cur ^ 1);
+            __syncthreads();
+        }
+        const int half = lane >> 5, c32 = lane & 31;
+        _Pragma("unroll") for (int j = 0; j < 2; j++) {
+            const int n = n0 + wn * 64 + j * 32 + c32;
+            const float bn = g.bias ? g.bias[n] : 0.f;
+            const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+            _Pragma("unroll") for (int i = 0; i < 2; i++)
+                epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
+        }
+    }
+}
+
+
 // ------------------------------------------------------------ GEMM, LDS ring
 // Same tiles, MFMA sequence and epilogue as gemm_kernel (bitwise equal
 // results), but the operands go from global memory straight into LDS
@@ -923,12 +1007,32 @@ static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_ring_kernel<PREC, OUTT, BM, BN, NS>), dim3(grid), dim3(256), lds, s, g);
 }
 
-// Tile ids: 0-3 LDS double buffer fed through registers, 4 the small-batch
-// kernel (one wave per 32 x 32 tile), 5-8 the LDS ring fed by direct loads.
-int gemm_tile_count() { return 9; }
+template <int PREC, int OUTT>
+static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
+    const int m_tiles = (L.m_cap + 255) / 256;
+    const int tiles = m_tiles * (L.N / 128);
+    g.m_tiles_cap = m_tiles;
+    int grid = tiles;
+    g.persistent = 0;
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.m_dev) g.persistent = 1;
+    hipLaunchKernelGGL((gemm_w8_kernel<PREC, OUTT>), dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, g);
+}
+
+// Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the
+// small-batch kernel (one wave per 32 x 32 tile), 5-8 the LDS ring fed by
+// direct loads, 9 the 8-wave 256 x 128 tile.
+int gemm_tile_count() { return 10; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[9][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
-                                {256, 128}, {128, 128}, {128, 256}, {64, 128}};
+    static const int T[10][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+                                 {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -945,6 +1049,7 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 6: launch_gemm_ring<PREC, OUTT, 128, 128, 3>(L, s); return true;
         case 7: launch_gemm_ring<PREC, OUTT, 128, 256, 3>(L, s); return true;
         case 8: launch_gemm_ring<PREC, OUTT, 64, 128, 4>(L, s); return true;
+        case 9: launch_gemm_w8<PREC, OUTT>(L, s); return true;
     }
     return false;
 }
@@ -994,6 +1099,10 @@ static hipError_t set_lds_attr_p() {
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 128, 256>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 64, 128>();
     if (e == hipSuccess) e = set_lds_attr<PREC, OUTT, 256, 128>();
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_w8_kernel<PREC, OUTT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (256 + 128) * 128);
+
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 256, 128, 3>();
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 128, 3>();
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 256, 3>();
