@@ -407,7 +407,7 @@ def main():
         tr.close()
 
     # CPU baseline: the oracle's FP64 forward on a bounded sample, all host cores
-    cpu = None
+    cpu = cpu_search = None
     if not args.no_cpu_baseline:
         from concurrent.futures import ThreadPoolExecutor
         cores = len(os.sched_getaffinity(0))
@@ -423,6 +423,23 @@ def main():
         cpu = {"value": n_cpu / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
                "sample": f"{n_cpu} of the {B} benchmark states, FP64 plain-C forward, one thread per core"}
         log(f"[bench] cpu oracle: {cpu['value']:.1f} evals/s on {cores} cores")
+        # the search on one core without a GPU: the oracle's IDA* with Manhattan
+        # pruning (the fixed tree) on the benchmark's 15-puzzle start for 20K
+        # expansions, plus the FP64 network on a sample of generated states
+        s0 = synth.stp4_instances(1)[0]
+        t0 = time.time()
+        o = O.ida(O.STP4, s0, hkind=O.H_MD, node_limit=20_000)
+        t_search = time.time() - t0
+        gen = sum(i["generated"] for i in o["iters"])
+        sample_st = synth.stp_walks(4, synth.throughput_seeds(500, 31337), lengths=200)
+        t0 = time.time()
+        onet.forward(sample_st)
+        t_eval = (time.time() - t0) / len(sample_st)
+        cpu_search = {"value": 1.0 / (t_search / max(1, gen) + t_eval), "unit": "generated nodes/s", "cores": 1,
+                      "kind": "oracle",
+                      "sample": f"IDA* with Manhattan pruning on the benchmark's 15-puzzle start, {gen} generated "
+                                f"nodes (20K expansions), plus the FP64 network on 500 states (one per generated node)"}
+        log(f"[bench] cpu oracle search: {cpu_search['value']:.1f} generated nodes/s on 1 core")
 
     f32 = results["f32"]
     ach = f32["gemm_tflops"]
@@ -449,6 +466,7 @@ def main():
                      "kernel": f"{f32_kernel} (dense/residual layer, M=batch, K=N=1000 padded to 1024)",
                      "avg_launch_us": f32["gemm_avg_us"], "flops_per_launch": f32["gemm_flops_per_launch"]},
         "cpu_baseline": cpu,
+        "cpu_baseline_search": cpu_search,
         "precisions": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
         "mfma_frac": {k: results[k]["evals_per_s"] * flops_eval / 1e12 / PEAK_TFLOPS[k] for k in results},
         "end_to_end_evals_per_s_pcie": B / e2e_ms * 1e3,
