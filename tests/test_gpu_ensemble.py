@@ -72,14 +72,25 @@ def test_ensemble_matches_oracle(tmp_path, prec, rule):
     assert (~tight).mean() <= (0.0 if prec == hb.HB_FP32 else 0.5)
 
 
-@pytest.mark.parametrize("prec", [hb.HB_FP32, hb.HB_BF16])
-def test_fused_equals_separate_members(tmp_path, prec):
+@pytest.mark.parametrize("prec,tile", [(hb.HB_FP32, 0), (hb.HB_BF16, 0), (hb.HB_BF16, 6), (hb.HB_BF16, 10),
+                                       (hb.HB_FP32, 10)])
+def test_fused_equals_separate_members(tmp_path, prec, tile):
+    """The fused ensemble (grouped GEMMs: each member's columns read their own
+    slice of the activations) equals the members evaluated one by one, for the
+    automatic tile and forced ring and 8-wave tiles."""
     paths = _members(tmp_path, "stp4_res", 256, [31, 32], 40.0)
     st = synth.stp_walks(4, synth.throughput_seeds(500, 505), lengths=200)
     packed = hb.hb_encode(1, st)
-    ys = [_y(hb.Model(p, prec=prec, out=hb.HB_OUT_REG_REAL), packed)[1] for p in paths]
-    y_min = _y(hb.Model(paths, prec=prec, out=hb.HB_OUT_REG_REAL, ensemble_rule=hb.HB_ENSEMBLE_MIN), packed)[1]
-    y_sum = _y(hb.Model(paths, prec=prec, out=hb.HB_OUT_REG_REAL, ensemble_rule=hb.HB_ENSEMBLE_SUM), packed)[1]
+
+    def model(p, **kw):
+        m = hb.Model(p, prec=prec, out=hb.HB_OUT_REG_REAL, **kw)
+        if tile:
+            m.set_tile(tile)
+        return m
+
+    ys = [_y(model(p), packed)[1] for p in paths]
+    y_min = _y(model(paths, ensemble_rule=hb.HB_ENSEMBLE_MIN), packed)[1]
+    y_sum = _y(model(paths, ensemble_rule=hb.HB_ENSEMBLE_SUM), packed)[1]
     np.testing.assert_array_equal(y_min, np.minimum(ys[0], ys[1]))
     np.testing.assert_array_equal(y_sum, (ys[0].astype(np.float32) + ys[1].astype(np.float32)).astype(np.float64))
 
