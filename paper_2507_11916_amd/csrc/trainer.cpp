@@ -6,6 +6,7 @@
 // gradient GEMMs on transposed activations (FP32 output, bias gradients as
 // column sums fused into the transposes); layer-1 gradient by scatter-add;
 // Adam on FP32 master weights, re-casting the working copies.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -119,7 +120,10 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
     g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.a_scale = g.r_scale = g.out_inv_scale = 1.f;
     g.relu = relu;
-    g.tile = (N % 256 == 0 && M >= 2048) ? 1 : 2;  // 128x256 or 64x128
+    // 128x256 or 64x128; FP32 weight gradients (K, the batch, far longer than M
+    // and N) take the one-wave 32x32 tile: 8x the tiles of 64x128 on a 1000 x
+    // 1000 output, measured 12% faster per FP32 step (slower for BF16).
+    g.tile = (tr->t == 0 && K >= 4 * std::max(M, N)) ? 4 : (N % 256 == 0 && M >= 2048) ? 1 : 2;
     if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM for this precision");
     HB_HIP(hipGetLastError());
     return HB_OK;
