@@ -84,6 +84,9 @@ def main():
                     help="instead of the benchmark line: search nodes/s over subtrees per thread (work_num) and "
                          "batch caps, FP32 and BF16, on the 15-puzzle (fixed tree, Manhattan) and the cube (fixed-tree "
                          "BTS, 8-corner PDB); prints its own JSON line")
+    ap.add_argument("--train-steps", type=int, default=0,
+                    help="instead of the benchmark line: this many training steps of the 15-puzzle network (BF16, "
+                         "batch 8192), for a profiler's kernel breakdown")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -152,6 +155,21 @@ def main():
 
     if args.size_sweep:
         size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp)
+        return
+    if args.train_steps > 0:
+        TB = 8192
+        tst = synth.stp_walks(4, synth.throughput_seeds(TB, 5005), length_base=0, length_span=201)
+        tlab = np.array([synth.Stream((5005 << 32) + i).next() % 201 for i in range(TB)], dtype=np.float32)
+        tr = hb.Trainer(wpath, prec=hb.HB_BF16, max_batch=TB)
+        d_tp = torch.from_numpy(hb.hb_encode(hb.HB_STP4, tst)).cuda()
+        d_tl = torch.from_numpy(tlab).cuda()
+        l0 = tr.step(d_tp, d_tl)
+        for _ in range(args.train_steps):
+            tr.step(d_tp, d_tl, want_loss=False)
+        l1 = tr.step(d_tp, d_tl)
+        torch.cuda.synchronize()
+        print(json.dumps({"train_steps": args.train_steps, "loss_first": l0, "loss_last": l1}))
+        tr.close()
         return
     if args.search_sweep:
         search_sweep(hb, synth, netcfg, torch, wpath, tmp)
