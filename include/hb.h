@@ -324,7 +324,11 @@ typedef enum { HB_IDA = 0, HB_BTS = 1 } hb_algo;
  *                    the HB_OUT_REG_REAL mode, unrounded (Regression-Based Neural
  *                    Heuristics experiment): f = g + h and the cost bounds are
  *                    real; IDA*'s next bound is the smallest pruned f and BTS
- *                    bisects over real bounds (cbdfs_iter.bound_real). */
+ *                    bisects over real bounds (cbdfs_iter.bound_real).  The
+ *                    model must be loaded with combine_md = 0: the real value is
+ *                    the network's own, so a Manhattan rule (min, max or plus)
+ *                    would be silently dropped; cbdfs_solve returns HB_E_INVAL
+ *                    for such a model. */
 typedef enum {
     HB_H_NN = 0, HB_H_MIN_NN_CLASSIC = 1, HB_H_FIXED_TREE = 2, HB_H_CLASSIC = 3, HB_H_CLASSIC_BATCHED = 4,
     HB_H_NN_REAL = 5

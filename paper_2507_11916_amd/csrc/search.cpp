@@ -544,6 +544,11 @@ struct Solver {
     std::mutex sol_mu;
     std::vector<int8_t> sol_path;
     bool budget_hit = false;
+    // Node stacks of each search thread.  A thread that stops early can leave
+    // children parked in a batch; the batch thread later writes their h through
+    // the slab's owner pointers, so the stacks live until run() has drained the
+    // batcher, not just until their thread returns.
+    std::vector<std::vector<std::unique_ptr<NodeRec[]>>> stacks_of;
 
     double prune_h(const NodeRec& r) const {
         switch (sh.combine) {
@@ -625,7 +630,8 @@ void Solver::thread_main(int tid, IterOut* out, int64_t* peak) {
     const Domain& D = *sh.D;
     const int W = std::max(1, P->work_num);
     const int pb = D.packed_bytes;
-    std::vector<std::unique_ptr<NodeRec[]>> stacks(W);
+    std::vector<std::unique_ptr<NodeRec[]>>& stacks = stacks_of[tid];  // freed by run() after drain()
+    stacks.resize(W);
     std::vector<int> top(W, 0);
     for (int w = 0; w < W; w++) stacks[w].reset(new NodeRec[stack_cap]);
     std::vector<char> terminated(W, 0);
@@ -873,9 +879,14 @@ IterOut Solver::run(double T, int64_t lim, bool stop_goal) {
     if (!stop.load() && !exceeded_flag.load() && !work.empty()) {
         std::vector<std::thread> pool;
         if (batcher) batcher->set_active(threads);
+        stacks_of.clear();
+        stacks_of.resize(threads);
         for (int t = 0; t < threads; t++) pool.emplace_back([this, t, &out, &peak] { thread_main(t, &out, &peak); });
         for (auto& th : pool) th.join();
+        // Every parked record gets its value (or the batcher stops on an
+        // error) before the stacks holding the records are released.
         if (batcher) batcher->drain();
+        stacks_of.clear();
     }
     peak_nodes = std::max(peak_nodes, peak);
     if (limit >= 0 && expanded_shared.load() > limit) exceeded_flag.store(true);
@@ -972,6 +983,8 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     if (h->combine == HB_H_NN_REAL &&
         (h->model->opts.out != HB_OUT_REG_REAL || h->model->spec.n_out != 1))
         return fail(HB_E_INVAL, "a real-valued heuristic needs a regression model in the REAL output mode");
+    if (h->combine == HB_H_NN_REAL && h->model->opts.combine_md != 0)
+        return fail(HB_E_INVAL, "a real-valued heuristic uses the network's value alone: load the model with combine_md = 0");
     S->sh.real = h->combine == HB_H_NN_REAL;
     S->sh.uses_gpu = nn;
     S->sh.uses_batches = nn || h->combine == HB_H_CLASSIC_BATCHED;
