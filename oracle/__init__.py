@@ -70,6 +70,7 @@ def _declare(L):
     L.orc_corner_k_index_batch.argtypes = [vp, C.c_int64, C.c_int, vp]
     L.orc_apdb_group.argtypes = [C.c_int, vp, vp]
     L.orc_apdb_h_batch.argtypes = [vp, C.c_int64, C.c_int, vp, vp, vp]
+    L.orc_apdb_group_lookup.argtypes = [C.c_int, vp, vp, vp, C.c_int64, vp]
     L.orc_bf16_round_array.argtypes = [vp, C.c_int64, vp]
     L.orc_e4m3_round_array.argtypes = [vp, C.c_int64, vp]
     L.orc_e4m3_decode.argtypes = [C.c_int]
@@ -177,6 +178,26 @@ def apdb(groups):
             raise ValueError("bad group")
         tables[g, :t.size] = t
     return tiles, tables
+
+
+def apdb_group_table(group):
+    """One group's table (1 to 6 tiles), indexed by sum of cell * 16^i over
+    the group's tiles in ascending order: (tiles, table)."""
+    ts = np.array(sorted(int(t) for t in group), dtype=np.int32)
+    if not 1 <= ts.size <= 6:
+        raise ValueError("groups of 1 to 6 tiles")
+    t = np.zeros(16 ** ts.size, dtype=np.uint8)
+    if not lib().orc_apdb_group(ts.size, ts.ctypes.data, t.ctypes.data):
+        raise ValueError("bad group or out of memory")
+    return ts, t
+
+
+def apdb_group_lookup(group_table, states):
+    ts, t = group_table
+    s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, 16)
+    out = np.zeros(s.shape[0], dtype=np.int32)
+    lib().orc_apdb_group_lookup(ts.size, ts.ctypes.data, t.ctypes.data, s.ctypes.data, s.shape[0], out.ctypes.data)
+    return out
 
 
 def apdb_h(states, spec):

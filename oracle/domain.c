@@ -387,7 +387,7 @@ int orc_corner_k_index_batch(const uint8_t* s, int64_t n, int k, int64_t* out) {
  * distance over the blank's cells (255 where two tiles share a cell).
  * ---------------------------------------------------------------------- */
 int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
-    if (k < 1 || k > 4) return 0;
+    if (k < 1 || k > 6) return 0;
     int64_t n_place = 1;
     for (int i = 0; i < k; i++) n_place *= 16;
     const int64_t n_state = n_place * 16;
@@ -410,7 +410,7 @@ int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
         for (int64_t q = 0; q < fill[d]; q++) {
             const int64_t st = bucket[d][q];
             if (dist[st] != d) continue;
-            int cell[4];
+            int cell[6];
             int64_t rest = st;
             for (int i = 0; i < k; i++) { cell[i] = (int)(rest % 16); rest /= 16; }
             const int blank = (int)rest;
@@ -422,7 +422,7 @@ int orc_apdb_group(int k, const int32_t* tiles, uint8_t* table) {
                 const int nb = r * 4 + c;
                 int who = -1;
                 for (int i = 0; i < k; i++) if (cell[i] == nb) who = i;
-                int ncell[4];
+                int ncell[6];
                 for (int i = 0; i < k; i++) ncell[i] = cell[i];
                 int step = 0;
                 if (who >= 0) { ncell[who] = blank; step = 1; }
@@ -470,6 +470,20 @@ int orc_apdb_h(const uint8_t* s, int n_groups, const int32_t* tiles, const uint8
         h += tables[(int64_t)g * 65536 + code];
     }
     return h;
+}
+
+/* One group's table of any size (1 to 6 tiles): out[i] = table[code] for
+ * state i, code = sum over the group's tiles of cell * 16^i. */
+int orc_apdb_group_lookup(int k, const int32_t* tiles, const uint8_t* table, const uint8_t* s, int64_t n,
+                          int32_t* out) {
+    for (int64_t b = 0; b < n; b++) {
+        int where[16];
+        for (int c = 0; c < 16; c++) where[s[b * 16 + c]] = c;
+        int64_t code = 0, mul = 1;
+        for (int i = 0; i < k; i++) { code += (int64_t)where[tiles[i]] * mul; mul *= 16; }
+        out[b] = table[code];
+    }
+    return 1;
 }
 
 int orc_apdb_h_batch(const uint8_t* s, int64_t n, int n_groups, const int32_t* tiles, const uint8_t* tables,

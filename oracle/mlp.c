@@ -328,8 +328,11 @@ int orc_h_regression(double y, int mode, double offset, int classic) {
 }
 
 /* mode 3 quantile: smallest class whose cumulative softmax probability is at
- * least q (the last class if none); mode 4 arg-max (lowest index on ties). */
+ * least q (the last class if none); mode 4 arg-max (lowest index on ties).
+ * Returns -1 when the output is undefined (a NaN or +infinite logit): the
+ * caller falls back to the classic heuristic, or 0. */
 int orc_h_classifier(const double* z, int n_out, int mode, double q) {
+    for (int c = 0; c < n_out; c++) if (isnan(z[c]) || z[c] == INFINITY) return -1;
     if (mode == 4) {
         int best = 0;
         for (int c = 1; c < n_out; c++) if (z[c] > z[best]) best = c;
@@ -350,8 +353,10 @@ int orc_h_classifier(const double* z, int n_out, int mode, double q) {
 int orc_h_batch(const orc_net* m, const double* y, int64_t n, int mode, double q, double offset,
                 const int32_t* classic, int32_t* h) {
     for (int64_t b = 0; b < n; b++) {
-        if (m->head_kind == 1 || mode >= 3)
+        if (m->head_kind == 1 || mode >= 3) {
             h[b] = orc_h_classifier(y + b * m->n_out, m->n_out, mode, q);
+            if (h[b] < 0) h[b] = classic ? classic[b] : 0;
+        }
         else
             h[b] = orc_h_regression(y[b * m->n_out], mode, offset, classic ? classic[b] : -1);
     }

@@ -878,8 +878,14 @@ __global__ __launch_bounds__(256) void head_cls_kernel(HeadArgs h) {
     }
     if (lane != 0) return;
     const int md = head_md(h, r);
+    // a NaN or +infinite logit leaves the rule undefined: classic value or 0
+    bool undefined = false;
+    for (int o = 0; o < NOUT; o++)
+        if (o < h.n_out && (y[o] != y[o] || y[o] == INFINITY)) undefined = true;
     int hv;
-    if (h.mode == 4) {
+    if (undefined && h.mode >= 3) {
+        hv = md >= 0 ? md : 0;
+    } else if (h.mode == 4) {
         int best = 0;
         for (int o = 1; o < NOUT; o++)
             if (o < h.n_out && y[o] > y[best]) best = o;

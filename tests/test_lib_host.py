@@ -196,6 +196,20 @@ def test_additive_stp_pdb_matches_oracle():
     pdb.close()
 
 
+@pytest.mark.slow
+def test_additive_stp_pdb_663_matches_oracle():
+    """The library's 6-6-3 split (the benchmark's and the training labels'
+    PDB) equals the sum of the oracle's three group tables on 10^5 states."""
+    groups = [range(1, 7), range(7, 13), range(13, 16)]
+    st = synth.stp_walks(4, synth.throughput_seeds(100000, 63), lengths=200)
+    ref = sum(O.apdb_group_lookup(O.apdb_group_table(g), st) for g in groups)
+    pdb = hb.Pdb(groups=groups)
+    np.testing.assert_array_equal(pdb.lookup(st), ref)
+    counts, _ = pdb.value_counts(128)
+    assert counts.sum() == 2 * 16 * 15 * 14 * 13 * 12 * 11 + 16 * 15 * 14
+    pdb.close()
+
+
 def test_additive_stp_pdb_rejects_bad_groupings():
     with pytest.raises(hb.HBError):
         hb.Pdb(groups=[range(1, 10), range(10, 16)])  # a group of 9 tiles

@@ -232,3 +232,32 @@ def test_additive_pdb_is_admissible_and_keeps_ida_optimal():
         assert O.apdb_h(s[None], spec)[0] <= r_md["cost"]
         assert r_pd["cost"] == r_md["cost"]
         assert sum(i["expanded"] for i in r_pd["iters"]) <= sum(i["expanded"] for i in r_md["iters"])
+
+
+# ------------------------------------------------ 6-tile pattern groups
+@pytest.fixture(scope="module")
+def group_1_6():
+    return O.apdb_group_table(range(1, 7))
+
+
+@pytest.mark.slow
+def test_six_tile_pattern_table_pins(group_1_6):
+    """The oracle's 6-tile table (0-1 breadth-first search over 16^7 dense
+    codes): every placement of the six tiles is reached (16!/10!), it dominates
+    the sum of its two disjoint 3-tile halves (a path for the six tiles is a
+    path for each half, and its six-tile moves split between them), it has the
+    parity of its tiles' Manhattan distance and lies above it, and it never
+    exceeds the optimal cost of short walks."""
+    ts, t = group_1_6
+    assert int((t < 255).sum()) == 16 * 15 * 14 * 13 * 12 * 11
+    st = synth.stp_walks(4, synth.config_seeds(9, 4000), lengths=200)
+    h6 = O.apdb_group_lookup(group_1_6, st)
+    h_a = O.apdb_group_lookup(O.apdb_group_table([1, 2, 3]), st)
+    h_b = O.apdb_group_lookup(O.apdb_group_table([4, 5, 6]), st)
+    assert np.all(h6 >= h_a + h_b) and np.any(h6 > h_a + h_b)
+    where = np.argsort(st, axis=1)  # cell of each tile
+    md6 = sum(np.abs(where[:, t] // 4 - t // 4) + np.abs(where[:, t] % 4 - t % 4) for t in range(1, 7))
+    assert np.all(h6 >= md6) and np.all((h6 - md6) % 2 == 0)
+    assert O.apdb_group_lookup(group_1_6, O.goal(O.STP4)[None])[0] == 0
+    for s in synth.stp_walks(4, synth.config_seeds(9, 8), lengths=34):
+        assert O.apdb_group_lookup(group_1_6, s[None])[0] <= O.ida(O.STP4, s, hkind=O.H_MD)["cost"]

@@ -50,10 +50,10 @@ def test_closed_form_network(n, tmp_path):
     np.testing.assert_array_equal(y[:, 1], 2 * md - 2)
 
 
-def test_reduced_precision_is_exact_on_representable_values(tmp_path):
-    # Small integers are exact in bfloat16; with every MFMA column max equal to
-    # a power of two times 7, the e4m3 weight codes are exact too; activations
-    # below 16 with scale 1 are exact e4m3 values.
+def test_bf16_forward_is_exact_on_representable_values(tmp_path):
+    # Small integers are exact in bfloat16, so the bf16 forward of this net equals
+    # the unrounded one (the rounding itself is pinned by hand-built nets in
+    # test_oracle_precision.py).
     path = str(tmp_path / "md.hbw")
     nets.write_md_net(path, 3)
     net = O.Net(path)
@@ -220,3 +220,16 @@ def test_combined_regression_rule():
     for mode in (0, 1):
         ref = [f(float(a), mode, 0.7, int(c)) for a, c in zip(ys, cl)]
         np.testing.assert_array_equal(O.h_regression(ys, cl, combine=1, offset=0.7, mode=mode), ref)
+
+
+def test_classifier_rule_is_undefined_on_nan_or_infinite_logits():
+    """A NaN or +infinite logit leaves softmax and arg-max undefined: the rule
+    returns -1 and the batch rule falls back to the classic value (or 0);
+    a -infinite logit is an ordinary class of probability zero."""
+    f = O.lib().orc_h_classifier
+    f.argtypes = [O.C.c_void_p, O.C.c_int, O.C.c_int, O.C.c_double]
+    for bad in (np.nan, np.inf):
+        z = np.ascontiguousarray([0.0, bad, 1.0])
+        assert f(z.ctypes.data, 3, 3, 0.99) == -1 and f(z.ctypes.data, 3, 4, 0.0) == -1
+    z = np.ascontiguousarray([-np.inf, 0.0, 0.0])
+    assert f(z.ctypes.data, 3, 4, 0.0) == 1 and f(z.ctypes.data, 3, 3, 0.4) == 1
