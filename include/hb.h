@@ -210,6 +210,23 @@ hb_status hb_model_set_act_scales(hb_model* m, const float* scales, int n);
 hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
                         float* d_raw_out, void* stream);
 
+/* Allocation-free variant of hb_eval_batch, for callers that cannot allocate
+ * device memory: code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and results (bitwise equal
+ * to hb_eval_batch's), but the two activation buffers live in a fixed 64 MiB
+ * device array of the library instead of a per-stream workspace; the array
+ * exists once per GPU and is held until the process ends.  The first call on a
+ * device looks up that device's copy (no allocation); no call allocates.
+ * Limit: ceil(n / 128) * 128 * (padded activation width summed over ensemble
+ * members) * (4 FP32, 2 BF16, 1 FP8 bytes) must fit in 32 MiB, e.g. n <= 8192
+ * for the 15-puzzle residual net at FP32, 16384 at BF16; a larger n returns
+ * HB_E_INVAL and launches nothing.  Every call on one GPU shares the array and
+ * leaves the last call's activations in it: calls that overlap in time on one
+ * GPU (other streams, other threads) race and give wrong results, so the
+ * caller serialises them.  FP8 models must be calibrated first. */
+hb_status hb_eval_batch_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
+                                float* d_raw_out, void* stream);
+
 /* Persistent, capture-friendly variant: the state count is read on the device
  * from *d_n (int32, 0 <= *d_n <= max_n) so one launch shape (sized for max_n)
  * serves every batch size; suitable for hipGraph capture. */

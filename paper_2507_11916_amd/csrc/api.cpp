@@ -242,6 +242,14 @@ hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t
     return model_eval(m, d_packed, n, nullptr, 0, d_h_out, d_raw_out, (hipStream_t)stream, nullptr);
 }
 
+hb_status hb_eval_batch_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
+                                float* d_raw_out, void* stream) {
+    if (!m) return fail(HB_E_INVAL, "null model");
+    if (n < 0) return fail(HB_E_INVAL, "negative count");
+    if (n > 0 && (!d_packed || !d_h_out)) return fail(HB_E_INVAL, "null device buffer");
+    return model_eval_noalloc(m, d_packed, n, d_h_out, d_raw_out, (hipStream_t)stream);
+}
+
 hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_t* d_n, int64_t max_n,
                               int32_t* d_h_out, float* d_raw_out, void* stream) {
     if (!m || !d_n || !d_packed || !d_h_out) return fail(HB_E_INVAL, "null argument");

@@ -409,7 +409,8 @@ hb_status model_profile_read(hb_model* m, hb_profile* out) {
 
 // Forward pass over one chunk of at most max_batch states.
 static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
-                            int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile) {
+                            int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile,
+                            bool timed = true) {
     const int prec = (int)m->opts.prec;
     if (cap && prec != 0) return fail(HB_E_INVAL, "calibration runs on a float32 model");
     const int rows = (int)round_up(m_cap, 128);
@@ -431,7 +432,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     G.ld_out = m->width_cap;
     G.out = X;
     G.out_inv_scale = 1.f / m->act_scale[0];
-    int pi = prof_begin(m, 0, s);
+    int pi = timed ? prof_begin(m, 0, s) : -1;
     if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "no layer-1 kernel for this domain/precision");
     HB_HIP(hipGetLastError());
     prof_end(m, pi, 0.0, s);
@@ -464,7 +465,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         g.r_scale = L.res_act >= 0 ? m->act_scale[L.res_act] : 1.f;
         g.out_inv_scale = 1.f / m->act_scale[L.out_act];
         g.relu = 1;
-        pi = prof_begin(m, 1, s);
+        pi = timed ? prof_begin(m, 1, s) : -1;
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());
         prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N * L.groups, s);
@@ -491,7 +492,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     H.ens_rule = m->ens_rule;
     H.h_out = d_h;
     H.raw = d_raw;
-    pi = prof_begin(m, 2, s);
+    pi = timed ? prof_begin(m, 2, s) : -1;
     if (!launch_head(H, prec, m_cap, s)) return fail(HB_E_UNSUPPORTED, "no head kernel for %d outputs", H.n_out);
     HB_HIP(hipGetLastError());
     prof_end(m, pi, 0.0, s);
@@ -527,6 +528,64 @@ hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int3
         const int c = (int)std::min<int64_t>(m->opts.max_batch, n - off);
         st = eval_chunk(m, w, d_packed + off * pb, c, nullptr, c, d_h + off,
                         d_raw ? d_raw + off * m->spec.n_out : nullptr, s, cap, force_tile);
+        if (st != HB_OK) return st;
+    }
+    return HB_OK;
+}
+
+// ------------------------------------------------ allocation-free evaluation
+// The activation buffers of hb_eval_batch_noalloc live in this fixed device
+// array (one copy per GPU, held until the process ends).  In host code the
+// name `scratch` is a host-side stand-in, not a device address: kernels are
+// given the address hipGetSymbolAddress returns with the device current, kept
+// per device in scratch_dev.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex scratch_mu;
+static unsigned char* scratch_dev[kScratchDevices];
+
+static hb_status scratch_address(int device, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[device]) {
+        void* p = nullptr;
+        HB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(HB_E_DEVICE, "no device address for the allocation-free scratch array");
+        scratch_dev[device] = static_cast<unsigned char*>(p);
+    }
+    *out = scratch_dev[device];
+    return HB_OK;
+}
+
+int64_t model_noalloc_capacity(const hb_model* m) {
+    const int eb = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
+    const size_t row_bytes = (size_t)m->width_cap * eb;
+    return (int64_t)(kScratchBytes / 2 / row_bytes) / 128 * 128;
+}
+
+hb_status model_eval_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h, float* d_raw,
+                             hipStream_t s) {
+    if (!m->calibrated) return fail(HB_E_INVAL, "FP8 model has no activation scales: call hb_model_calibrate first");
+    if (m->device < 0 || m->device >= kScratchDevices) return fail(HB_E_INVAL, "device %d out of range", m->device);
+    const int64_t cap = model_noalloc_capacity(m);
+    if (n > cap)
+        return fail(HB_E_INVAL, "n = %lld exceeds the allocation-free limit of %lld states for this model "
+                    "(two activation rows of %d elements per state in a %zu-byte array)",
+                    (long long)n, (long long)cap, m->width_cap, kScratchBytes);
+    if (n == 0) return HB_OK;
+    HB_HIP(hipSetDevice(m->device));
+    unsigned char* base = nullptr;
+    hb_status st = scratch_address(m->device, &base);
+    if (st != HB_OK) return st;
+    Workspace w;
+    w.x = base;
+    w.t = base + kScratchBytes / 2;
+    w.rows_cap = (int)cap;
+    const int pb = m->spec.domain == 2 ? 24 : 8;
+    for (int64_t off = 0; off < n; off += m->opts.max_batch) {
+        const int c = (int)std::min<int64_t>(m->opts.max_batch, n - off);
+        st = eval_chunk(m, &w, d_packed + off * pb, c, nullptr, c, d_h + off,
+                        d_raw ? d_raw + off * m->spec.n_out : nullptr, s, nullptr, -1, false);
         if (st != HB_OK) return st;
     }
     return HB_OK;

@@ -85,6 +85,9 @@ hb_status model_load_members(const std::vector<std::string>& paths, int rule, co
 void model_free(hb_model* m);
 hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n,
                      int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile = -1);
+hb_status model_eval_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h, float* d_raw,
+                             hipStream_t s);
+int64_t model_noalloc_capacity(const hb_model* m);
 hb_status model_calibrate(hb_model* m, const uint8_t* d_packed, int64_t n);
 hb_status model_prepare(hb_model* m, hipStream_t s);  // allocate the stream's workspace now
 hb_status model_tune(hb_model* m, const uint8_t* d_packed, int64_t n, double* report, int cap);
