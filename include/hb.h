@@ -210,6 +210,19 @@ hb_status hb_model_set_act_scales(hb_model* m, const float* scales, int n);
 hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
                         float* d_raw_out, void* stream);
 
+/* Layer-by-layer inspection (used by the parity tests): runs the forward pass
+ * on the n packed states at d_packed (device) and copies stored activation
+ * tensor `act` into d_out (device): n rows of `width` elements, row stride
+ * ld_out elements, in the model's operand type (float32; bfloat16 bits as
+ * uint16; e4m3 codes as uint8, value = code x the tensor's activation scale).
+ * act 0 is layer 1's output, 1..n_dense-1 the dense layers' outputs, then per
+ * residual block its inner activation and its output (n_act tensors in all);
+ * width = the layer's output width padded to 128 (times the ensemble size).
+ * Synchronous on `stream`; allocates a temporary h buffer.  HB_E_INVAL for an
+ * index outside 0..n_act-1 or ld_out < width. */
+hb_status hb_model_activation(hb_model* m, const uint8_t* d_packed, int64_t n, int act, void* d_out,
+                              int64_t ld_out, void* stream);
+
 /* Allocation-free variant of hb_eval_batch, for callers that cannot allocate
  * device memory: code under hipGraph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments, kernels and results (bitwise equal

@@ -85,6 +85,9 @@ def _declare(L):
     L.orc_net_forward.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp, vp]
     L.orc_net_calibrate.argtypes = [vp, vp, C.c_int64, vp]
     L.orc_net_fp8_col_scales.argtypes = [vp, C.c_int, vp]
+    L.orc_net_layer_width.argtypes = [vp, C.c_int]
+    L.orc_net_layer1.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp]
+    L.orc_net_layer.argtypes = [vp, C.c_int, vp, vp, C.c_int64, C.c_int, vp, vp]
     L.orc_h_batch.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_double, C.c_double, vp, vp]
     L.orc_ida.argtypes = [C.c_int, vp, C.POINTER(HSpec), C.c_int, C.c_int, C.c_int64,
                           C.POINTER(Iter), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
@@ -274,6 +277,36 @@ class Net:
         out = np.zeros(self.n_act, dtype=np.float64)
         lib().orc_net_calibrate(self._h, s.ctypes.data, s.shape[0], out.ctypes.data)
         return out
+
+    def is_residual_output(self, a):
+        """True for the activation a residual block's second layer writes."""
+        return self.n_dense <= a < self.n_act and (a - self.n_dense) % 2 == 1
+
+    def layer(self, a, x_in=None, r_in=None, states=None, mode=0):
+        """One layer in double precision from given (dequantised) inputs:
+        returns (z, A), the pre-activation and the sum of |terms| (inputs times
+        weights, bias, residual) that bounds any float32 evaluation's error.
+        a = 0 gathers layer 1 from `states`; 1..n_act-1 are the matrix layers
+        (r_in: the block input for a residual block's second layer); a = n_act
+        is the head."""
+        N = lib().orc_net_layer_width(self._h, a)
+        if N == 0:
+            raise ValueError(f"no layer for activation index {a}")
+        if a == 0:
+            s = np.ascontiguousarray(states, dtype=np.uint8).reshape(-1, STATE_LEN[self.domain])
+            n = s.shape[0]
+            z = np.zeros((n, N)); A = np.zeros((n, N))
+            lib().orc_net_layer1(self._h, s.ctypes.data, n, mode, z.ctypes.data, A.ctypes.data)
+            return z, A
+        x = np.ascontiguousarray(x_in, dtype=np.float64)
+        n = x.shape[0]
+        if self.is_residual_output(a) != (r_in is not None):
+            raise ValueError("r_in is required exactly for a residual block's second layer")
+        r = None if r_in is None else np.ascontiguousarray(r_in, dtype=np.float64)
+        z = np.zeros((n, N)); A = np.zeros((n, N))
+        lib().orc_net_layer(self._h, a, x.ctypes.data, None if r is None else r.ctypes.data, n, mode,
+                            z.ctypes.data, A.ctypes.data)
+        return z, A
 
     def fp8_col_scales(self, tensor_index):
         cols = None

@@ -284,6 +284,75 @@ int orc_net_forward(const orc_net* m, const uint8_t* states, int64_t n, int mode
     return 1;
 }
 
+/* ------------------------------------------------- one layer at a time
+ * For layer-by-layer parity: the pre-activation z of one layer computed in
+ * double precision from given (already quantised) inputs, together with
+ * A = sum of |terms| (|x_k w_kn| over k, plus |bias| and |residual|), which
+ * bounds the rounding error of any float32 evaluation order (the caller
+ * applies ReLU and the storage rounding).  Activation index a as in the
+ * forward pass: 0 = layer 1 (gathered from states), 1..n_dense-1 = dense
+ * layers, then two per residual block (t, then x), n_act = the head.
+ * x_in: n x K inputs (doubles, dequantised); r_in: n x N residual input for
+ * the second layer of a residual block (else ignored, may be NULL).
+ * Returns the output width, or 0 for a bad index. */
+static int layer_tensor(const orc_net* m, int a) {
+    /* each activation after layer 1, and the head, comes from one weight
+       tensor, in file order */
+    return 2 * a;
+}
+
+int orc_net_layer_width(const orc_net* m, int a) {
+    if (a < 0 || a > orc_net_n_act(m)) return 0;
+    return m->cols[layer_tensor(m, a)];
+}
+
+int orc_net_layer1(const orc_net* m, const uint8_t* states, int64_t n, int mode, double* z_out, double* abs_out) {
+    double* W0 = effective_weights(m, 0, mode);
+    int H = m->dims[0];
+    for (int64_t b = 0; b < n; b++) {
+        const uint8_t* s = states + b * m->P;
+        double* z = z_out + b * H;
+        double* A = abs_out + b * H;
+        for (int j = 0; j < H; j++) { z[j] = m->T[1][j]; A[j] = fabs(m->T[1][j]); }
+        for (int p = 0; p < m->P; p++) {
+            const double* w = W0 + (size_t)(p * m->S + s[p]) * H;
+            for (int j = 0; j < H; j++) { z[j] += w[j]; A[j] += fabs(w[j]); }
+        }
+    }
+    free(W0);
+    return H;
+}
+
+int orc_net_layer(const orc_net* m, int a, const double* x_in, const double* r_in, int64_t n, int mode,
+                  double* z_out, double* abs_out) {
+    int n_act = orc_net_n_act(m);
+    if (a < 1 || a > n_act) return 0;
+    int t = layer_tensor(m, a);
+    int K = m->rows[t], N = m->cols[t];
+    /* the second layer of residual block r produces activation n_dense + 2r + 1 */
+    int residual = a < n_act && a >= m->n_dense && (a - m->n_dense) % 2 == 1;
+    double* W = effective_weights(m, t, mode);
+    for (int64_t b = 0; b < n; b++) {
+        const double* x = x_in + b * K;
+        for (int j = 0; j < N; j++) {
+            double acc = 0.0, aa = 0.0;
+            for (int k = 0; k < K; k++) {
+                double term = x[k] * W[(size_t)k * N + j];
+                acc += term;
+                aa += fabs(term);
+            }
+            double bias = m->T[t + 1][j];
+            acc += bias;
+            aa += fabs(bias);
+            if (residual) { acc += r_in[b * N + j]; aa += fabs(r_in[b * N + j]); }
+            z_out[b * N + j] = acc;
+            abs_out[b * N + j] = aa;
+        }
+    }
+    free(W);
+    return N;
+}
+
 /* Static fp8 activation scales: for each stored activation tensor, the
  * smallest power of two a with max|activation| / a <= 448 over a calibration
  * set, from the unquantised forward pass. */

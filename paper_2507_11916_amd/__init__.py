@@ -119,6 +119,7 @@ def lib():
             "hb_eval_batch": ([vp, vp, i64, vp, vp, vp], C.c_int),
             "hb_eval_batch_dev_n": ([vp, vp, vp, i64, vp, vp, vp], C.c_int),
             "hb_eval_batch_noalloc": ([vp, vp, i64, vp, vp, vp], C.c_int),
+            "hb_model_activation": ([vp, vp, i64, C.c_int, vp, i64, vp], C.c_int),
             "hb_model_set_tile": ([vp, C.c_int], C.c_int),
             "hb_model_tune": ([vp, vp, i64, vp, C.c_int], C.c_int),
             "hb_model_autotune": ([vp, vp, i64, C.POINTER(TuneEntry), C.c_int, C.POINTER(C.c_int),
@@ -307,6 +308,13 @@ class Model:
         _check(lib().hb_eval_batch(self.handle, C.c_void_p(d_packed.data_ptr()), n,
                                    C.c_void_p(d_h.data_ptr()),
                                    None if d_raw is None else C.c_void_p(d_raw.data_ptr()), _stream(stream)))
+
+    def activation(self, d_packed, act, d_out, n=None, stream=None):
+        """hb_model_activation: stored activation tensor `act` of the forward pass
+        into d_out (a 2-D device tensor of the operand type's element size)."""
+        n = d_packed.shape[0] if n is None else n
+        _check(lib().hb_model_activation(self.handle, C.c_void_p(d_packed.data_ptr()), n, act,
+                                         C.c_void_p(d_out.data_ptr()), d_out.stride(0), _stream(stream)))
 
     def eval_batch_noalloc(self, d_packed, d_h, d_raw=None, n=None, stream=None):
         """hb_eval_batch_noalloc: as eval_batch, with the library's fixed device array as workspace."""

@@ -242,6 +242,26 @@ hb_status hb_eval_batch(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t
     return model_eval(m, d_packed, n, nullptr, 0, d_h_out, d_raw_out, (hipStream_t)stream, nullptr);
 }
 
+hb_status hb_model_activation(hb_model* m, const uint8_t* d_packed, int64_t n, int act, void* d_out,
+                              int64_t ld_out, void* stream) {
+    if (!m || !d_packed || !d_out) return fail(HB_E_INVAL, "null argument");
+    if (n < 0) return fail(HB_E_INVAL, "negative count");
+    if (act < 0 || act >= m->n_act) return fail(HB_E_INVAL, "activation index %d outside 0..%d", act, m->n_act - 1);
+    const int width = act == 0 ? m->members * m->N1_pad : m->layers[act - 1].N_pad * m->layers[act - 1].groups;
+    if (ld_out < width) return fail(HB_E_INVAL, "row stride %lld below the activation width %d", (long long)ld_out, width);
+    if (n == 0) return HB_OK;
+    const int eb = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
+    int32_t* d_h = nullptr;
+    HB_HIP(hipSetDevice(m->device));
+    HB_HIP(hipMalloc((void**)&d_h, (size_t)n * 4));
+    ActCopy ac{act, static_cast<uint8_t*>(d_out), ld_out * eb};
+    hb_status st = model_eval(m, d_packed, n, nullptr, 0, d_h, nullptr, (hipStream_t)stream, nullptr, -1, &ac);
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(d_h);
+    if (st == HB_OK && e != hipSuccess) return fail(HB_E_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return st;
+}
+
 hb_status hb_eval_batch_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h_out,
                                 float* d_raw_out, void* stream) {
     if (!m) return fail(HB_E_INVAL, "null model");

@@ -410,7 +410,14 @@ hb_status model_profile_read(hb_model* m, hb_profile* out) {
 // Forward pass over one chunk of at most max_batch states.
 static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
                             int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile,
-                            bool timed = true) {
+                            bool timed = true, const ActCopy* ac = nullptr) {
+    const int eb_act = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
+    auto copy_act = [&](int act, const void* buf, int width) -> hb_status {
+        if (!ac || ac->act != act) return HB_OK;
+        HB_HIP(hipMemcpy2DAsync(ac->out, (size_t)ac->ld_bytes, buf, (size_t)m->width_cap * eb_act,
+                                (size_t)width * eb_act, (size_t)n, hipMemcpyDeviceToDevice, s));
+        return HB_OK;
+    };
     const int prec = (int)m->opts.prec;
     if (cap && prec != 0) return fail(HB_E_INVAL, "calibration runs on a float32 model");
     const int rows = (int)round_up(m_cap, 128);
@@ -436,6 +443,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     if (!launch_gather(G, s)) return fail(HB_E_UNSUPPORTED, "no layer-1 kernel for this domain/precision");
     HB_HIP(hipGetLastError());
     prof_end(m, pi, 0.0, s);
+    if (hb_status st = copy_act(0, X, m->members * m->N1_pad); st != HB_OK) return st;
     if (cap) launch_absmax((const float*)X, n, m->members * m->N1_pad, m->width_cap, w->absmax + 0, s);
     // X holds the running activation x, Tb is scratch.  A dense layer writes
     // Tb and the two swap roles; the first layer of a residual block writes
@@ -469,6 +477,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());
         prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N * L.groups, s);
+        if (hb_status st = copy_act(L.out_act, g.C, L.N_pad * L.groups); st != HB_OK) return st;
         if (cap) launch_absmax((const float*)g.C, n, L.N_pad * L.groups, m->width_cap, w->absmax + L.out_act, s);
         if (!L.res_in_place && !res_first) std::swap(X, Tb);
     }
@@ -511,7 +520,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
 }
 
 hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n, int32_t* d_h,
-                     float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile) {
+                     float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile, const ActCopy* act_copy) {
     if (!m) return fail(HB_E_INVAL, "null model");
     if (!m->calibrated) return fail(HB_E_INVAL, "FP8 model has no activation scales: call hb_model_calibrate first");
     HB_HIP(hipSetDevice(m->device));
@@ -526,8 +535,11 @@ hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int3
     }
     for (int64_t off = 0; off < n; off += m->opts.max_batch) {
         const int c = (int)std::min<int64_t>(m->opts.max_batch, n - off);
+        ActCopy ac;
+        if (act_copy) { ac = *act_copy; ac.out += off * ac.ld_bytes; }
         st = eval_chunk(m, w, d_packed + off * pb, c, nullptr, c, d_h + off,
-                        d_raw ? d_raw + off * m->spec.n_out : nullptr, s, cap, force_tile);
+                        d_raw ? d_raw + off * m->spec.n_out : nullptr, s, cap, force_tile, true,
+                        act_copy ? &ac : nullptr);
         if (st != HB_OK) return st;
     }
     return HB_OK;

@@ -36,6 +36,12 @@ struct Workspace {
     unsigned* absmax = nullptr;  // calibration scratch (n_act entries)
 };
 
+struct ActCopy {  // copy of one stored activation tensor (hb_model_activation)
+    int act;
+    uint8_t* out;
+    int64_t ld_bytes;
+};
+
 struct CalibCapture {
     std::vector<float>* act_max;  // filled per activation tensor
 };
@@ -84,7 +90,8 @@ hb_status model_load(const char* path, const hb_model_opts& o, hb_model** out);
 hb_status model_load_members(const std::vector<std::string>& paths, int rule, const hb_model_opts& o, hb_model** out);
 void model_free(hb_model* m);
 hb_status model_eval(hb_model* m, const uint8_t* d_packed, int64_t n, const int32_t* d_n, int64_t max_n,
-                     int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile = -1);
+                     int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile = -1,
+                     const ActCopy* act_copy = nullptr);
 hb_status model_eval_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h, float* d_raw,
                              hipStream_t s);
 int64_t model_noalloc_capacity(const hb_model* m);

@@ -243,3 +243,49 @@ def test_pdb_entry_points_reject_bad_arguments():
         apdb.lookup(np.zeros((1, 16), dtype=np.uint8))
     apdb.close()
     pdb.close()
+
+
+def _md_of(st, tiles):
+    where = np.argsort(st, axis=1)  # cell of each tile
+    return sum(np.abs(where[:, t] // 4 - t // 4) + np.abs(where[:, t] % 4 - t % 4) for t in tiles)
+
+
+def _big_group_pins(group, six, n_tiles):
+    """Pins of a library pattern table over `group` (7 or 8 tiles) built with
+    every other tile as its own group (so h = PDB(group) + MD(others)):
+    every placement of the group is reached (16!/(16-k)!); it dominates the
+    oracle's table over the first six of its tiles plus the Manhattan distance
+    of the rest (a path for the k tiles is a path for those six, and the other
+    tiles' moves are at least their Manhattan distance), strictly somewhere;
+    it has MD's parity; and it never exceeds optimal costs of short walks."""
+    others = [t for t in range(1, 16) if t not in group]
+    pdb = hb.Pdb(groups=[group] + [[t] for t in others])
+    counts, _ = pdb.value_counts(128)
+    placements = 1
+    for i in range(n_tiles):
+        placements *= 16 - i
+    assert counts.sum() == placements + 16 * len(others)
+    st = synth.stp_walks(4, synth.throughput_seeds(20000, 78), lengths=200)
+    h = pdb.lookup(st)
+    pk = h - _md_of(st, others)
+    lower = O.apdb_group_lookup(O.apdb_group_table(six), st) + _md_of(st, [t for t in group if t not in six])
+    assert np.all(pk >= lower) and np.any(pk > lower)
+    md = _md_of(st, range(1, 16))
+    assert np.all(h >= md) and np.all((h - md) % 2 == 0)
+    assert pdb.lookup(O.goal(O.STP4)[None])[0] == 0
+    for s in synth.stp_walks(4, synth.config_seeds(9, 8), lengths=34):
+        assert pdb.lookup(s[None])[0] <= O.ida(O.STP4, s, hkind=O.H_MD)["cost"]
+    pdb.close()
+
+
+@pytest.mark.slow
+def test_seven_tile_group_of_the_paper_split():
+    """Tiles 1-7, the first half of the paper's 7-8 additive PDB."""
+    _big_group_pins(list(range(1, 8)), range(1, 7), 7)
+
+
+@pytest.mark.slow
+def test_eight_tile_group_of_the_paper_split():
+    """Tiles 8-15, the second half of the paper's 7-8 additive PDB (518,918,400
+    placements: index arithmetic at the library's largest group size)."""
+    _big_group_pins(list(range(8, 16)), range(8, 14), 8)

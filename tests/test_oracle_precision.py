@@ -227,3 +227,37 @@ def test_bf16_forward_closed_form(tmp_path):
     st = synth.stp_walks(3, range(5), lengths=12)
     np.testing.assert_array_equal(net.forward(st, mode=1)[:, 0], 8.09375)
     assert net.forward(st, mode=0)[0, 0] != 8.09375
+
+
+# ------------------------------------------------ one layer at a time
+@pytest.mark.parametrize("name", ["stp4_res", "rc_cls"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_layer_by_layer_composes_to_the_forward_pass(net_files, name, mode):
+    """orc_net_layer (used for the library's layer-by-layer parity) applied
+    layer after layer, with ReLU and the storage rounding between layers (bf16
+    and e4m3 here from the format definitions above), gives the oracle's
+    forward pass; its sum of |terms| bounds |z|.  A layer that took the wrong
+    tensor, skipped the residual input or the bias fails this."""
+    net = O.Net(net_files[name])
+    dom = 2 if name == "rc_cls" else 1
+    if dom == 2:
+        mv = synth.rc_walk_moves_array(synth.throughput_seeds(6, 31), length_base=20, length_span=11)
+        st = O.apply_moves(2, mv)
+    else:
+        st = synth.stp_walks(4, synth.throughput_seeds(6, 31), lengths=200)
+    scales = net.calibrate(st) if mode == 2 else np.ones(net.n_act)
+    acts = {}
+    for a in range(net.n_act):
+        if a == 0:
+            z, A = net.layer(0, states=st, mode=mode)
+        else:
+            r = acts[a - 2] if net.is_residual_output(a) else None
+            z, A = net.layer(a, x_in=acts[a - 1], r_in=r, mode=mode)
+        assert np.all(A >= np.abs(z) * (1 - 1e-12))
+        v = np.maximum(z, 0.0)
+        acts[a] = v if mode == 0 else bf16(v) if mode == 1 else e4m3(v / scales[a]) * scales[a]
+    y, _ = net.layer(net.n_act, x_in=acts[net.n_act - 1], mode=mode)
+    ref = net.forward(st, mode=mode, act_scale=scales if mode == 2 else None)
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-9)
+    with pytest.raises(ValueError):
+        net.layer(net.n_act + 1, x_in=acts[0])
