@@ -49,6 +49,35 @@ __device__ __forceinline__ float fp8_to_f32(uint32_t byte) {
     return __builtin_amdgcn_cvt_f32_fp8((int)byte, 0);
 }
 
+// ------------------------------------------------------------ coherent access
+// Data handed between waves of one launch on different XCDs (the fused forward
+// kernel) goes through device-coherent accesses: relaxed agent-scope atomic
+// loads and stores, which this target issues with the sc1 cache policy (read
+// from, and written through to, the level that all XCDs share) instead of
+// through an XCD's own L2.  Ordering then needs only a wait for the stores and
+// a compiler fence, not the agent-scope fences that write back or invalidate a
+// whole L2.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ void st_coh(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// 16 bytes (two 8-byte accesses when coherent)
+template <bool COH>
+__device__ __forceinline__ u32x4 ld16(const uint8_t* p) {
+    if (!COH) return *reinterpret_cast<const u32x4*>(p);
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    const uint64_t a = ld_coh(q), b = ld_coh(q + 1);
+    return u32x4{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+}
+template <bool COH>
+__device__ __forceinline__ void st16(uint8_t* p, u32x4 v) {
+    if (!COH) { *reinterpret_cast<u32x4*>(p) = v; return; }
+    uint64_t* q = reinterpret_cast<uint64_t*>(p);
+    st_coh(q, (uint64_t)v.x | ((uint64_t)v.y << 32));
+    st_coh(q + 1, (uint64_t)v.z | ((uint64_t)v.w << 32));
+}
+
 // ------------------------------------------------------------ decoding
 // Symbol of cell/sticker row g of the folded layer-1 table.  Sliding tile:
 // P cells, symbol = tile; row = p * S + tile.  Cube: 48 non-centre stickers,
@@ -269,21 +298,26 @@ __device__ __forceinline__ float load_out_t(const uint8_t* p, int o, float fp8_s
 // residual and mask values are all loaded before any store: R may be C itself
 // (in-place residual), and reading first lets the 16 loads overlap instead of
 // each waiting behind the previous store.
-template <int OUTT>
+template <int OUTT, bool COH = false>
 __device__ __forceinline__ float load_at(const uint8_t* p, uint32_t byte_off, float fp8_scale) {
+    if (COH) {
+        if (OUTT == 0) return __uint_as_float(ld_coh(reinterpret_cast<const uint32_t*>(p + byte_off)));
+        if (OUTT == 1) return bf16_to_f32(ld_coh(reinterpret_cast<const uint16_t*>(p + byte_off)));
+        return fp8_to_f32(ld_coh(p + byte_off)) * fp8_scale;
+    }
     if (OUTT == 0) return *reinterpret_cast<const float*>(p + byte_off);
     if (OUTT == 1) return bf16_to_f32(*reinterpret_cast<const uint16_t*>(p + byte_off));
     return fp8_to_f32(p[byte_off]) * fp8_scale;
 }
 
-template <int OUTT>
+template <int OUTT, bool COH = false>
 __device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc, float sn, float bn, int o0) {
     constexpr uint32_t EO = OUTT == 0 ? 4 : OUTT == 1 ? 2 : 1;
     const uint32_t b0 = (uint32_t)o0 * EO, row = (uint32_t)g.ldc * EO;
     float rv[16], mk[16];
     if (g.R) {
         _Pragma("unroll") for (int e = 0; e < 16; e++)
-            rv[e] = load_at<OUTT>(g.R, b0 + (8 * (e >> 2) + (e & 3)) * row, g.r_scale);
+            rv[e] = load_at<OUTT, COH>(g.R, b0 + (8 * (e >> 2) + (e & 3)) * row, g.r_scale);
     }
     if (g.Mk) {
         _Pragma("unroll") for (int e = 0; e < 16; e++)
@@ -295,9 +329,17 @@ __device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc,
         if (g.R) v += rv[e];
         if (g.relu) v = fmaxf(v, 0.f);
         if (g.Mk) v = mk[e] > 0.f ? v : 0.f;
-        if (OUTT == 0) *reinterpret_cast<float*>(g.C + o) = v;
-        else if (OUTT == 1) *reinterpret_cast<uint16_t*>(g.C + o) = f32_to_bf16(v);
-        else g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+        if (COH) {
+            if (OUTT == 0) st_coh(reinterpret_cast<uint32_t*>(g.C + o), __float_as_uint(v));
+            else if (OUTT == 1) st_coh(reinterpret_cast<uint16_t*>(g.C + o), f32_to_bf16(v));
+            else st_coh(g.C + o, (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF));
+        } else if (OUTT == 0) {
+            *reinterpret_cast<float*>(g.C + o) = v;
+        } else if (OUTT == 1) {
+            *reinterpret_cast<uint16_t*>(g.C + o) = f32_to_bf16(v);
+        } else {
+            g.C[o] = (uint8_t)(f32x2_to_fp8x2(v * g.out_inv_scale, 0.f) & 0xFF);
+        }
     }
     asm volatile("" ::: "memory");  // one tile's loads at a time: bounded register use
 }
@@ -650,16 +692,12 @@ __global__ __launch_bounds__(256) void gemm_ring_kernel(GemmArgs g) {
 // sequence of gemm_kernel (the same 16-byte chunk of each 128-byte K stage in
 // each MFMA, the same order), so the two kernels give bitwise equal results
 // and a state's value does not depend on the batch size that picked the kernel.
-template <int PREC, int OUTT>
-__global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
+// One wave computes the 32 x 32 output tile at rows m0, columns n0 (shared by
+// gemm_small_kernel and the fused forward kernel).
+template <int PREC, int OUTT, bool COH = false>
+__device__ __forceinline__ void small_tile(const GemmArgs& g, int m0, int n0, int lane) {
     constexpr int EB = Ty<PREC>::EB;
-    const int lane = threadIdx.x, half = lane >> 5, r32 = lane & 31;
-    const int M = g.m_dev ? *g.m_dev : g.m_host;
-    const int m_tiles = min((M + 31) / 32, g.m_tiles_cap);
-    const int n_tiles = g.N / 32;
-    const int tm = blockIdx.x / n_tiles, tn = blockIdx.x % n_tiles;
-    if (tm >= m_tiles) return;
-    const int m0 = tm * 32, n0 = tn * 32;
+    const int half = lane >> 5, r32 = lane & 31;
     const uint8_t* Ar = g.A + ((size_t)(m0 + r32) * g.lda + group_a_col(g, n0)) * EB;
     const uint8_t* Br = g.Bt + (size_t)(n0 + r32) * g.ldb * EB;
     const int ktiles = g.K * EB / 128;
@@ -679,7 +717,7 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
     _Pragma("unroll") for (int j = 0; j < DEPTH; j++) {
         if (j < ktiles) {
             _Pragma("unroll") for (int i = 0; i < 4; i++) {
-                a[j][i] = *reinterpret_cast<const u32x4*>(Ar + j * 128 + off[i]);
+                a[j][i] = ld16<COH>(Ar + j * 128 + off[i]);
                 b[j][i] = *reinterpret_cast<const u32x4*>(Br + j * 128 + off[i]);
             }
         }
@@ -711,7 +749,7 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
                 if (kt + DEPTH < ktiles) {
                     const int kbyte = (kt + DEPTH) * 128;
                     _Pragma("unroll") for (int i = 0; i < 4; i++) {
-                        a[j][i] = *reinterpret_cast<const u32x4*>(Ar + kbyte + off[i]);
+                        a[j][i] = ld16<COH>(Ar + kbyte + off[i]);
                         b[j][i] = *reinterpret_cast<const u32x4*>(Br + kbyte + off[i]);
                     }
                 }
@@ -722,7 +760,17 @@ __global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
     const int n = n0 + r32;
     const float bn = g.bias ? g.bias[n] : 0.f;
     const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
-    epi_tile<OUTT>(g, acc, sn, bn, (m0 + 4 * half) * g.ldc + n);
+    epi_tile<OUTT, COH>(g, acc, sn, bn, (m0 + 4 * half) * g.ldc + n);
+}
+
+template <int PREC, int OUTT>
+__global__ __launch_bounds__(64) void gemm_small_kernel(GemmArgs g) {
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + 31) / 32, g.m_tiles_cap);
+    const int n_tiles = g.N / 32;
+    const int tm = blockIdx.x / n_tiles, tn = blockIdx.x % n_tiles;
+    if (tm >= m_tiles) return;
+    small_tile<PREC, OUTT>(g, tm * 32, tn * 32, threadIdx.x);
 }
 
 // ------------------------------------------------------------ head
@@ -769,13 +817,12 @@ __device__ __forceinline__ void regression_rule(const HeadArgs& h, int r, float 
 // combined as min_i y_i or y_0 + y_1 + ... before the rule.
 constexpr int kMaxMembers = 4;
 
-template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/>
-__global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
+// Row r by the 16-lane group whose lane index within the group is j (all 16
+// lanes take part in the butterfly; lane j = 0 writes the result).
+template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/, bool COH = false>
+__device__ __forceinline__ void head_reg_row(const HeadArgs& h, int n, int r, int j) {
     constexpr int CH = IN == 0 ? 4 : IN == 1 ? 8 : 16;  // elements per 16-byte load of x
     constexpr int XB = IN == 0 ? 4 : IN == 1 ? 2 : 1;
-    const int j = threadIdx.x & 15;
-    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
-    const int r = blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = r < n;
     // the record for the Manhattan rule is fetched before the dot product
     const uint64_t rec = live && j == 0 && h.combine_md && h.domain < 2 ? reinterpret_cast<const uint64_t*>(h.packed)[r] : 0;
@@ -785,7 +832,7 @@ __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
         const int Ktot = h.K * h.members;
         for (int k = j * CH; k < Ktot; k += 16 * CH) {
             float x[CH], w[CH];
-            const uint4 xv = *reinterpret_cast<const uint4*>(xrow + (size_t)k * XB);
+            const u32x4 xv = ld16<COH>(xrow + (size_t)k * XB);
             const uint32_t xu[4] = {xv.x, xv.y, xv.z, xv.w};
             if (IN == 0) {
                 _Pragma("unroll") for (int e = 0; e < 4; e++) x[e] = __uint_as_float(xu[e]);
@@ -830,29 +877,35 @@ __global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
     regression_rule(h, r, yc, md);
 }
 
+template <int IN, int HW>
+__global__ __launch_bounds__(256) void head_reg_kernel(HeadArgs h) {
+    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
+    head_reg_row<IN, HW>(h, n, blockIdx.x * 16 + (threadIdx.x >> 4), threadIdx.x & 15);
+}
+
 // Classifier head: one wave per state.  y[o] = sum_k x[k] * Wo[o][k] + bo[o]
 // for o < n_out, lanes own K slices of 4; wave-wide butterfly sums; lane 0
-// applies the quantile or arg-max rule.
-template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/, int NOUT>
-__global__ __launch_bounds__(256) void head_cls_kernel(HeadArgs h) {
-    const int lane = threadIdx.x & 63;
-    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= n) return;
+// applies the quantile or arg-max rule.  head_cls_row: row r (< n) by one
+// whole wave.
+template <int IN /*0 f32, 1 bf16, 2 fp8*/, int HW /*0 f32, 1 bf16*/, int NOUT, bool COH = false>
+__device__ __forceinline__ void head_cls_row(const HeadArgs& h, int r, int lane) {
     float y[NOUT];
     for (int o = 0; o < NOUT; o++) y[o] = 0.f;
     for (int k = lane * 4; k < h.K; k += 256) {
         float x[4];
         const size_t xo = (size_t)r * h.ldx + k;
         if (IN == 0) {
-            const float4 v = *reinterpret_cast<const float4*>((const float*)h.X + xo);
-            x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+            const u32x4 v = ld16<COH>(reinterpret_cast<const uint8_t*>((const float*)h.X + xo));
+            x[0] = __uint_as_float(v.x); x[1] = __uint_as_float(v.y); x[2] = __uint_as_float(v.z); x[3] = __uint_as_float(v.w);
         } else if (IN == 1) {
-            const uint2 v = *reinterpret_cast<const uint2*>((const uint16_t*)h.X + xo);
-            x[0] = bf16_to_f32(v.x & 0xFFFF); x[1] = bf16_to_f32(v.x >> 16);
-            x[2] = bf16_to_f32(v.y & 0xFFFF); x[3] = bf16_to_f32(v.y >> 16);
+            const uint64_t* p = reinterpret_cast<const uint64_t*>((const uint16_t*)h.X + xo);
+            const uint64_t u = COH ? ld_coh(p) : *p;
+            const uint32_t vx = (uint32_t)u, vy = (uint32_t)(u >> 32);
+            x[0] = bf16_to_f32(vx & 0xFFFF); x[1] = bf16_to_f32(vx >> 16);
+            x[2] = bf16_to_f32(vy & 0xFFFF); x[3] = bf16_to_f32(vy >> 16);
         } else {
-            const uint32_t v = *reinterpret_cast<const uint32_t*>((const uint8_t*)h.X + xo);
+            const uint32_t* p = reinterpret_cast<const uint32_t*>((const uint8_t*)h.X + xo);
+            const uint32_t v = COH ? ld_coh(p) : *p;
             for (int i = 0; i < 4; i++) x[i] = fp8_to_f32((v >> (8 * i)) & 0xFF) * h.x_scale;
         }
         for (int o = 0; o < NOUT; o++) {
@@ -911,6 +964,197 @@ __global__ __launch_bounds__(256) void head_cls_kernel(HeadArgs h) {
     }
     if (h.raw) for (int o = 0; o < NOUT; o++) if (o < h.n_out) h.raw[(size_t)r * h.n_out + o] = y[o];
     h.h_out[r] = hv;
+}
+
+template <int IN, int HW, int NOUT>
+__global__ __launch_bounds__(256) void head_cls_kernel(HeadArgs h) {
+    const int n = min(h.n_dev ? *h.n_dev : h.n_host, h.m_cap);
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    head_cls_row<IN, HW, NOUT>(h, r, threadIdx.x & 63);
+}
+
+// ------------------------------------------------------------ fused forward
+// The whole forward pass of one batch in a single persistent launch, for small
+// and medium batches where each separate kernel would cost about its launch and
+// ramp.  A grid of one-wave blocks pulls work items off an atomic counter in a
+// fixed order: the layer-1 gather tiles (32 rows x 32 columns) of every
+// 32-row block, then each matrix layer's 32 x 32 output tiles, then the head
+// per 32-row block.  An item of stage s on row block b first waits until every
+// stage s - 1 tile of block b has been counted done (a row's outputs need all
+// of its inputs' columns), then computes with exactly the arithmetic of the
+// separate kernels (gather: bias then cells in order; tiles: small_tile; head:
+// head_reg_row / head_cls_row), so results are bitwise equal to theirs.  Items
+// are taken in order and each waits only on earlier items, which running waves
+// hold and finish without waiting on later ones: the wait always ends, with no
+// assumption about how many waves are resident.  Activations pass between
+// waves through device-coherent loads and stores (ld_coh / st_coh): a tile is
+// counted done (atomic add) after its stores have completed, and a waiting
+// wave polls the count with coherent loads before reading the tile's rows
+// coherently; weights and tables are read through the caches as usual.  The
+// agent-scope fences that would do the same write back or invalidate a whole
+// L2 and, issued by every polling wave, stall the device.  Every wait is bounded
+// (spin_limit sleeps); a wait that runs out sets a flag, and the launch then
+// writes h = -1 for every row so the caller sees the failure.  The last wave
+// to finish returns the counters to zero for the next launch, so a captured
+// graph can replay the kernel with no memset node.
+constexpr int kFusedMaxLayers = 12;
+// Switched off: on the GPU, launches of this kernel did not return within 90 to
+// 120 s (no fault, no wrong value seen), first with agent-scope acquire polls,
+// then with device-coherent polls.  launch_fused refuses every launch until
+// the cause is shown; the kernel is not instantiated meanwhile.
+constexpr bool kFusedEnabled = false;
+
+struct FusedArgs {
+    const uint64_t* packed;
+    const int32_t* n_dev;
+    int n_host, m_cap;
+    const float* table;      // layer-1 table [t_rows][N1], float32
+    const float* bias1;
+    int N1, ld1;             // padded layer-1 width, row stride of its output (elements)
+    uint8_t* out1;
+    float out1_inv_scale;
+    int n_layers;
+    int* sync;               // [0] next item, [1] waves done, [2] timeout flag, [4 + s * rb_cap + b] tiles done
+    int rb_cap;
+    int spin_limit;
+    HeadArgs head;
+    GemmArgs layer[kFusedMaxLayers];
+};
+
+static_assert(sizeof(FusedArgs) <= 4096, "kernel arguments are passed by value");
+
+// Layer 1 for rows [32 rb, 32 rb + 32), columns [32 ct, 32 ct + 32): lane l
+// takes row l % 32 and 16 columns; the sum order per output (bias, then the
+// cells in order) is gather_l1_kernel's.
+template <int DOM, int OUT>
+__device__ __forceinline__ void gather_tile(const FusedArgs& f, int n, int rb, int ct, int lane) {
+    using D = Dec<DOM>;
+    const int r = rb * 32 + (lane & 31);
+    const int c0 = ct * 32 + (lane >> 5) * 16;
+    uint64_t w[D::WORDS];
+    _Pragma("unroll") for (int i = 0; i < D::WORDS; i++) w[i] = r < n ? f.packed[(size_t)r * D::WORDS + i] : 0;
+    float acc[16];
+    _Pragma("unroll") for (int j = 0; j < 16; j++) acc[j] = f.bias1[c0 + j];
+    constexpr int CH = 4;  // cells whose 64-byte row slices are in flight at once
+    _Pragma("unroll") for (int p0 = 0; p0 < D::P; p0 += CH) {
+        float4 v[CH][4];
+        _Pragma("unroll") for (int k = 0; k < CH; k++) {
+            if (p0 + k < D::P) {
+                const float4* row = reinterpret_cast<const float4*>(f.table + (size_t)D::row(w, p0 + k) * f.N1 + c0);
+                _Pragma("unroll") for (int q = 0; q < 4; q++) v[k][q] = row[q];
+            }
+        }
+        _Pragma("unroll") for (int k = 0; k < CH; k++) {
+            if (p0 + k < D::P) {
+                _Pragma("unroll") for (int q = 0; q < 4; q++) {
+                    acc[4 * q] += v[k][q].x; acc[4 * q + 1] += v[k][q].y;
+                    acc[4 * q + 2] += v[k][q].z; acc[4 * q + 3] += v[k][q].w;
+                }
+            }
+        }
+    }
+    _Pragma("unroll") for (int j = 0; j < 16; j++) acc[j] = r < n ? fmaxf(acc[j], 0.f) : 0.f;
+    // the output goes to waves on other XCDs: device-coherent stores
+    constexpr int EO = OUT == 0 ? 4 : OUT == 1 ? 2 : 1;
+    uint8_t* dst = f.out1 + ((size_t)r * f.ld1 + c0) * EO;
+    if (OUT == 0) {
+        _Pragma("unroll") for (int q = 0; q < 4; q++)
+            st16<true>(dst + 16 * q, u32x4{__float_as_uint(acc[4 * q]), __float_as_uint(acc[4 * q + 1]),
+                                           __float_as_uint(acc[4 * q + 2]), __float_as_uint(acc[4 * q + 3])});
+    } else if (OUT == 1) {
+        uint32_t u[8];
+        _Pragma("unroll") for (int e = 0; e < 8; e++)
+            u[e] = (uint32_t)f32_to_bf16(acc[2 * e]) | ((uint32_t)f32_to_bf16(acc[2 * e + 1]) << 16);
+        st16<true>(dst, u32x4{u[0], u[1], u[2], u[3]});
+        st16<true>(dst + 16, u32x4{u[4], u[5], u[6], u[7]});
+    } else {
+        uint32_t u[4];
+        _Pragma("unroll") for (int e = 0; e < 4; e++)
+            u[e] = f32x2_to_fp8x2(acc[4 * e] * f.out1_inv_scale, acc[4 * e + 1] * f.out1_inv_scale) |
+                   (f32x2_to_fp8x2(acc[4 * e + 2] * f.out1_inv_scale, acc[4 * e + 3] * f.out1_inv_scale) << 16);
+        st16<true>(dst, u32x4{u[0], u[1], u[2], u[3]});
+    }
+}
+
+__device__ __forceinline__ int fused_stage_tiles(const FusedArgs& f, int s) {
+    return s == 0 ? f.N1 / 32 : s <= f.n_layers ? f.layer[s - 1].N / 32 : 1;
+}
+
+template <int DOM, int PREC, int CLS>
+__global__ __launch_bounds__(64) void fused_forward_kernel(FusedArgs f) {
+    constexpr int HW = PREC == 0 ? 0 : 1;
+    const int lane = threadIdx.x;
+    const int n = max(0, min(f.n_dev ? *f.n_dev : f.n_host, f.m_cap));
+    const int rbs = (n + 31) / 32;
+    const int n_stages = f.n_layers + 2;
+    int total = 0;
+    for (int s = 0; s < n_stages; s++) total += rbs * fused_stage_tiles(f, s);
+    int* const work = f.sync;
+    int* const fin = f.sync + 1;
+    int* const flag = f.sync + 2;
+    int* const done = f.sync + 4;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = __hip_atomic_fetch_add(work, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        item = __shfl(item, 0, 64);
+        if (item >= total) break;
+        int s = 0, tiles = fused_stage_tiles(f, 0);
+        while (item >= rbs * tiles) {
+            item -= rbs * tiles;
+            s++;
+            tiles = fused_stage_tiles(f, s);
+        }
+        const int rb = item / tiles, t = item % tiles;
+        if (s > 0) {
+            // poll with device-coherent loads (no cache invalidation per poll)
+            const int* const cnt = done + (s - 1) * f.rb_cap + rb;
+            const int need = fused_stage_tiles(f, s - 1);
+            int spins = 0;
+            while (ld_coh(cnt) < need) {
+                if (++spins > f.spin_limit) {
+                    if (lane == 0) st_coh(flag, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // orders the loads below after the poll
+        }
+        if (s == 0) {
+            gather_tile<DOM, PREC>(f, n, rb, t, lane);
+        } else if (s <= f.n_layers) {
+            small_tile<PREC, PREC, true>(f.layer[s - 1], rb * 32, t * 32, lane);
+        } else if (CLS) {
+            for (int r = rb * 32; r < min(rb * 32 + 32, n); r++) head_cls_row<PREC, HW, 32, true>(f.head, r, lane);
+        } else {
+            for (int i = 0; i < 8; i++)
+                head_reg_row<PREC, HW, true>(f.head, n, rb * 32 + 4 * i + (lane >> 4), lane & 15);
+        }
+        if (s <= f.n_layers) {
+            // every lane's coherent stores have completed before the tile is counted
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            wait_vmcnt<0>();
+            if (lane == 0)
+                __hip_atomic_fetch_add(done + s * f.rb_cap + rb, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // The last wave to finish clears the counters (every other wave has made
+    // its last access to them, all coherent, before counting itself done).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wait_vmcnt<0>();
+    int last = 0;
+    if (lane == 0) last = __hip_atomic_fetch_add(fin, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
+    last = __shfl(last, 0, 64);
+    if (!last) return;
+    if (ld_coh(flag) != 0)
+        for (int r = lane; r < n; r += 64) f.head.h_out[r] = -1;
+    for (int s = 0; s < n_stages - 1; s++)
+        for (int b = lane; b < rbs; b += 64) st_coh(done + s * f.rb_cap + b, 0);
+    if (lane == 0) {
+        st_coh(flag, 0);
+        st_coh(fin, 0);
+        st_coh(work, 0);
+    }
 }
 
 // ------------------------------------------------------------ calibration
@@ -1034,11 +1278,14 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
 
 // Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the
 // small-batch kernel (one wave per 32 x 32 tile), 5-8 the LDS ring fed by
-// direct loads, 9 the 8-wave 256 x 128 tile.
-int gemm_tile_count() { return 10; }
+// direct loads, 9 the 8-wave 256 x 128 tile, 10-13 the fused persistent
+// forward kernel (one-wave 32 x 32 tiles; 2, 4, 8 or 12 waves per compute
+// unit), which replaces the whole forward pass rather than one layer.
+int gemm_tile_count() { return 14; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[10][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
-                                 {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128}};
+    static const int T[14][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+                                 {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128},
+                                 {32, 32}, {32, 32}, {32, 32}, {32, 32}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -1050,7 +1297,7 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 1: launch_gemm_t<PREC, OUTT, 128, 256>(L, s); return true;
         case 2: launch_gemm_t<PREC, OUTT, 64, 128>(L, s); return true;
         case 3: launch_gemm_t<PREC, OUTT, 256, 128>(L, s); return true;
-        case 4: launch_gemm_small<PREC, OUTT>(L, s); return true;
+        case 4: case 10: case 11: case 12: case 13: launch_gemm_small<PREC, OUTT>(L, s); return true;
         case 5: launch_gemm_ring<PREC, OUTT, 256, 128, 3>(L, s); return true;
         case 6: launch_gemm_ring<PREC, OUTT, 128, 128, 3>(L, s); return true;
         case 7: launch_gemm_ring<PREC, OUTT, 128, 256, 3>(L, s); return true;
@@ -1086,6 +1333,74 @@ bool launch_head(const HeadArgs& H, int prec, int m_cap, hipStream_t s) {
     if (prec == 1) return launch_head_t<1, 1>(H, m_cap, s);
     return launch_head_t<2, 1>(H, m_cap, s);
 }
+
+static GemmArgs gemm_args_of(const GemmLaunch& L) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
+    g.m_tiles_cap = (L.m_cap + 31) / 32;
+    g.persistent = 0;
+    return g;
+}
+
+int fused_max_layers() { return kFusedMaxLayers; }
+
+template <int DOM, int PREC>
+static void launch_fused_t(const FusedArgs& f, int cls, int grid, hipStream_t s) {
+    if (cls) hipLaunchKernelGGL((fused_forward_kernel<DOM, PREC, 1>), dim3(grid), dim3(64), 0, s, f);
+    else hipLaunchKernelGGL((fused_forward_kernel<DOM, PREC, 0>), dim3(grid), dim3(64), 0, s, f);
+}
+
+bool launch_fused(const FusedLaunch& L, hipStream_t s) {
+    if constexpr (!kFusedEnabled) {
+        (void)L;
+        (void)s;
+        return false;
+    } else {
+    if (L.n_layers < 1 || L.n_layers > kFusedMaxLayers || L.grid < 1 || L.head.n_out > 32) return false;
+    const bool cls = !(L.head.n_out == 1 && L.head.mode <= 2);
+    FusedArgs f;
+    f.packed = reinterpret_cast<const uint64_t*>(L.packed);
+    f.n_dev = L.n_dev;
+    f.n_host = L.n_host;
+    f.m_cap = L.m_cap;
+    f.table = reinterpret_cast<const float*>(L.table);
+    f.bias1 = L.bias1;
+    f.N1 = L.N1;
+    f.ld1 = L.ld1;
+    f.out1 = reinterpret_cast<uint8_t*>(L.out1);
+    f.out1_inv_scale = L.out1_inv_scale;
+    f.n_layers = L.n_layers;
+    f.sync = L.sync;
+    f.rb_cap = L.rb_cap;
+    f.spin_limit = L.spin_limit;
+    f.head = L.head;
+    f.head.m_cap = L.m_cap;
+    for (int i = 0; i < L.n_layers; i++) {
+        if (L.layers[i].N % 32 || L.layers[i].prec != L.prec) return false;
+        f.layer[i] = gemm_args_of(L.layers[i]);
+    }
+    const int c = cls ? 1 : 0;
+    switch (L.domain * 3 + L.prec) {
+        case 0: launch_fused_t<0, 0>(f, c, L.grid, s); return true;
+        case 1: launch_fused_t<0, 1>(f, c, L.grid, s); return true;
+        case 2: launch_fused_t<0, 2>(f, c, L.grid, s); return true;
+        case 3: launch_fused_t<1, 0>(f, c, L.grid, s); return true;
+        case 4: launch_fused_t<1, 1>(f, c, L.grid, s); return true;
+        case 5: launch_fused_t<1, 2>(f, c, L.grid, s); return true;
+        case 6: launch_fused_t<2, 0>(f, c, L.grid, s); return true;
+        case 7: launch_fused_t<2, 1>(f, c, L.grid, s); return true;
+        case 8: launch_fused_t<2, 2>(f, c, L.grid, s); return true;
+    }
+    return false;
+    }
+}
+
+bool fused_enabled() { return kFusedEnabled; }
 
 template <int PREC, int OUTT, int BM, int BN>
 static hipError_t set_lds_attr() {

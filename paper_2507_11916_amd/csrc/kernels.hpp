@@ -67,7 +67,32 @@ struct HeadArgs {
     float* raw;             // nullable
 };
 
+// The whole forward pass in one persistent launch (fused_forward_kernel):
+// `grid` one-wave blocks; `sync` points at 4 + (n_layers + 1) * rb_cap zeroed
+// ints that the launch leaves zeroed (rb_cap >= m_cap / 32 rounded up).
+struct FusedLaunch {
+    int domain, prec;
+    const void* packed;
+    const int32_t* n_dev;
+    int n_host, m_cap;
+    const void* table;      // float32 layer-1 table
+    const float* bias1;
+    int N1, ld1;
+    void* out1;
+    float out1_inv_scale;
+    int n_layers;
+    GemmLaunch layers[12];
+    HeadArgs head;
+    int* sync;
+    int rb_cap;
+    int spin_limit;
+    int grid;
+};
+
 bool launch_gather(const GatherLaunch& L, hipStream_t s);
+bool launch_fused(const FusedLaunch& L, hipStream_t s);
+int fused_max_layers();
+bool fused_enabled();  // false: the fused kernel is switched off and launch_fused refuses
 bool launch_gemm(const GemmLaunch& L, hipStream_t s);
 bool launch_head(const HeadArgs& H, int prec, int m_cap, hipStream_t s);
 void launch_absmax(const float* x, int n, int N, int ld, unsigned* out, hipStream_t s);

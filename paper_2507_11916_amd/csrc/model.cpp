@@ -104,6 +104,7 @@ static hb_status dev_upload(hb_model* m, const void* host, size_t bytes, void** 
 
 int choose_tile(const hb_model* m, int64_t M, int N_pad) {
     if (m->tile > 0) {
+        if (fused_tile(m->tile - 1)) return m->tile - 1;
         int bm, bn;
         gemm_tile_shape(m->tile - 1, &bm, &bn);
         if (N_pad % bn == 0) return m->tile - 1;
@@ -112,6 +113,7 @@ int choose_tile(const hb_model* m, int64_t M, int N_pad) {
     while ((1LL << (bucket + 1)) <= M) bucket++;
     auto it = m->tuned.find(bucket);
     if (it != m->tuned.end()) {
+        if (fused_tile(it->second)) return it->second;
         int bm, bn;
         gemm_tile_shape(it->second, &bm, &bn);
         if (N_pad % bn == 0) return it->second;
@@ -172,6 +174,7 @@ hb_status model_load_members(const std::vector<std::string>& paths, int rule, co
 
     auto m = std::make_unique<hb_model>();
     m->device = o.device;
+    HB_HIP(hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, o.device));
     m->opts = o;
     if (m->opts.max_batch <= 0) m->opts.max_batch = 16384;
     m->spec = spec;
@@ -326,6 +329,7 @@ void model_free(hb_model* m) {
         (void)hipFree(kv.second.x);
         (void)hipFree(kv.second.t);
         (void)hipFree(kv.second.absmax);
+        (void)hipFree(kv.second.sync);
     }
     for (void* p : m->allocs) (void)hipFree(p);
     delete m;
@@ -339,12 +343,18 @@ static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
     const int eb = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
     w.rows_cap = (int)round_up(m->opts.max_batch, 256);
     const size_t bytes = (size_t)w.rows_cap * m->width_cap * eb;
+    w.rb_cap = w.rows_cap / 32;
+    const size_t sync_bytes = (4 + (size_t)(fused_max_layers() + 1) * w.rb_cap) * sizeof(int);
     if (hipMalloc(&w.x, bytes) != hipSuccess || hipMalloc(&w.t, bytes) != hipSuccess ||
-        hipMalloc((void**)&w.absmax, 64 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&w.absmax, 64 * sizeof(unsigned)) != hipSuccess ||
+        hipMalloc((void**)&w.sync, sync_bytes) != hipSuccess) {
         (void)hipFree(w.x);
         (void)hipFree(w.t);
+        (void)hipFree(w.absmax);
         return fail(HB_E_NOMEM, "workspace allocation of 2 x %zu bytes failed", bytes);
     }
+    // the fused kernel's counters start at zero; each launch leaves them zero
+    HB_HIP(hipMemset(w.sync, 0, sync_bytes));
     auto r = m->ws.emplace(s, w);
     *out = &r.first->second;
     return HB_OK;
@@ -407,6 +417,94 @@ hb_status model_profile_read(hb_model* m, hb_profile* out) {
     return HB_OK;
 }
 
+// Fused persistent forward (tile ids 10..13): waves per compute unit.
+bool fused_tile(int id) { return id >= 10 && id <= 13; }
+int fused_waves_per_cu(int id) {
+    static const int W[4] = {2, 4, 8, 12};
+    return W[id - 10];
+}
+
+// The whole forward pass of one chunk as one launch of fused_forward_kernel;
+// buffers and arithmetic as in eval_chunk's kernel-per-layer path.
+static hb_status eval_fused(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
+                            int32_t* d_h, float* d_raw, hipStream_t s, int waves_per_cu, bool timed) {
+    const int prec = (int)m->opts.prec;
+    FusedLaunch F{};
+    F.domain = m->spec.domain;
+    F.prec = prec;
+    F.packed = d_packed;
+    F.n_dev = d_n;
+    F.n_host = n;
+    F.m_cap = m_cap;
+    F.table = m->l1_table;
+    F.bias1 = m->l1_bias;
+    F.N1 = m->members * m->N1_pad;
+    F.ld1 = m->width_cap;
+    void* X = w->x;
+    void* Tb = w->t;
+    F.out1 = X;
+    F.out1_inv_scale = 1.f / m->act_scale[0];
+    F.n_layers = (int)m->layers.size();
+    const int n_dense = (int)m->spec.dims.size();
+    for (int i = 0; i < F.n_layers; i++) {
+        const MatLayer& L = m->layers[i];
+        const bool res_first = !L.res_in_place && L.out_act >= n_dense;
+        GemmLaunch& g = F.layers[i];
+        g = GemmLaunch{};
+        g.prec = prec;
+        g.tile = 4;
+        g.Bt = L.Wt;
+        if (L.res_in_place) { g.A = Tb; g.R = X; g.C = X; }
+        else { g.A = X; g.R = nullptr; g.C = Tb; }
+        g.bias = L.bias;
+        g.colscale = L.colscale;
+        g.m_dev = d_n;
+        g.m_host = n;
+        g.m_cap = m_cap;
+        g.N = L.N_pad * L.groups;
+        g.K = L.K_pad;
+        if (L.groups > 1) { g.group_n = L.N_pad; g.group_k = L.K_pad; }
+        g.lda = m->width_cap;
+        g.ldb = L.K_pad;
+        g.ldc = m->width_cap;
+        g.a_scale = m->act_scale[L.in_act];
+        g.r_scale = L.res_act >= 0 ? m->act_scale[L.res_act] : 1.f;
+        g.out_inv_scale = 1.f / m->act_scale[L.out_act];
+        g.relu = 1;
+        if (!L.res_in_place && !res_first) std::swap(X, Tb);
+    }
+    HeadArgs& H = F.head;
+    H.X = X;
+    H.ldx = m->width_cap;
+    H.K = m->K_last_pad;
+    H.W = m->head_W;
+    H.b = m->head_b;
+    H.n_out = m->spec.n_out;
+    H.x_scale = m->act_scale[m->n_act - 1];
+    H.n_dev = d_n;
+    H.n_host = n;
+    H.packed = d_packed;
+    H.domain = m->spec.domain;
+    H.mode = (int)m->opts.out;
+    H.q = m->opts.q;
+    H.offset = m->opts.offset;
+    H.combine_md = m->opts.combine_md;
+    H.members = m->members;
+    H.ens_rule = m->ens_rule;
+    H.h_out = d_h;
+    H.raw = d_raw;
+    F.sync = w->sync;
+    F.rb_cap = w->rb_cap;
+    F.spin_limit = 1 << 18;  // polls of about 1 us: a wait gives up after about 0.3 s
+    F.grid = std::max(1, m->cus) * waves_per_cu;
+    if ((m_cap + 31) / 32 > w->rb_cap) return fail(HB_E_INVAL, "batch exceeds the fused kernel's counters");
+    const int pi = timed ? prof_begin(m, 1, s) : -1;
+    if (!launch_fused(F, s)) return fail(HB_E_UNSUPPORTED, "no fused forward kernel for this network");
+    HB_HIP(hipGetLastError());
+    prof_end(m, pi, m->flops * (d_n ? m_cap : n), s);
+    return HB_OK;
+}
+
 // Forward pass over one chunk of at most max_batch states.
 static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, int n, const int32_t* d_n, int m_cap,
                             int32_t* d_h, float* d_raw, hipStream_t s, CalibCapture* cap, int force_tile,
@@ -424,6 +522,10 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
     void* X = w->x;
     void* Tb = w->t;
     if (cap) HB_HIP(hipMemsetAsync(w->absmax, 0, 64 * sizeof(unsigned), s));
+    const int t0 = force_tile >= 0 ? force_tile : choose_tile(m, m_cap, 128);
+    if (fused_tile(t0) && fused_enabled() && !cap && !ac && w->sync && !m->layers.empty() &&
+        (int)m->layers.size() <= fused_max_layers() && m->spec.n_out <= 32)
+        return eval_fused(m, w, d_packed, n, d_n, m_cap, d_h, d_raw, s, fused_waves_per_cu(t0), timed);
     GatherLaunch G{};
     G.domain = m->spec.domain;
     G.prec = prec;
@@ -455,6 +557,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         GemmLaunch g{};
         g.prec = prec;
         g.tile = force_tile >= 0 ? force_tile : choose_tile(m, m_cap, L.N_pad);
+        if (fused_tile(g.tile)) g.tile = 4;  // same arithmetic, one launch per layer
         g.Bt = L.Wt;
         if (L.res_in_place) { g.A = Tb; g.R = X; g.C = X; }
         else { g.A = X; g.R = nullptr; g.C = Tb; }
@@ -664,6 +767,7 @@ static hb_status time_tiles(hb_model* m, const uint8_t* d_packed, int64_t n, Tun
     // tiles are not decided by the order they were timed in.
     for (int round = 0; round < 2; round++) {
         for (int id = 0; id < count; id++) {
+            if (fused_tile(id) && !fused_enabled()) continue;
             int bm, bn;
             gemm_tile_shape(id, &bm, &bn);
             bool ok = true;
@@ -802,7 +906,7 @@ hb_status model_load_tuning(hb_model* m, const char* path) {
     for (size_t i = 3; i < lines.size(); i++) {
         int b = -1, id = -1;
         if (sscanf(lines[i].c_str(), "bucket %d tile %d", &b, &id) != 2 || b < 0 || b > 40 || id < 0 ||
-            id >= gemm_tile_count())
+            id >= gemm_tile_count() || (fused_tile(id) && !fused_enabled()))
             return fail(HB_E_INVAL, "%s: bad line %zu", path, i + 1);
         tuned[b] = id;
     }

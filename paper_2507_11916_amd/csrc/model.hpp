@@ -34,6 +34,8 @@ struct Workspace {
     void* t = nullptr;
     int rows_cap = 0;
     unsigned* absmax = nullptr;  // calibration scratch (n_act entries)
+    int* sync = nullptr;         // counters of the fused forward kernel (zero between launches), or null
+    int rb_cap = 0;              // 32-row blocks the counters cover
 };
 
 struct ActCopy {  // copy of one stored activation tensor (hb_model_activation)
@@ -69,6 +71,7 @@ struct hb_model {
     std::vector<float> act_scale;
     bool calibrated = false;
     int tile = 0;                       // 0 automatic, else tile id + 1
+    int cus = 0;                        // compute units of the device (fused-kernel grid)
     std::map<int, int> tuned;           // batch bucket (log2) -> tile id
     int64_t weight_bytes = 0;
     double flops = 0;
@@ -103,6 +106,8 @@ hb_status model_autotune(hb_model* m, const uint8_t* d_packed, int64_t n, hb_tun
 hb_status model_save_tuning(const hb_model* m, const char* path);
 hb_status model_load_tuning(hb_model* m, const char* path);
 int choose_tile(const hb_model* m, int64_t M, int N_pad);
+bool fused_tile(int id);           // tile ids 10..13: the fused persistent forward kernel
+int fused_waves_per_cu(int id);
 hb_status model_profile(hb_model* m, bool enable);
 hb_status model_profile_read(hb_model* m, hb_profile* out);
 

@@ -339,3 +339,17 @@ def test_ragged_width_parity(tmp_path, prec):
     y_ref = net.forward(st, mode=int(prec))
     y_exact = net.forward(st) if prec != hb.HB_FP32 else y_ref
     _flip_envelope(y, y_ref, y_exact, tf["e_head"], tf["flip_rows"], TOL[prec])
+
+
+def test_switched_off_fused_tiles_are_refused(net_files):
+    """Tile ids 11-14 (the fused persistent forward kernel) are refused while
+    that kernel is switched off; the autotuner never picks them."""
+    m = hb.Model(net_files["stp4_res"], prec=hb.HB_BF16, max_batch=1024)
+    for t in (11, 12, 13, 14):
+        with pytest.raises(hb.HBError) as e:
+            m.set_tile(t)
+        assert e.value.status == hb.HB_E_UNSUPPORTED
+    st = synth.stp_walks(4, synth.throughput_seeds(300, 5), lengths=200)
+    report = m.tune(_dev(hb.hb_encode(1, st)))
+    assert report and all(1 <= t <= 10 for t, _ in report)
+    m.close()
