@@ -35,19 +35,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# FP32 kernel of each tile id (hb_model_set_tile numbering)
-TILE_KERNELS = {1: "gemm_kernel<0, 0, 128, 128>", 2: "gemm_kernel<0, 0, 128, 256>", 3: "gemm_kernel<0, 0, 64, 128>",
-                4: "gemm_kernel<0, 0, 256, 128>", 5: "gemm_small_kernel<0, 0>",
-                6: "gemm_ring_kernel<0, 0, 256, 128, 3>", 7: "gemm_ring_kernel<0, 0, 128, 128, 3>",
-                8: "gemm_ring_kernel<0, 0, 128, 256, 3>", 9: "gemm_ring_kernel<0, 0, 64, 128, 4>",
-                10: "gemm_w8_kernel<0, 0>"}
+# GEMM kernel of each tile id (hb_model_set_tile numbering); {p}: precision template argument
+TILE_KERNELS = {1: "gemm_kernel<{p}, {p}, 128, 128>", 2: "gemm_kernel<{p}, {p}, 128, 256>",
+                3: "gemm_kernel<{p}, {p}, 64, 128>", 4: "gemm_kernel<{p}, {p}, 256, 128>",
+                5: "gemm_small_kernel<{p}, {p}>", 6: "gemm_ring_kernel<{p}, {p}, 256, 128, 3>",
+                7: "gemm_ring_kernel<{p}, {p}, 128, 128, 3>", 8: "gemm_ring_kernel<{p}, {p}, 128, 256, 3>",
+                9: "gemm_ring_kernel<{p}, {p}, 64, 128, 4>", 10: "gemm_w8_kernel<{p}, {p}>"}
+PREC_ARG = {"f32": 0, "bf16": 1, "fp8": 2}
 
 
-def measured_traffic(kernel):
+def tile_kernel(tile, prec):
+    k = TILE_KERNELS.get(tile)
+    return k.format(p=PREC_ARG[prec]) if k else None
+
+
+def measured_traffic(kernel, prec="f32"):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None
     when the summary has no row for it or the kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gemm_f32_stp4res_b8000_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", f"gemm_{prec}_stp4res_b8000_hbm_bytes.md")
     try:
         fields = dict(l.strip().split(": ", 1) for l in open(path) if l.startswith("    ") and ": " in l)
         src = os.path.join(ROOT, "paper_2507_11916_amd", "csrc", "kernels.hip")
@@ -232,7 +238,7 @@ def main():
     if args.profile_only:
         if args.all_tiles:
             m = models[args.prec]
-            for t in sorted(TILE_KERNELS):
+            for t in sorted(TILE_KERNELS):  # every GEMM tile at the benchmark shape
                 m.set_tile(t)
                 us = timed_loop(m, max(3, args.steps // 5), 1) * 1e3
                 log(f"[bench] {args.prec} tile {t}: {us:.1f} us/step")
@@ -461,8 +467,13 @@ def main():
 
     f32 = results["f32"]
     ach = f32["gemm_tflops"]
-    f32_kernel = TILE_KERNELS.get(f32["tile"])
-    traffic = measured_traffic(f32_kernel)
+    f32_kernel = tile_kernel(f32["tile"], "f32")
+    traffic = measured_traffic(f32_kernel, "f32")
+    for name, r in results.items():  # each precision's GEMM: kernel, HBM bytes per launch (counters), roofline
+        k = tile_kernel(r["tile"], name)
+        r["gemm_kernel"] = k
+        r["gemm_traffic"] = measured_traffic(k, name)
+        r["gemm_frac"] = r["gemm_tflops"] / PEAK_TFLOPS[name]
     line = {
         "metric": "heuristic evals/s + search nodes/s per GPU (FP32 vs BF16/FP8) at matched h",
         "value": f32["evals_per_s"],
