@@ -301,14 +301,18 @@ hb_status hb_model_profile(hb_model* m, int enable); /* enabling also resets the
 hb_status hb_model_profile_read(hb_model* m, hb_profile* out);
 
 /* ------------------------------------------------------------ training */
-/* On-GPU training of a sliding-tile regression network (the learned
- * heuristic; design objective of the appendix: large mean h with h_M <= h*).
+/* On-GPU training of a regression network (the learned heuristic; design
+ * objective of the appendix: large mean h with h_M <= h*), for the sliding-tile
+ * domains and the cube.
  * Loss over a batch of n labelled states:
  *   L = (1/n) sum_b w_b (y_b - t_b)^2,  w_b = alpha if asym and y_b > t_b else 1.
  * Gradients by the chain rule on the GPU (weight gradients in FP32; the
  * layer-1 gradient is the scatter-add of the pre-activation gradient rows that
- * the one-hot input selects); Adam (Kingma & Ba) on FP32 master weights, after
- * which the working copies (BF16 or FP32) are re-cast.  ReLU'(z) = [z > 0]. */
+ * the one-hot input selects; the cube's six centre rows, always active, get the
+ * bias gradient); Adam (Kingma & Ba) on FP32 master weights, after which the
+ * working copies (BF16 or FP32) are re-cast.  ReLU'(z) = [z > 0].  Every
+ * reduction over the batch runs in a fixed order (no float atomics), so a
+ * step's gradients are bitwise repeatable. */
 typedef struct {
     hb_precision prec;   /* HB_BF16 (BF16 operands, FP32 master) or HB_FP32 */
     int device;
@@ -319,8 +323,8 @@ typedef struct {
 } hb_train_opts;
 
 typedef struct hb_trainer hb_trainer;
-/* opts NULL = defaults.  The weight file must be a regression network of a
- * sliding-tile domain whose hidden widths are at most 1024. */
+/* opts NULL = defaults.  The weight file must be a regression network whose
+ * hidden widths are at most 1024. */
 hb_status hb_trainer_create(const char* weights_path, const hb_train_opts* opts, hb_trainer** out);
 void hb_trainer_free(hb_trainer* t); /* NULL-safe */
 int64_t hb_trainer_n_params(const hb_trainer* t);

@@ -1,11 +1,12 @@
 // HIP kernels of on-GPU training of the heuristic network (regression head,
-// sliding-tile inputs): loss and output-layer gradient, transposes with fused
+// sliding-tile or cube inputs): loss and output-layer gradient, transposes with fused
 // bias-gradient column sums, the layer-1 scatter-add (transpose of the
 // gather-sum), Adam with re-cast of the working weights, and a fill kernel.
 // The matrix products (forward, input gradients, weight gradients) run on the
 // MFMA GEMM of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "train.hpp"
@@ -37,8 +38,9 @@ __global__ void fill_kernel(float* p, int64_t n, float v) {
 // One wave per row, 8 rows per wave, 4 waves per block.  y = w.x + b;
 // loss += w_b (y - t)^2 / n; dy = 2 w_b (y - t) / n; delta_k = dy * w_k where
 // x_k > 0 (gradient at the pre-activation of the last hidden layer).  Rows >= n
-// get delta = 0.  dWo and dbo are reduced over the block's rows in LDS and then
-// added atomically.
+// get delta = 0.  dWo, dbo and the loss are reduced over the block's rows in
+// LDS; each block writes its partial sums, which column_sum_kernel adds in
+// block order.
 constexpr int kHeadRowsPerWave = 8;
 constexpr int kHeadMaxGroups = 4;  // K <= 1024
 
@@ -88,19 +90,50 @@ __global__ __launch_bounds__(256) void head_train_kernel(HeadTrainArgs a) {
         for (int e = 0; e < 4; e++) s_w[wave][gi * 256 + lane * 4 + e] = accw[gi][e];
     if (lane == 0) { s_b[wave] = accb; s_l[wave] = accl; }
     __syncthreads();
-    for (int k = threadIdx.x; k < a.K; k += 256) {
-        const float v = s_w[0][k] + s_w[1][k] + s_w[2][k] + s_w[3][k];
-        if (v != 0.f) atomicAdd(&a.dWo[k], v);
-    }
+    // the block's partial sums (output weights, bias, loss) into its row of
+    // `part`; column_sum_kernel adds the rows in block order
+    float* part = a.part + (size_t)blockIdx.x * (a.K + 2);
+    for (int k = threadIdx.x; k < a.K; k += 256) part[k] = s_w[0][k] + s_w[1][k] + s_w[2][k] + s_w[3][k];
     if (threadIdx.x == 0) {
-        atomicAdd(a.dbo, s_b[0] + s_b[1] + s_b[2] + s_b[3]);
-        atomicAdd(a.loss, s_l[0] + s_l[1] + s_l[2] + s_l[3]);
+        part[a.K] = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+        part[a.K + 1] = s_l[0] + s_l[1] + s_l[2] + s_l[3];
+    }
+}
+
+// out[c] = sum over r < rows of part[r * ld + c], in row order (the fixed-order
+// second pass of every reduction over blocks: no float atomics, so results are
+// bitwise repeatable).
+// A block takes 64 columns; its 16 row groups each sum a contiguous quarter..
+// sixteenth of the rows in order (loads issued 8 ahead), then the group sums
+// are added in group order.
+__global__ __launch_bounds__(1024) void column_sum_kernel(const float* part, int rows, int cols, int ld, float* out) {
+    __shared__ float gs[16][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + tx;
+    const int per = (rows + 15) / 16, r0 = ty * per, r1 = min(rows, r0 + per);
+    float s = 0.f;
+    if (c < cols) {
+        int r = r0;
+        for (; r + 8 <= r1; r += 8) {
+            float v[8];
+            _Pragma("unroll") for (int u = 0; u < 8; u++) v[u] = part[(size_t)(r + u) * ld + c];
+            _Pragma("unroll") for (int u = 0; u < 8; u++) s += v[u];
+        }
+        for (; r < r1; r++) s += part[(size_t)r * ld + c];
+    }
+    gs[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && c < cols) {
+        float t = 0.f;
+        for (int g = 0; g < 16; g++) t += gs[g][tx];
+        out[c] = t;
     }
 }
 
 // ------------------------------------------------------------- transpose
 // out[c][r] = in[r][c] for r < R, c < C through a 64 x 64 LDS tile; with
-// colsum, every column's sum over rows < rows_sum is added atomically.
+// colpart, the block's column sums over rows < rows_sum go to row blockIdx.y
+// of colpart (row stride C), for column_sum_kernel.
 template <int T>
 __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
     __shared__ float tile[64][65];
@@ -115,62 +148,238 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
         const int c = c0 + i, r = r0 + tx;
         if (c < a.C && r < a.R) st_t<T>(a.out, (size_t)c * a.ld_out + r, tile[tx][i]);
     }
-    if (a.colsum && ty == 0) {
+    if (a.colpart && ty == 0) {
         float s = 0.f;
         for (int i = 0; i < 64; i++)
             if (r0 + i < a.rows_sum) s += tile[i][tx];
-        if (c0 + tx < a.C && s != 0.f) atomicAdd(&a.colsum[c0 + tx], s);
+        if (c0 + tx < a.C) a.colpart[(size_t)blockIdx.y * a.C + c0 + tx] = s;
     }
 }
 
 // ------------------------------------------------------------ layer 1
-// dW1[p*S + s_p][c] += dz[b][c] and db1[c] += dz[b][c] over the states.  A
-// block of 64 threads owns 64 columns (one each) and a run of states; the
-// per-row partial sums live in LDS (no two threads share a column), then every
-// non-zero partial is added atomically.
-template <int T, int SIDE>
-__global__ __launch_bounds__(64) void scatter_l1_kernel(ScatterArgs a) {
-    constexpr int P = SIDE * SIDE, S = SIDE * SIDE, ROWS = P * S;
-    __shared__ float acc[ROWS][64];
-    const int c = blockIdx.x * 64 + threadIdx.x;
-    for (int r = 0; r < ROWS; r++) acc[r][threadIdx.x] = 0.f;
-    float bsum = 0.f;
-    const int b0 = blockIdx.y * a.states_per_block;
-    const int b1 = min(b0 + a.states_per_block, a.n);
-    for (int b = b0; b < b1; b++) {
-        const uint64_t w = reinterpret_cast<const uint64_t*>(a.packed)[b];
-        const float v = ld_t<T>(a.dz, (size_t)b * a.ld + c);
-        if (v == 0.f) continue;
-        bsum += v;
-        for (int p = 0; p < P; p++) {
-            const int s = min((int)((w >> (4 * p)) & 15), S - 1);
-            acc[p * S + s][threadIdx.x] += v;
+// dW1[row][c] = sum over states b whose one-hot input has `row` of dz[b][c]
+// (the transpose of the gather-sum), db1[c] = sum_b dz[b][c].
+// Pass 1 (scatter_partial_kernel): a block of NW waves (4; 8 for the cube's
+// 48 cells) owns 64 columns and one chunk of states; its LDS holds every table
+// row's 64 partial sums.  Wave w owns the cells p = w, w + NW, ... (so the rows
+// p*S .. p*S + S - 1), and wave 0 also the bias row: no two waves touch one LDS word, and each wave adds
+// its states in order, so every partial is a fixed sequence of additions.
+// Per state a wave reads all of its cells' rows (distinct rows), then adds
+// and writes them back: one LDS round trip per state instead of one per cell.
+// (LDS float atomics measured several times slower than these plain
+// read-modify-writes.)  Pass 2 (scatter_reduce_kernel) sums the chunks'
+// partials in chunk order into the gradient rows.  No global atomics: the
+// gradient is bitwise repeatable.
+template <int DOM>
+struct TrCells {
+    static constexpr int P = DOM == 0 ? 9 : DOM == 1 ? 16 : 48;  // gathered cells
+    static constexpr int S = DOM == 0 ? 9 : DOM == 1 ? 16 : 6;
+    static constexpr int W = DOM == 2 ? 3 : 1;                   // 64-bit words per packed state
+    static constexpr int NW = DOM == 2 ? 8 : 4;                  // waves of a scatter block
+    // symbol of cell p of a packed state given as its words (by value, so the
+    // words stay in registers; the word is selected, p varies per wave)
+    __device__ static int sym(uint64_t w0, uint64_t w1, uint64_t w2, int p) {
+        if (DOM != 2) return min((int)((w0 >> (4 * p)) & 15), S - 1);
+        const uint64_t word = (p >> 4) == 0 ? w0 : (p >> 4) == 1 ? w1 : w2;
+        return min((int)((word >> (3 * (p & 15))) & 7), S - 1);
+    }
+};
+
+int scatter_table_rows(int domain) { return domain == 0 ? 81 : domain == 1 ? 256 : 288; }
+
+// The gradient values of one batch of states for this lane, kept as loaded
+// (raw bits) so that all of the batch's loads are in flight at once; they are
+// converted when added.  The states' packed records are read from LDS.
+template <int T, int DOM, int U>
+struct ScatterBatch {
+    uint32_t v[U];
+    // States past b1 load row b1 - 1 (in bounds; add() skips them), so the
+    // loads are unconditional; the scheduling barrier keeps them ahead of the
+    // previous batch's additions.
+    __device__ __forceinline__ void load(const ScatterArgs& a, int b, int b1, int c) {
+        _Pragma("unroll") for (int u = 0; u < U; u++) {
+            const size_t i = (size_t)min(b + u, b1 - 1) * a.ld + c;
+            v[u] = T == 0 ? reinterpret_cast<const uint32_t*>(a.dz)[i]
+                          : (uint32_t)reinterpret_cast<const uint16_t*>(a.dz)[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // add the batch's states, in order, into this wave's rows; recs holds the
+    // records of the states from rb on
+    __device__ __forceinline__ void add(float* acc, const uint64_t* recs, int rb, int b, int b1, int wave,
+                                        int lane) const {
+        using D = TrCells<DOM>;
+        constexpr int ROWS = D::P * D::S;
+        constexpr int CW = (D::P + D::NW - 1) / D::NW;  // cells per wave (the last waves may own one fewer)
+        // the batch's records first (one LDS round trip), then one round trip per state
+        uint64_t wr[U][D::W];
+        _Pragma("unroll") for (int u = 0; u < U; u++)
+            _Pragma("unroll") for (int i = 0; i < D::W; i++)
+                wr[u][i] = recs[(size_t)(min(b + u, b1 - 1) - rb) * D::W + i];
+        _Pragma("unroll") for (int u = 0; u < U; u++) {
+            if (b + u < b1) {
+                const uint64_t w0 = wr[u][0], w1 = wr[u][D::W > 1 ? 1 : 0], w2 = wr[u][D::W > 2 ? 2 : 0];
+                int row[CW + 1];
+                float cur[CW + 1];
+                _Pragma("unroll") for (int j = 0; j < CW; j++) {
+                    const int p = wave + D::NW * j;
+                    row[j] = p < D::P ? (p * D::S + D::sym(w0, w1, w2, p)) * 64 + lane : -1;
+                }
+                row[CW] = wave == 0 ? ROWS * 64 + lane : -1;  // the bias row
+                const float x = __uint_as_float(T == 0 ? v[u] : v[u] << 16);
+                _Pragma("unroll") for (int j = 0; j <= CW; j++) cur[j] = row[j] >= 0 ? acc[row[j]] : 0.f;
+                _Pragma("unroll") for (int j = 0; j <= CW; j++)
+                    if (row[j] >= 0) acc[row[j]] = cur[j] + x;
+            }
         }
     }
-    for (int r = 0; r < ROWS; r++) {
-        const float v = acc[r][threadIdx.x];
-        if (v != 0.f) atomicAdd(&a.dW1[(size_t)r * a.ld_w + c], v);
+};
+
+constexpr int kScatterStage = 256;  // states whose packed records are staged in LDS at a time
+
+template <int DOM>
+constexpr size_t scatter_lds_bytes() {
+    return (size_t)(TrCells<DOM>::P * TrCells<DOM>::S + 1) * 64 * sizeof(float) +
+           (size_t)kScatterStage * TrCells<DOM>::W * sizeof(uint64_t);
+}
+
+template <int T, int DOM>
+__global__ __launch_bounds__(512) void scatter_partial_kernel(ScatterArgs a) {
+    using D = TrCells<DOM>;
+    constexpr int ROWS = D::P * D::S;
+    constexpr int U = D::W == 1 ? 32 : 16;  // states per batch; the next batch loads while one is added
+    extern __shared__ float acc[];          // [(ROWS + 1) * 64], then the staged records
+    uint64_t* recs = reinterpret_cast<uint64_t*>(acc + (ROWS + 1) * 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    for (int i = threadIdx.x; i < (ROWS + 1) * 64; i += 64 * D::NW) acc[i] = 0.f;
+    const uint64_t* packed = reinterpret_cast<const uint64_t*>(a.packed);
+    const int b0 = blockIdx.y * a.chunk, b1 = min(b0 + a.chunk, a.n);
+    for (int sb = b0; sb < b1; sb += kScatterStage) {
+        const int sb1 = min(sb + kScatterStage, b1);
+        for (int i = threadIdx.x; i < (sb1 - sb) * D::W; i += 64 * D::NW) recs[i] = packed[(size_t)sb * D::W + i];
+        __syncthreads();
+        ScatterBatch<T, DOM, U> x, y;
+        x.load(a, sb, sb1, c);
+        for (int b = sb; b < sb1; b += 2 * U) {
+            y.load(a, b + U, sb1, c);
+            x.add(acc, recs, sb, b, sb1, wave, lane);
+            x.load(a, b + 2 * U, sb1, c);
+            y.add(acc, recs, sb, b + U, sb1, wave, lane);
+        }
+        __syncthreads();
     }
-    if (bsum != 0.f) atomicAdd(&a.db1[c], bsum);
+    float* out = a.partial + (size_t)blockIdx.y * (ROWS + 1) * a.N1 + c;
+    for (int r = wave; r <= ROWS; r += D::NW) out[(size_t)r * a.N1] = acc[r * 64 + lane];
+}
+
+// Table row -> gradient row (the weight file's order).  Cube: non-centre
+// sticker q of the table is sticker q + q/8 + (q%8 >= 4) of the file.
+template <int DOM>
+__device__ __forceinline__ int grad_row(int r) {
+    if (DOM != 2) return r;
+    const int q = r / 6, col = r % 6;
+    return (q + q / 8 + (q % 8 >= 4 ? 1 : 0)) * 6 + col;
+}
+
+// A block takes 64 columns of one row; its 16 groups of 64 threads each add
+// an equal run of chunks in order, then the group sums are added in group
+// order (a fixed summation order).
+template <int DOM>
+__global__ __launch_bounds__(1024) void scatter_reduce_kernel(ScatterArgs a, int chunks) {
+    using D = TrCells<DOM>;
+    constexpr int ROWS = D::P * D::S;
+    __shared__ float gs[16][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int per = (chunks + 15) / 16, k0 = ty * per, k1 = min(chunks, k0 + per);
+    const int cblocks = a.N1 / 64;
+    for (int blk = blockIdx.x; blk < (ROWS + 1) * cblocks; blk += gridDim.x) {
+        const int r = blk / cblocks, c = (blk % cblocks) * 64 + tx;
+        float part = 0.f;
+        for (int k = k0; k < k1; k++) part += a.partial[((size_t)k * (ROWS + 1) + r) * a.N1 + c];
+        gs[ty][tx] = part;
+        __syncthreads();
+        float s = 0.f;
+        if (ty == 0)
+            for (int g = 0; g < 16; g++) s += gs[g][tx];
+        __syncthreads();
+        if (ty != 0) continue;
+        if (r < ROWS) {
+            a.dW1[(size_t)grad_row<DOM>(r) * a.ld_w + c] = s;
+        } else {
+            a.db1[c] = s;
+            if (DOM == 2)  // centre f always shows colour f: its row's gradient is the bias gradient
+                for (int f = 0; f < 6; f++)
+                    for (int col = 0; col < 6; col++) a.dW1[(size_t)((9 * f + 4) * 6 + col) * a.ld_w + c] = col == f ? s : 0.f;
+        }
+    }
+}
+
+// Cube: working table and folded bias from the master weights, in the order
+// the inference model folds them (bias, then the centres of faces 0..5).
+template <int T>
+__global__ void cube_fold_kernel(const float* master, const float* bias, int N1, int N1_pad, void* table, float* bias_work) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N1_pad; j += gridDim.x * blockDim.x) {
+        for (int r = 0; r < 288; r++) {
+            const float w = j < N1 ? master[(size_t)grad_row<2>(r) * N1 + j] : 0.f;
+            st_t<T>(table, (size_t)r * N1_pad + j, w);
+        }
+        float b = j < N1 ? bias[j] : 0.f;
+        for (int f = 0; f < 6; f++) {
+            const float w = j < N1 ? master[(size_t)((9 * f + 4) * 6 + f) * N1 + j] : 0.f;
+            b += T == 0 ? w : tr_bf16_to_f32(tr_f32_to_bf16(w));
+        }
+        bias_work[j] = b;
+    }
 }
 
 // ------------------------------------------------------------------ Adam
 // master[k][n] (float32, K x N) updated from grad[k*gk + n*gn]; the working
 // copies out1 (type T) at k*s1k + n*s1n and out2 at k*s2k + n*s2n are rewritten.
+// One grid row per tensor, so every tensor's step is one launch.
+// Blocks take 64 x 64 tiles (k, n) of one tensor: the master, moments and
+// gradient are read and written along n, and a working copy that is stored
+// transposed (element stride along n > 1, as the forward operand W^T) is
+// written from an LDS tile along k, so every global access is coalesced.
 template <int T>
-__global__ void adam_kernel(AdamArgs a) {
-    const int64_t total = (int64_t)a.K * a.N;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(i / a.N), n = (int)(i % a.N);
-        const float g = a.grad[(size_t)k * a.gk + (size_t)n * a.gn];
-        const float m = a.b1 * a.m[i] + (1.f - a.b1) * g;
-        const float v = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
-        a.m[i] = m;
-        a.v[i] = v;
-        const float w = a.master[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
-        a.master[i] = w;
-        if (a.out1) st_t<T>(a.out1, (size_t)k * a.s1k + (size_t)n * a.s1n, w);
-        if (a.out2) st_t<T>(a.out2, (size_t)k * a.s2k + (size_t)n * a.s2n, w);
+__global__ __launch_bounds__(256) void multi_adam_kernel(const AdamTensor* ts, float lr, float b1, float b2, float eps,
+                                                        float c1, float c2) {
+    __shared__ float tile[64][65];
+    const AdamTensor d = ts[blockIdx.y];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tk = (d.K + 63) / 64, tn = (d.N + 63) / 64;
+    for (int t = blockIdx.x; t < tk * tn; t += gridDim.x) {
+        const int k0 = (t / tn) * 64, n0 = (t % tn) * 64;
+        const int n = n0 + tx;
+        for (int kk = ty; kk < 64; kk += 4) {
+            const int k = k0 + kk;
+            float w = 0.f;
+            if (k < d.K && n < d.N) {
+                const size_t i = (size_t)k * d.N + n;
+                const float g = d.grad[(size_t)k * d.gk + (size_t)n * d.gn];
+                const float m = b1 * d.m[i] + (1.f - b1) * g;
+                const float v = b2 * d.v[i] + (1.f - b2) * g * g;
+                d.m[i] = m;
+                d.v[i] = v;
+                w = d.master[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+                d.master[i] = w;
+                if (d.out1 && d.s1n == 1) st_t<T>(d.out1, (size_t)k * d.s1k + n, w);
+                if (d.out2 && d.s2n == 1) st_t<T>(d.out2, (size_t)k * d.s2k + n, w);
+            }
+            tile[kk][tx] = w;
+        }
+        const bool t1 = d.out1 && d.s1n != 1, t2 = d.out2 && d.s2n != 1;
+        if (t1 || t2) {
+            __syncthreads();
+            for (int nn = ty; nn < 64; nn += 4) {
+                const int k = k0 + tx, n2 = n0 + nn;
+                if (k < d.K && n2 < d.N) {
+                    if (t1) st_t<T>(d.out1, (size_t)k * d.s1k + (size_t)n2 * d.s1n, tile[tx][nn]);
+                    if (t2) st_t<T>(d.out2, (size_t)k * d.s2k + (size_t)n2 * d.s2n, tile[tx][nn]);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -182,11 +391,16 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
 }
 
+int head_train_blocks(int m_pad) { return (m_pad + 4 * kHeadRowsPerWave - 1) / (4 * kHeadRowsPerWave); }
+
 bool launch_head_train(const HeadTrainArgs& a, int t, hipStream_t s) {
     if (a.K % 4 || a.K > kHeadMaxGroups * 256) return false;
-    const int blocks = (a.m_pad + 4 * kHeadRowsPerWave - 1) / (4 * kHeadRowsPerWave);
+    const int blocks = head_train_blocks(a.m_pad);
     if (t == 0) hipLaunchKernelGGL(head_train_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(head_train_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+    // output-weight gradient, bias gradient and loss: the blocks' partials in order
+    launch_column_sum(a.part, blocks, a.K, a.K + 2, a.dWo, s);
+    launch_column_sum(a.part + a.K, blocks, 2, a.K + 2, a.dbo_loss, s);
     return true;
 }
 
@@ -194,31 +408,65 @@ void launch_transpose(const TransposeArgs& a, int t, hipStream_t s) {
     dim3 grid((a.C + 63) / 64, (a.R + 63) / 64);
     if (t == 0) hipLaunchKernelGGL(transpose_kernel<0>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(transpose_kernel<1>, grid, dim3(256), 0, s, a);
+    if (a.colpart) launch_column_sum(a.colpart, (a.rows_sum + 63) / 64, a.C, a.C, a.colsum, s);
 }
 
-bool launch_scatter_l1(const ScatterArgs& a, int t, int side, hipStream_t s) {
-    if (a.N1 % 64) return false;
-    dim3 grid(a.N1 / 64, (a.n + a.states_per_block - 1) / a.states_per_block);
-    if (grid.y == 0) return true;
-    if (side == 3) {
-        if (t == 0) hipLaunchKernelGGL((scatter_l1_kernel<0, 3>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((scatter_l1_kernel<1, 3>), grid, dim3(64), 0, s, a);
-    } else if (side == 4) {
-        if (t == 0) hipLaunchKernelGGL((scatter_l1_kernel<0, 4>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((scatter_l1_kernel<1, 4>), grid, dim3(64), 0, s, a);
-    } else {
-        return false;
+void launch_column_sum(const float* part, int rows, int cols, int ld, float* out, hipStream_t s) {
+    const int blocks = (cols + 63) / 64;
+    hipLaunchKernelGGL(column_sum_kernel, dim3(blocks), dim3(1024), 0, s, part, rows, cols, ld, out);
+}
+
+template <int T, int DOM>
+static void launch_scatter_t(const ScatterArgs& a, int chunks, hipStream_t s) {
+    const size_t lds = scatter_lds_bytes<DOM>();
+    hipLaunchKernelGGL((scatter_partial_kernel<T, DOM>), dim3(a.N1 / 64, chunks), dim3(64 * TrCells<DOM>::NW), lds, s, a);
+    const int blocks = std::min(2048, (scatter_table_rows(DOM) + 1) * (a.N1 / 64));
+    hipLaunchKernelGGL((scatter_reduce_kernel<DOM>), dim3(blocks), dim3(1024), 0, s, a, chunks);
+}
+
+bool launch_scatter_l1(const ScatterArgs& a, int t, int domain, int chunks, hipStream_t s) {
+    if (a.N1 % 64 || chunks < 1 || domain < 0 || domain > 2 || t < 0 || t > 1) return false;
+    switch (domain * 2 + t) {
+        case 0: launch_scatter_t<0, 0>(a, chunks, s); break;
+        case 1: launch_scatter_t<1, 0>(a, chunks, s); break;
+        case 2: launch_scatter_t<0, 1>(a, chunks, s); break;
+        case 3: launch_scatter_t<1, 1>(a, chunks, s); break;
+        case 4: launch_scatter_t<0, 2>(a, chunks, s); break;
+        case 5: launch_scatter_t<1, 2>(a, chunks, s); break;
     }
     return true;
 }
 
-void launch_adam(const AdamArgs& a, int t, hipStream_t s) {
-    const int64_t total = (int64_t)a.K * a.N;
-    int blocks = (int)((total + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    if (t == 0) hipLaunchKernelGGL(adam_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(adam_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
+void launch_multi_adam(const AdamTensor* d_tensors, int count, float lr, float b1, float b2, float eps, float c1,
+                       float c2, int t, hipStream_t s) {
+    const dim3 grid(256, count);
+    if (t == 0) hipLaunchKernelGGL(multi_adam_kernel<0>, grid, dim3(256), 0, s, d_tensors, lr, b1, b2, eps, c1, c2);
+    else hipLaunchKernelGGL(multi_adam_kernel<1>, grid, dim3(256), 0, s, d_tensors, lr, b1, b2, eps, c1, c2);
 }
+
+template <int T, int DOM>
+static hipError_t set_scatter_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&scatter_partial_kernel<T, DOM>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds_bytes<DOM>());
+}
+
+// The layer-1 scatter holds up to 289 x 64 floats and 256 staged records of LDS per block.
+hipError_t train_prepare_attributes() {
+    hipError_t e = set_scatter_attr<0, 0>();
+    if (e == hipSuccess) e = set_scatter_attr<1, 0>();
+    if (e == hipSuccess) e = set_scatter_attr<0, 1>();
+    if (e == hipSuccess) e = set_scatter_attr<1, 1>();
+    if (e == hipSuccess) e = set_scatter_attr<0, 2>();
+    if (e == hipSuccess) e = set_scatter_attr<1, 2>();
+    return e;
+}
+
+void launch_cube_fold(const float* master, const float* bias, int N1, int N1_pad, void* table, float* bias_work, int t,
+                      hipStream_t s) {
+    const int blocks = (N1_pad + 255) / 256;
+    if (t == 0) hipLaunchKernelGGL(cube_fold_kernel<0>, dim3(blocks), dim3(256), 0, s, master, bias, N1, N1_pad, table, bias_work);
+    else hipLaunchKernelGGL(cube_fold_kernel<1>, dim3(blocks), dim3(256), 0, s, master, bias, N1, N1_pad, table, bias_work);
+}
+
 
 }  // namespace hb

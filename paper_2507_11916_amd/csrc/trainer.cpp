@@ -24,6 +24,8 @@
 namespace hb {
 namespace {
 
+constexpr int kScatterChunks = 32;  // state chunks of the layer-1 scatter (its blocks: chunks x N1 / 64)
+
 struct TLayer {
     int K, N, K_pad, N_pad;
     float *master, *m, *v;     // K*N
@@ -51,7 +53,14 @@ struct hb_trainer {
     hb_train_opts o{};
     hb::NetSpec spec;
     int t = 1, eb = 2;
-    int side = 4, P = 16, S = 16, rows1 = 256;
+    int side = 4, P = 16, S = 16, rows1 = 256;  // rows1: layer-1 weight rows in the file (cube: 54 x 6)
+    int dom = 1, trows = 256;                    // trows: gathered table rows (cube: 48 x 6, centres folded)
+    float* l1_bias_work = nullptr;               // cube: bias + the six centre rows (the gather's bias)
+    float* partial = nullptr;                    // layer-1 scatter: per-chunk partial sums
+    float* head_part = nullptr;                  // output layer: per-block partial gradients and loss
+    float* colpart = nullptr;                    // bias gradients: per-row-block column sums
+    hb::AdamTensor* d_adam = nullptr;            // every parameter tensor's Adam descriptor (device)
+    int n_adam = 0;
     int N1 = 0, N1_pad = 0, H = 0, H_pad = 0, M_pad = 0, W_pad = 0;
     float *l1_master = nullptr, *l1_m = nullptr, *l1_v = nullptr;
     void* l1_table = nullptr;
@@ -133,7 +142,7 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
 
 hb_status transpose(hb_trainer* tr, const void* in, int ld_in, void* out, int ld_out, int R, int C, float* colsum,
                     int rows_sum, hipStream_t s) {
-    TransposeArgs a{in, ld_in, out, ld_out, R, C, colsum, rows_sum};
+    TransposeArgs a{in, ld_in, out, ld_out, R, C, colsum, rows_sum, colsum ? tr->colpart : nullptr};
     launch_transpose(a, tr->t, s);
     HB_HIP(hipGetLastError());
     return HB_OK;
@@ -143,13 +152,7 @@ hb_status transpose(hb_trainer* tr, const void* in, int ld_in, void* out, int ld
 hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels, int n, hipStream_t s) {
     const int Me = (int)round_up(n, 128);
     const int t = tr->t;
-    // zero the accumulated gradients
-    launch_fill(tr->dW1, (int64_t)tr->rows1 * tr->N1_pad, 0.f, s);
-    launch_fill(tr->db1, tr->N1_pad, 0.f, s);
-    launch_fill(tr->dWo, tr->H_pad, 0.f, s);
-    launch_fill(tr->dbo, 1, 0.f, s);
-    launch_fill(tr->d_loss, 1, 0.f, s);
-    for (auto& l : tr->L) launch_fill(l.db, l.N_pad, 0.f, s);
+    // every gradient buffer is written (not accumulated) by a fixed-order reduction
     // forward
     GatherLaunch G{};
     G.domain = tr->spec.domain;
@@ -159,8 +162,8 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     G.m_rows = Me;
     G.table = tr->l1_table;
     G.table_f32 = t == 0;
-    G.t_rows = tr->rows1;
-    G.bias = tr->l1_bias;
+    G.t_rows = tr->trows;
+    G.bias = tr->dom == 2 ? tr->l1_bias_work : tr->l1_bias;
     G.N = tr->N1_pad;
     G.ld_out = tr->W_pad;
     G.out = tr->act[0];
@@ -186,9 +189,9 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     h.asym = tr->o.asym;
     h.alpha = tr->o.alpha;
     h.delta = tr->G;
+    h.part = tr->head_part;
     h.dWo = tr->dWo;
-    h.dbo = tr->dbo;
-    h.loss = tr->d_loss;
+    h.dbo_loss = tr->dbo;  // dbo, then the loss
     if (!launch_head_train(h, t, s)) return fail(HB_E_UNSUPPORTED, "head width");
     HB_HIP(hipGetLastError());
     // backward: cur holds the gradient at the pre-activation of the current layer output
@@ -232,37 +235,53 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     sa.packed = d_packed;
     sa.n = n;
     sa.N1 = tr->N1_pad;
+    sa.partial = tr->partial;
+    sa.chunk = (n + kScatterChunks - 1) / kScatterChunks;
     sa.dW1 = tr->dW1;
     sa.ld_w = tr->N1_pad;
     sa.db1 = tr->db1;
-    sa.states_per_block = 256;
-    if (!launch_scatter_l1(sa, t, tr->side, s)) return fail(HB_E_UNSUPPORTED, "layer-1 gradient");
+    if (!launch_scatter_l1(sa, t, tr->dom, (n + sa.chunk - 1) / sa.chunk, s))
+        return fail(HB_E_UNSUPPORTED, "layer-1 gradient");
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
-void adam(hb_trainer* tr, float* master, float* m, float* v, const float* grad, int64_t gk, int64_t gn, int K, int N,
-          void* out1, int64_t s1k, int64_t s1n, void* out2, int64_t s2k, int64_t s2n, hipStream_t s) {
-    AdamArgs a{};
-    a.master = master; a.m = m; a.v = v; a.grad = grad; a.gk = gk; a.gn = gn; a.K = K; a.N = N;
-    a.lr = tr->o.lr; a.b1 = tr->o.beta1; a.b2 = tr->o.beta2; a.eps = tr->o.eps;
-    a.c1 = 1.f - std::pow(tr->o.beta1, (float)tr->step);
-    a.c2 = 1.f - std::pow(tr->o.beta2, (float)tr->step);
-    a.out1 = out1; a.s1k = s1k; a.s1n = s1n; a.out2 = out2; a.s2k = s2k; a.s2n = s2n;
-    launch_adam(a, tr->t, s);
+AdamTensor adam_tensor(float* master, float* m, float* v, const float* grad, int64_t gk, int64_t gn, int K, int N,
+                       void* out1, int64_t s1k, int64_t s1n, void* out2, int64_t s2k, int64_t s2n) {
+    return AdamTensor{master, m, v, grad, gk, gn, K, N, out1, s1k, s1n, out2, s2k, s2n};
+}
+
+// The descriptors of every parameter tensor (fixed at creation): master
+// weights, moments, gradient, and the working copies Adam rewrites.  The
+// cube's layer-1 table and bias are rebuilt from the masters after the step.
+hb_status upload_adam_table(hb_trainer* tr) {
+    std::vector<AdamTensor> ts;
+    const bool cube = tr->dom == 2;
+    ts.push_back(adam_tensor(tr->l1_master, tr->l1_m, tr->l1_v, tr->dW1, tr->N1_pad, 1, tr->rows1, tr->N1,
+                             cube ? nullptr : tr->l1_table, tr->N1_pad, 1, nullptr, 0, 0));
+    ts.push_back(adam_tensor(tr->l1_bias, tr->l1_bm, tr->l1_bv, tr->db1, 0, 1, 1, tr->N1, nullptr, 0, 0, nullptr, 0, 0));
+    for (auto& l : tr->L) {
+        ts.push_back(adam_tensor(l.master, l.m, l.v, l.dW, l.N_pad, 1, l.K, l.N, l.Wt, 1, l.K_pad, l.Wkn, l.N_pad, 1));
+        ts.push_back(adam_tensor(l.bias, l.bm, l.bv, l.db, 0, 1, 1, l.N, nullptr, 0, 0, nullptr, 0, 0));
+    }
+    ts.push_back(adam_tensor(tr->ho_master, tr->ho_m, tr->ho_v, tr->dWo, 1, 0, tr->H, 1, tr->ho_W, 1, 0, nullptr, 0, 0));
+    ts.push_back(adam_tensor(tr->ho_b, tr->ho_bm, tr->ho_bv, tr->dbo, 0, 1, 1, 1, nullptr, 0, 0, nullptr, 0, 0));
+    void* d = nullptr;
+    hb_status st = dalloc(tr, ts.size() * sizeof(AdamTensor), &d);
+    if (st != HB_OK) return st;
+    HB_HIP(hipMemcpy(d, ts.data(), ts.size() * sizeof(AdamTensor), hipMemcpyHostToDevice));
+    tr->d_adam = static_cast<AdamTensor*>(d);
+    tr->n_adam = (int)ts.size();
+    return HB_OK;
 }
 
 void apply_adam(hb_trainer* tr, hipStream_t s) {
     tr->step++;
-    adam(tr, tr->l1_master, tr->l1_m, tr->l1_v, tr->dW1, tr->N1_pad, 1, tr->rows1, tr->N1, tr->l1_table, tr->N1_pad, 1,
-         nullptr, 0, 0, s);
-    adam(tr, tr->l1_bias, tr->l1_bm, tr->l1_bv, tr->db1, 0, 1, 1, tr->N1, nullptr, 0, 0, nullptr, 0, 0, s);
-    for (auto& l : tr->L) {
-        adam(tr, l.master, l.m, l.v, l.dW, l.N_pad, 1, l.K, l.N, l.Wt, 1, l.K_pad, l.Wkn, l.N_pad, 1, s);
-        adam(tr, l.bias, l.bm, l.bv, l.db, 0, 1, 1, l.N, nullptr, 0, 0, nullptr, 0, 0, s);
-    }
-    adam(tr, tr->ho_master, tr->ho_m, tr->ho_v, tr->dWo, 1, 0, tr->H, 1, tr->ho_W, 1, 0, nullptr, 0, 0, s);
-    adam(tr, tr->ho_b, tr->ho_bm, tr->ho_bv, tr->dbo, 0, 1, 1, 1, nullptr, 0, 0, nullptr, 0, 0, s);
+    const float c1 = 1.f - std::pow(tr->o.beta1, (float)tr->step);
+    const float c2 = 1.f - std::pow(tr->o.beta2, (float)tr->step);
+    launch_multi_adam(tr->d_adam, tr->n_adam, tr->o.lr, tr->o.beta1, tr->o.beta2, tr->o.eps, c1, c2, tr->t, s);
+    if (tr->dom == 2)
+        launch_cube_fold(tr->l1_master, tr->l1_bias, tr->N1, tr->N1_pad, tr->l1_table, tr->l1_bias_work, tr->t, s);
 }
 
 // Copy rows x cols floats from a padded device array (row stride ld) to dst.
@@ -293,7 +312,6 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     NetSpec spec;
     const char* why = "";
     if (!read_weight_file(path, &spec, &why)) return fail(HB_E_INVAL, "%s: %s", path, why);
-    if (spec.domain == 2) return fail(HB_E_UNSUPPORTED, "training supports the sliding-tile domains");
     if (spec.head_kind != 0 || spec.n_out != 1) return fail(HB_E_UNSUPPORTED, "training needs a regression head");
     for (int d : spec.dims)
         if (d > 1024) return fail(HB_E_UNSUPPORTED, "hidden widths above 1024 are not supported in training");
@@ -302,7 +320,11 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     if (o.device < 0 || o.device >= ndev) return fail(HB_E_INVAL, "device out of range");
     HB_HIP(hipSetDevice(o.device));
     static bool attrs = false;
-    if (!attrs) { HB_HIP(gemm_prepare_attributes()); attrs = true; }
+    if (!attrs) {
+        HB_HIP(gemm_prepare_attributes());
+        HB_HIP(train_prepare_attributes());
+        attrs = true;
+    }
     auto tr = std::make_unique<hb_trainer>();
     hb_trainer* T = tr.get();
     T->device = o.device;
@@ -310,9 +332,12 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     T->spec = spec;
     T->t = o.prec == HB_FP32 ? 0 : 1;
     T->eb = o.prec == HB_FP32 ? 4 : 2;
+    T->dom = spec.domain;
     T->side = spec.domain == 0 ? 3 : 4;
-    T->P = T->S = T->side * T->side;
+    T->P = spec.domain == 2 ? 54 : T->side * T->side;
+    T->S = spec.domain == 2 ? 6 : T->side * T->side;
     T->rows1 = T->P * T->S;
+    T->trows = scatter_table_rows(spec.domain);
     auto pad = [](int v) { return (int)round_up(v, 128); };
     T->N1 = spec.dims[0];
     T->N1_pad = pad(T->N1);
@@ -328,13 +353,22 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     if ((st = up_f32(T, TS[0], &T->l1_master)) != HB_OK) return st;
     if ((st = dalloc_t(T, TS[0].size(), &T->l1_m)) != HB_OK || (st = dalloc_t(T, TS[0].size(), &T->l1_v)) != HB_OK) return st;
     {
-        std::vector<float> tab((size_t)T->rows1 * T->N1_pad, 0.f);
-        for (int r = 0; r < T->rows1; r++)
-            for (int j = 0; j < T->N1; j++) tab[(size_t)r * T->N1_pad + j] = TS[0][(size_t)r * T->N1 + j];
-        if ((st = up_work(T, tab, &T->l1_table)) != HB_OK) return st;
         std::vector<float> b(T->N1_pad, 0.f);
         for (int j = 0; j < T->N1; j++) b[j] = TS[1][j];
         if ((st = up_f32(T, b, &T->l1_bias)) != HB_OK) return st;
+        if (T->dom == 2) {
+            // the working table and folded bias are built from the masters on the device
+            if ((st = dalloc(T, (size_t)T->trows * T->N1_pad * T->eb, &T->l1_table)) != HB_OK) return st;
+            if ((st = dalloc_t(T, T->N1_pad, &T->l1_bias_work)) != HB_OK) return st;
+            launch_cube_fold(T->l1_master, T->l1_bias, T->N1, T->N1_pad, T->l1_table, T->l1_bias_work, T->t, nullptr);
+            HB_HIP(hipGetLastError());
+            HB_HIP(hipDeviceSynchronize());
+        } else {
+            std::vector<float> tab((size_t)T->rows1 * T->N1_pad, 0.f);
+            for (int r = 0; r < T->rows1; r++)
+                for (int j = 0; j < T->N1; j++) tab[(size_t)r * T->N1_pad + j] = TS[0][(size_t)r * T->N1 + j];
+            if ((st = up_work(T, tab, &T->l1_table)) != HB_OK) return st;
+        }
     }
     if ((st = dalloc_t(T, T->N1_pad, &T->l1_bm)) != HB_OK || (st = dalloc_t(T, T->N1_pad, &T->l1_bv)) != HB_OK) return st;
     if ((st = dalloc_t(T, (size_t)T->rows1 * T->N1_pad, &T->dW1)) != HB_OK || (st = dalloc_t(T, T->N1_pad, &T->db1)) != HB_OK)
@@ -384,7 +418,9 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     }
     if ((st = up_f32(T, TS[ti + 1], &T->ho_b)) != HB_OK) return st;
     if ((st = dalloc_t(T, 1, &T->ho_bm)) != HB_OK || (st = dalloc_t(T, 1, &T->ho_bv)) != HB_OK) return st;
-    if ((st = dalloc_t(T, T->H_pad, &T->dWo)) != HB_OK || (st = dalloc_t(T, 1, &T->dbo)) != HB_OK) return st;
+    if ((st = dalloc_t(T, T->H_pad, &T->dWo)) != HB_OK || (st = dalloc_t(T, 2, &T->dbo)) != HB_OK) return st;
+    T->d_loss = T->dbo + 1;
+    if ((st = dalloc_t(T, (size_t)head_train_blocks(T->M_pad) * (T->H_pad + 2), &T->head_part)) != HB_OK) return st;
     // activations and scratch
     const size_t abytes = (size_t)T->M_pad * T->W_pad * T->eb;
     T->act.resize(T->n_act);
@@ -393,7 +429,9 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     if ((st = dalloc(T, abytes, &T->G)) != HB_OK || (st = dalloc(T, abytes, &T->G2)) != HB_OK ||
         (st = dalloc(T, abytes, &T->XT)) != HB_OK || (st = dalloc(T, abytes, &T->GT)) != HB_OK)
         return st;
-    if ((st = dalloc_t(T, 1, &T->d_loss)) != HB_OK) return st;
+    if ((st = dalloc_t(T, (size_t)(T->M_pad / 64 + 1) * T->W_pad, &T->colpart)) != HB_OK) return st;
+    if ((st = dalloc_t(T, (size_t)kScatterChunks * (T->trows + 1) * T->N1_pad, &T->partial)) != HB_OK) return st;
+    if ((st = upload_adam_table(T)) != HB_OK) return st;
     *out = tr.release();
     return HB_OK;
 }
