@@ -98,6 +98,11 @@ def _declare(L):
                                C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
     L.orc_bts_real.argtypes = [vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                C.POINTER(IterReal), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
+    L.orc_ida_real_net.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int64, C.POINTER(IterReal),
+                                   C.POINTER(C.c_int), C.POINTER(C.c_int32), vp, C.POINTER(C.c_int)]
+    L.orc_bts_real_net.argtypes = [vp, C.c_double, vp, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                   C.POINTER(IterReal), C.POINTER(C.c_int), C.POINTER(C.c_int32), vp,
+                                   C.POINTER(C.c_int)]
     L.orc_train_grad.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_double, vp, vp]
     L.orc_train_grad.restype = C.c_double
     L.orc_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double,
@@ -474,6 +479,31 @@ def ida_real(start, table8f, complete_final=False, max_iters=5000, node_limit=-1
     path = np.zeros(512, dtype=np.int8)
     rc = lib().orc_ida_real(s.ctypes.data, t.ctypes.data, int(complete_final), max_iters, node_limit, arr,
                             C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters_real(arr, n.value))
+
+
+def ida_real_net(net, start, offset=0.0, complete_final=False, max_iters=5000, node_limit=-1):
+    """Serial IDA* on the network's domain with h = max(0, y - offset), y the
+    oracle's double-precision output per node."""
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (IterReal * max_iters)()
+    n, cost, plen = C.c_int(0), C.c_int32(-1), C.c_int(0)
+    path = np.zeros(512, dtype=np.int8)
+    rc = lib().orc_ida_real_net(net._h, offset, s.ctypes.data, int(complete_final), max_iters, node_limit, arr,
+                                C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
+    return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
+                iters=_iters_real(arr, n.value))
+
+
+def bts_real_net(net, start, offset=0.0, b0=10000, c1=2, c2=8, plus_one=True, max_iters=2000, max_total=-1):
+    """Serial BTS on the network's domain with h = max(0, y - offset)."""
+    s = np.ascontiguousarray(start, dtype=np.uint8)
+    arr = (IterReal * max_iters)()
+    n, cost, plen = C.c_int(0), C.c_int32(-1), C.c_int(0)
+    path = np.zeros(512, dtype=np.int8)
+    rc = lib().orc_bts_real_net(net._h, offset, s.ctypes.data, b0, c1, c2, int(plus_one), max_iters, max_total, arr,
+                                C.byref(n), C.byref(cost), path.ctypes.data, C.byref(plen))
     return dict(status=rc, cost=cost.value, path=path[:plen.value].tolist() if rc == 1 else [],
                 iters=_iters_real(arr, n.value))
 

@@ -8,7 +8,8 @@
  * bound is the smallest pruned f, so with real values the bound grows by the
  * smallest f gap each iteration; BTS chooses bounds by expansion counts and
  * bisects over real bounds: probe = lo + (hi - lo) / 2.  h is read from a
- * table over 8-puzzle permutation ranks.
+ * table over 8-puzzle permutation ranks, or (any domain) computed per node as
+ * max(0, y - offset) from the oracle's own double-precision network.
  */
 #include <math.h>
 #include <stdint.h>
@@ -23,8 +24,14 @@ typedef struct {
     int64_t limit;
 } orc_iter_real;
 
+int orc_net_forward(const orc_net* m, const uint8_t* states, int64_t n, int mode, const double* act_scale,
+                    double* y_out, double* act_max);
+
 typedef struct {
+    int domain;
     const float* table8f;
+    const orc_net* net;
+    double offset;
     double bound, next;
     int64_t expanded, generated, limit;
     int exceeded, stop_at_goal, found;
@@ -32,7 +39,13 @@ typedef struct {
     int path_len;
 } rctx;
 
-static double h_real(const rctx* c, const uint8_t* s) { return (double)c->table8f[orc_perm9_rank(s)]; }
+static double h_real(const rctx* c, const uint8_t* s) {
+    if (!c->net) return (double)c->table8f[orc_perm9_rank(s)];
+    double y;
+    orc_net_forward(c->net, s, 1, 0, NULL, &y, NULL);
+    const double v = y - c->offset;
+    return v > 0.0 ? v : 0.0;
+}
 
 static int rdfs(rctx* c, const uint8_t* s, int g, int prev) {
     const double f = (double)g + h_real(c, s);
@@ -40,7 +53,7 @@ static int rdfs(rctx* c, const uint8_t* s, int g, int prev) {
         if (f < c->next) c->next = f;
         return 0;
     }
-    if (orc_is_goal(0, s)) {
+    if (orc_is_goal(c->domain, s)) {
         if (!c->found) {
             c->found = 1;
             c->path_len = g;
@@ -50,10 +63,10 @@ static int rdfs(rctx* c, const uint8_t* s, int g, int prev) {
     }
     if (c->limit >= 0 && c->expanded >= c->limit) { c->exceeded = 1; return 1; }
     c->expanded++;
-    for (int a = 0; a < orc_n_actions(0); a++) {
-        if (!orc_allowed(0, prev, a)) continue;
-        uint8_t ch[9];
-        if (!orc_apply(0, s, a, ch)) continue;
+    for (int a = 0; a < orc_n_actions(c->domain); a++) {
+        if (!orc_allowed(c->domain, prev, a)) continue;
+        uint8_t ch[54];
+        if (!orc_apply(c->domain, s, a, ch)) continue;
         c->generated++;
         if (g >= 511) continue;
         c->cur[g] = (int8_t)a;
@@ -71,12 +84,36 @@ static int rcbdfs(rctx* c, const uint8_t* start, double bound) {
     return !c->exceeded;
 }
 
+static int ida_real(rctx* cp, const uint8_t* start, int complete_final, int max_iters, int64_t node_limit,
+                    orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path, int* path_len);
+static int bts_real(rctx* cp, const uint8_t* start, int64_t b0, int c1, int c2, int plus_one, int max_iters,
+                    int64_t max_total, orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path, int* path_len);
+
 /* Serial IDA* on the 8-puzzle with a real-valued h table.  Returns as orc_ida. */
 int orc_ida_real(const uint8_t* start, const float* table8f, int complete_final, int max_iters, int64_t node_limit,
                  orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path, int* path_len) {
     rctx c;
     memset(&c, 0, sizeof(c));
     c.table8f = table8f;
+    return ida_real(&c, start, complete_final, max_iters, node_limit, iters, n_iters, cost, path, path_len);
+}
+
+/* Serial IDA* on any domain with h = max(0, y - offset), y the network's
+ * double-precision output for the state. */
+int orc_ida_real_net(const orc_net* net, double offset, const uint8_t* start, int complete_final, int max_iters,
+                     int64_t node_limit, orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path,
+                     int* path_len) {
+    rctx c;
+    memset(&c, 0, sizeof(c));
+    c.domain = net->domain;
+    c.net = net;
+    c.offset = offset;
+    return ida_real(&c, start, complete_final, max_iters, node_limit, iters, n_iters, cost, path, path_len);
+}
+
+static int ida_real(rctx* cp, const uint8_t* start, int complete_final, int max_iters, int64_t node_limit,
+                    orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path, int* path_len) {
+    rctx c = *cp;
     c.stop_at_goal = !complete_final;
     double bound = h_real(&c, start);
     int64_t total = 0;
@@ -113,6 +150,24 @@ int orc_bts_real(const uint8_t* start, const float* table8f, int64_t b0, int c1,
     rctx c;
     memset(&c, 0, sizeof(c));
     c.table8f = table8f;
+    return bts_real(&c, start, b0, c1, c2, plus_one, max_iters, max_total, iters, n_iters, cost, path, path_len);
+}
+
+/* Serial BTS on any domain with h = max(0, y - offset) from the network. */
+int orc_bts_real_net(const orc_net* net, double offset, const uint8_t* start, int64_t b0, int c1, int c2, int plus_one,
+                     int max_iters, int64_t max_total, orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path,
+                     int* path_len) {
+    rctx c;
+    memset(&c, 0, sizeof(c));
+    c.domain = net->domain;
+    c.net = net;
+    c.offset = offset;
+    return bts_real(&c, start, b0, c1, c2, plus_one, max_iters, max_total, iters, n_iters, cost, path, path_len);
+}
+
+static int bts_real(rctx* cp, const uint8_t* start, int64_t b0, int c1, int c2, int plus_one, int max_iters,
+                    int64_t max_total, orc_iter_real* iters, int* n_iters, int32_t* cost, int8_t* path, int* path_len) {
+    rctx c = *cp;
     c.stop_at_goal = 0;
     const double hroot = h_real(&c, start);
     int64_t b = b0, total = 0;

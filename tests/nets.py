@@ -30,3 +30,30 @@ def md_net_tensors(n):
 def write_md_net(path, n):
     dom = 0 if n == 3 else 1
     synth.write_weights_arrays(path, dom, n * n * n * n, [2, 3], 1, 2, 0, md_net_tensors(n))
+
+
+def cube_misplaced_net_tensors(scale):
+    """Cube regression net with y = scale x (number of non-centre stickers not
+    showing their face's colour).  Sticker p sits on face p // 9 (centre
+    9f + 4), whose colour is f.  Layer 1 gathers scale for each sticker whose
+    colour differs from its face into unit 0; one identity dense layer; the
+    head reads unit 0.  With a power-of-two scale every value is exact in
+    float32.  A half turn or quarter turn moves 20 stickers, so the value
+    changes by at most 20 x scale per move."""
+    W0 = np.zeros((54 * 6, 2))
+    for p in range(54):
+        if p % 9 == 4:
+            continue
+        for c in range(6):
+            if c != p // 9:
+                W0[p * 6 + c, 0] = scale
+    b0 = np.zeros(2)
+    W1 = np.eye(2)
+    b1 = np.zeros(2)
+    Wo = np.array([[1.0], [0.0]])
+    bo = np.zeros(1)
+    return [W0, b0, W1, b1, Wo, bo]
+
+
+def write_cube_misplaced_net(path, scale):
+    synth.write_weights_arrays(path, 2, 324, [2, 2], 0, 1, 0, cube_misplaced_net_tensors(scale))

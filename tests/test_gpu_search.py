@@ -13,6 +13,7 @@ import pytest
 import oracle as O
 import paper_2507_11916_amd as hb
 import synth
+from tests import nets
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -125,7 +126,6 @@ def _real_md_net(path):
     """Closed-form 8-puzzle network with y = MD/2 - 1/2 off the goal (the
     hand-built 2 MD - 2 network with its head scaled by 1/4): exact in float32
     and float64."""
-    from tests import nets
     ts = [np.asarray(t, dtype=np.float64) for t in nets.md_net_tensors(3)]
     ts[-2] = ts[-2][:, 1:2] * 0.25
     ts[-1] = np.asarray(ts[-1]).reshape(-1)[1:2] * 0.25
@@ -166,3 +166,38 @@ def test_real_valued_search_matches_oracle(tmp_path):
                [(it["bound"], it["limit"], it["complete"]) for it in o["iters"]]
         assert _complete_counts(r["iters"]) == [(int(np.floor(it["bound"])), it["expanded"], it["generated"])
                                                 for it in o["iters"] if it["complete"]]
+
+
+def test_real_valued_cube_search_matches_oracle(tmp_path):
+    """The cube with a real-valued h (Regression-Based Neural Heuristics runs
+    IDA* and BTS on the cube): h = max(0, y) with y = (misplaced stickers) / 16
+    from the GPU, exact in float32, so the oracle's double-precision network
+    gives the same values.  Batch IDA* and Batch BTS take the serial oracle's
+    iterations (real bounds, limits, counts) exactly and return its cost on
+    walks of 3-6 turns, with one and four search threads."""
+    path = str(tmp_path / "cube_mis.hbw")
+    nets.write_cube_misplaced_net(path, 1.0 / 16)
+    net = O.Net(path)
+    m = hb.Model(path, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=0.0, max_batch=4096)
+    for i, L in enumerate((3, 4, 5, 6, 5, 6)):
+        mv = synth.rc_walk_moves_array([3300 + i], length_base=L, length_span=1)
+        s = O.apply_moves(2, mv)[0]
+        threads = 1 if i % 2 == 0 else 4
+        p = hb.default_params(batch_size=256, work_num=4, complete_final_iter=1)
+        r = hb.cbdfs_solve(2, s, model=m, combine=hb.HB_H_NN_REAL, classic=hb.HB_CLASSIC_ZERO, threads=threads,
+                           params=p)
+        o = O.ida_real_net(net, s, complete_final=True)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"] == L
+        assert [(it["bound_real"], it["expanded"], it["generated"]) for it in r["iters"]] == \
+               [(it["bound"], it["expanded"], it["generated"]) for it in o["iters"]]
+        assert np.array_equal(_follow(2, s, r["path"]), O.goal(2))
+        p = hb.default_params(batch_size=256, work_num=4, bts_b0=50)
+        r = hb.cbdfs_solve(2, s, model=m, combine=hb.HB_H_NN_REAL, classic=hb.HB_CLASSIC_ZERO, algo=hb.HB_BTS,
+                           threads=threads, params=p)
+        o = O.bts_real_net(net, s, b0=50)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"] == L
+        assert [(it["bound_real"], it["limit"], it["complete"]) for it in r["iters"]] == \
+               [(it["bound"], it["limit"], it["complete"]) for it in o["iters"]]
+        assert _complete_counts(r["iters"]) == [(int(np.floor(it["bound"])), it["expanded"], it["generated"])
+                                                for it in o["iters"] if it["complete"]]
+    m.close()
