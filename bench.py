@@ -49,20 +49,30 @@ def tile_kernel(tile, prec):
     return k.format(p=PREC_ARG[prec]) if k else None
 
 
-def measured_traffic(kernel, prec="f32"):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    when the summary has no row for it or the kernel source has changed since."""
+def committed_counter(summary, key):
+    """A value from a committed rocprofv3 counter summary under profiles/, or None
+    when the summary has no such row or the kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"gemm_{prec}_stp4res_b8000_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         fields = dict(l.strip().split(": ", 1) for l in open(path) if l.startswith("    ") and ": " in l)
         src = os.path.join(ROOT, "paper_2507_11916_amd", "csrc", "kernels.hip")
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         if fields.get("kernels_hip_sha256_16") != sha:
             return None
-        return float(fields[f"traffic {kernel}"])
+        return float(fields[key])
     except (OSError, ValueError, KeyError):
         return None
+
+
+def measured_traffic(kernel, prec="f32"):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, copy-scaled)."""
+    return committed_counter(f"gemm_{prec}_stp4res_b8000_hbm_bytes.md", f"traffic {kernel}")
+
+
+def measured_mfma_busy(kernel):
+    """Fraction of SIMD cycles with the MFMA unit busy during `kernel` (counter)."""
+    return committed_counter("mfma_busy_stp4res_b8000.md", f"mfma_busy {kernel}")
 
 
 def main():
@@ -474,6 +484,7 @@ def main():
         r["gemm_kernel"] = k
         r["gemm_traffic"] = measured_traffic(k, name)
         r["gemm_frac"] = r["gemm_tflops"] / PEAK_TFLOPS[name]
+        r["gemm_mfma_busy_counter"] = measured_mfma_busy(k)
     line = {
         "metric": "heuristic evals/s + search nodes/s per GPU (FP32 vs BF16/FP8) at matched h",
         "value": f32["evals_per_s"],
@@ -493,6 +504,7 @@ def main():
                      "frac": ach / PEAK_TFLOPS["f32"], "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": f"{f32_kernel} (dense/residual layer, M=batch, K=N=1000 padded to 1024)",
+                     "mfma_busy_counter": measured_mfma_busy(f32_kernel),
                      "avg_launch_us": f32["gemm_avg_us"], "flops_per_launch": f32["gemm_flops_per_launch"]},
         "cpu_baseline": cpu,
         "cpu_baseline_search": cpu_search,
