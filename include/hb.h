@@ -253,8 +253,13 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
  * 5 32x32: one wave per tile, operands straight from global memory (small batches);
  * 6 256x128, 7 128x128, 8 128x256 (3-stage LDS ring), 9 64x128 (4-stage ring):
  *   LDS ring filled by direct global-to-LDS loads, 4 waves;
- * 10 256x128: LDS double buffer filled through registers, 8 waves (4 x 2).
- * All shapes give bitwise equal results.  HB_E_INVAL outside 0..10.  See hb_model_tune. */
+ * 10 256x128: LDS double buffer filled through registers, 8 waves (4 x 2);
+ * 11-14: the fused one-launch forward kernel, switched off in this build
+ *   (HB_E_UNSUPPORTED);
+ * 15 256x128 (2-stage ring), 16 256x128 (3-stage ring): LDS ring filled by
+ *   direct loads, each stage's operands read whole before its MFMAs, 8 waves;
+ * 17 256x128 (2-stage ring), the same with 16 waves (4 x 4, 64x32 each).
+ * All shapes give bitwise equal results.  HB_E_INVAL outside 0..17.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
 /* Autotuner for one batch size: times every tile shape on the n packed states
  * (device) and keeps the fastest for batches in n's power-of-two bucket

@@ -683,6 +683,154 @@ __global__ __launch_bounds__(256) void gemm_ring_kernel(GemmArgs g) {
     }
 }
 
+// ------------------------------------------------------------ GEMM, wide blocks
+// MFMAs of one 128-byte K stage for a wave's TI x TJ 32 x 32 tiles (A rows
+// ar0 + 32 i, B rows br0 + 32 j), with every LDS read of the stage issued before
+// the first MFMA: the MFMAs then wait only for their own operands and run while
+// the rest of the stage is still arriving.  A scheduling barrier keeps the
+// compiler from sinking the reads back next to their MFMAs (which it does to
+// save registers, leaving one LDS round trip exposed per 32-byte K group).
+// The MFMA sequence per output element is mma_stage's (same chunk, same order).
+template <int PREC, int TI, int TJ>
+__device__ __forceinline__ void mma_stage_pre(const uint8_t* a_s, const uint8_t* b_s, floatx16 (&acc)[TI][TJ],
+                                              int ar0, int br0, int lane) {
+    const int half = lane >> 5, r32 = lane & 31;
+    if (PREC == 2) {
+        intx8 af[2][TI], bfr[2][TJ];
+        _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
+            _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                const int row = ar0 + i * 32 + r32;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
+                af[kg][i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+            _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+                const int row = br0 + j * 32 + r32;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
+                const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
+                bfr[kg][j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        _Pragma("unroll") for (int kg = 0; kg < 2; kg++)
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[kg][i], bfr[kg][j], acc[i][j], 0, 0,
+                                                                               0, 127, 0, 127);
+    } else {
+        u32x4 af[4][TI], bfr[4][TJ];
+        _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                af[kg][i] = *reinterpret_cast<const u32x4*>(a_s + swz(ar0 + i * 32 + r32, 2 * kg + half));
+            _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                bfr[kg][j] = *reinterpret_cast<const u32x4*>(b_s + swz(br0 + j * 32 + r32, 2 * kg + half));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
+            if (PREC == 1) {
+                _Pragma("unroll") for (int i = 0; i < TI; i++)
+                    _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[kg][i]),
+                                                                            __builtin_bit_cast(bf16x8, bfr[kg][j]),
+                                                                            acc[i][j], 0, 0, 0);
+            } else {
+                _Pragma("unroll") for (int e = 0; e < 4; e++)
+                    _Pragma("unroll") for (int i = 0; i < TI; i++)
+                        _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(af[kg][i][e]),
+                                                                             __uint_as_float(bfr[kg][j][e]), acc[i][j],
+                                                                             0, 0, 0);
+            }
+        }
+    }
+}
+
+// 256 x 128 tile, one block per compute unit, NW waves in a 4 x (NW / 4) grid
+// (8 waves: 64 x 64 each; 16 waves: 64 x 32 each), operands from global memory
+// straight into a ring of NS LDS stages (as gemm_ring_kernel), each stage's
+// fragments read whole before its MFMAs (mma_stage_pre).  With 8 waves, a wave
+// raises its priority while it issues MFMAs, so that of the two waves sharing
+// a SIMD the one with operands in registers goes first instead of both reading
+// LDS and then both multiplying.  Same per-element MFMA sequence and epilogue
+// as the other tiles: bitwise equal results.
+template <int PREC, int OUTT, int NW, int NS>
+__global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
+    constexpr int BM = 256, BN = 128, NT = NW * 64;
+    constexpr int EB = Ty<PREC>::EB;
+    constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128, STAGE = A_BYTES + B_BYTES;
+    constexpr int NA = A_BYTES / 1024, LD = STAGE / 1024 / NW;  // 1 KiB load instructions per wave per stage
+    constexpr int TI = 2, TJ = NW == 8 ? 2 : 1;
+    static_assert(NW == 8 || NW == 16, "wave count");
+    static_assert(NS >= 2 && NS <= 3, "ring depth");
+    static_assert((STAGE / 1024) % NW == 0, "loads per wave");
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int M = g.m_dev ? *g.m_dev : g.m_host;
+    const int m_tiles = min((M + BM - 1) / BM, g.m_tiles_cap);
+    const int n_tiles = g.N / BN;
+    const int total = m_tiles * n_tiles;
+    const int ktiles = g.K * EB / 128;
+    const int grid = gridDim.x, grid8 = grid & ~7;
+    int first = blockIdx.x;
+    if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
+    const int lrow = lane >> 3;
+    (void)NT;
+
+    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+        const int m0 = (t / n_tiles) * BM, n0 = (t % n_tiles) * BN;
+        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
+        const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
+        floatx16 acc[TI][TJ];
+        _Pragma("unroll") for (int i = 0; i < TI; i++)
+            _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                _Pragma("unroll") for (int e = 0; e < 16; e++) acc[i][j][e] = 0.f;
+
+        auto issue = [&](int kt) {
+            uint8_t* base = smem + (kt % NS) * STAGE;
+            const int kbyte = kt * 128;
+            _Pragma("unroll") for (int i = 0; i < LD; i++) {
+                const int q = wave + NW * i;
+                const bool isA = q < NA;
+                const int qq = isA ? q : q - NA;
+                const int row = 8 * qq + lrow;
+                const int ch = (lane & 7) ^ ((row >> 1) & 7);
+                const uint8_t* src =
+                    (isA ? Ag + (size_t)row * g.lda * EB : Bg + (size_t)row * g.ldb * EB) + kbyte + ch * 16;
+                uint8_t* dst = base + (isA ? 0 : A_BYTES) + qq * 1024;
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+            }
+        };
+
+        __syncthreads();  // the previous tile's readers are done with every slot
+        _Pragma("unroll") for (int s0 = 0; s0 < NS - 1; s0++)
+            if (s0 < ktiles) issue(s0);
+        for (int kt = 0; kt < ktiles; kt++) {
+            // stages issued: min(ktiles, kt + NS - 1); those after kt may stay in flight
+            if (NS == 3 && kt + 1 < ktiles) wait_vmcnt<(NS == 3 ? LD : 0)>();
+            else wait_vmcnt<0>();
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (kt + NS - 1 < ktiles) issue(kt + NS - 1);
+            const uint8_t* a_s = smem + (kt % NS) * STAGE;
+            if (NW == 8) __builtin_amdgcn_s_setprio(1);
+            mma_stage_pre<PREC, TI, TJ>(a_s, a_s + A_BYTES, acc, wm * 64, wn * (TJ * 32), lane);
+            if (NW == 8) __builtin_amdgcn_s_setprio(0);
+        }
+
+        const int half = lane >> 5, c32 = lane & 31;
+        _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+            const int n = n0 + wn * (TJ * 32) + j * 32 + c32;
+            const float bn = g.bias ? g.bias[n] : 0.f;
+            const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
+            _Pragma("unroll") for (int i = 0; i < TI; i++)
+                epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
+        }
+    }
+}
+
 // ------------------------------------------------------------ small-batch GEMM
 // One wave per 32 x 32 output tile, operands read from global memory straight
 // into registers (no LDS, no barriers), several K stages prefetched ahead of
@@ -1276,16 +1424,39 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_w8_kernel<PREC, OUTT>), dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, g);
 }
 
+template <int PREC, int OUTT, int NW, int NS>
+static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
+    GemmArgs g;
+    g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
+    g.Mk = (const uint8_t*)L.Mk;
+    g.bias = L.bias; g.colscale = L.colscale; g.m_dev = L.m_dev; g.m_host = L.m_host;
+    g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
+    g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
+    g.group_n = L.group_n; g.group_k = L.group_k;
+    const int m_tiles = (L.m_cap + 255) / 256;
+    const int tiles = m_tiles * (L.N / 128);
+    g.m_tiles_cap = m_tiles;
+    int grid = tiles;
+    g.persistent = 0;
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.m_dev) g.persistent = 1;
+    hipLaunchKernelGGL((gemm_wide_kernel<PREC, OUTT, NW, NS>), dim3(grid), dim3(NW * 64), (size_t)NS * (256 + 128) * 128,
+                       s, g);
+}
+
 // Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the
 // small-batch kernel (one wave per 32 x 32 tile), 5-8 the LDS ring fed by
 // direct loads, 9 the 8-wave 256 x 128 tile, 10-13 the fused persistent
 // forward kernel (one-wave 32 x 32 tiles; 2, 4, 8 or 12 waves per compute
-// unit), which replaces the whole forward pass rather than one layer.
-int gemm_tile_count() { return 14; }
+// unit), which replaces the whole forward pass rather than one layer;
+// 14-16 the wide-block ring kernels (8 waves with a 2- or 3-stage ring, 16
+// waves with a 2-stage ring).
+int gemm_tile_count() { return 17; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[14][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+    static const int T[17][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
                                  {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128},
-                                 {32, 32}, {32, 32}, {32, 32}, {32, 32}};
+                                 {32, 32}, {32, 32}, {32, 32}, {32, 32},
+                                 {256, 128}, {256, 128}, {256, 128}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -1303,6 +1474,9 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 7: launch_gemm_ring<PREC, OUTT, 128, 256, 3>(L, s); return true;
         case 8: launch_gemm_ring<PREC, OUTT, 64, 128, 4>(L, s); return true;
         case 9: launch_gemm_w8<PREC, OUTT>(L, s); return true;
+        case 14: launch_gemm_wide<PREC, OUTT, 8, 2>(L, s); return true;
+        case 15: launch_gemm_wide<PREC, OUTT, 8, 3>(L, s); return true;
+        case 16: launch_gemm_wide<PREC, OUTT, 16, 2>(L, s); return true;
     }
     return false;
 }
@@ -1414,6 +1588,12 @@ static hipError_t set_ring_attr() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, NS * (BM + BN) * 128);
 }
 
+template <int PREC, int OUTT, int NW, int NS>
+static hipError_t set_wide_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_wide_kernel<PREC, OUTT, NW, NS>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, NS * (256 + 128) * 128);
+}
+
 template <int PREC, int OUTT>
 static hipError_t set_lds_attr_p() {
     hipError_t e = set_lds_attr<PREC, OUTT, 128, 128>();
@@ -1428,6 +1608,9 @@ static hipError_t set_lds_attr_p() {
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 128, 3>();
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 128, 256, 3>();
     if (e == hipSuccess) e = set_ring_attr<PREC, OUTT, 64, 128, 4>();
+    if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 8, 2>();
+    if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 8, 3>();
+    if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 16, 2>();
     return e;
 }
 

@@ -84,11 +84,11 @@ def test_ensemble_matches_oracle(tmp_path, prec, rule):
 
 
 @pytest.mark.parametrize("prec,tile", [(hb.HB_FP32, 0), (hb.HB_BF16, 0), (hb.HB_BF16, 6), (hb.HB_BF16, 10),
-                                       (hb.HB_FP32, 10)])
+                                       (hb.HB_FP32, 10), (hb.HB_BF16, 15), (hb.HB_FP32, 17)])
 def test_fused_equals_separate_members(tmp_path, prec, tile):
     """The fused ensemble (grouped GEMMs: each member's columns read their own
     slice of the activations) equals the members evaluated one by one, for the
-    automatic tile and forced ring and 8-wave tiles."""
+    automatic tile and forced ring, 8-wave and wide-block ring tiles."""
     paths = _members(tmp_path, "stp4_res", 256, [31, 32], 40.0)
     st = synth.stp_walks(4, synth.throughput_seeds(500, 505), lengths=200)
     packed = hb.hb_encode(1, st)
