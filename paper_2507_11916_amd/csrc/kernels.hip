@@ -265,6 +265,10 @@ struct GemmArgs {
     int persistent;          // loop over tiles with a grid stride
     const uint8_t* Mk;       // mask (C's type and layout) or null: zero where Mk <= 0
     int group_n, group_k;    // grouped product: C columns of group g read A columns from g * group_k
+    // split-K (wide tiles only): slice s of `split` multiplies K elements
+    // [s K / split, (s + 1) K / split) into C + s * c_split elements
+    int split = 1;
+    int64_t c_split = 0;
 };
 
 // Column offset in A of the group that output column n0 belongs to.
@@ -770,8 +774,11 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
     const int M = g.m_dev ? *g.m_dev : g.m_host;
     const int m_tiles = min((M + BM - 1) / BM, g.m_tiles_cap);
     const int n_tiles = g.N / BN;
-    const int total = m_tiles * n_tiles;
-    const int ktiles = g.K * EB / 128;
+    const int split = g.split > 1 ? g.split : 1;
+    const int tiles_mn = m_tiles * n_tiles;
+    const int total = tiles_mn * split;
+    const int kslice = g.K / split;
+    const int ktiles = kslice * EB / 128;
     const int grid = gridDim.x, grid8 = grid & ~7;
     int first = blockIdx.x;
     if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
@@ -779,9 +786,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
     (void)NT;
 
     for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
-        const int m0 = (t / n_tiles) * BM, n0 = (t % n_tiles) * BN;
-        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
-        const uint8_t* Bg = g.Bt + (size_t)n0 * g.ldb * EB;
+        const int sl = t / tiles_mn, tt = t - sl * tiles_mn;
+        const int m0 = (tt / n_tiles) * BM, n0 = (tt % n_tiles) * BN;
+        const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0) + (size_t)sl * kslice) * EB;
+        const uint8_t* Bg = g.Bt + ((size_t)n0 * g.ldb + (size_t)sl * kslice) * EB;
         floatx16 acc[TI][TJ];
         _Pragma("unroll") for (int i = 0; i < TI; i++)
             _Pragma("unroll") for (int j = 0; j < TJ; j++)
@@ -821,12 +829,14 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
         }
 
         const int half = lane >> 5, c32 = lane & 31;
+        GemmArgs gs = g;  // slice sl writes its own C
+        if (sl) gs.C = g.C + (size_t)sl * g.c_split * (OUTT == 0 ? 4 : OUTT == 1 ? 2 : 1);
         _Pragma("unroll") for (int j = 0; j < TJ; j++) {
             const int n = n0 + wn * (TJ * 32) + j * 32 + c32;
             const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
             _Pragma("unroll") for (int i = 0; i < TI; i++)
-                epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
+                epi_tile<OUTT>(gs, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
         }
     }
 }
@@ -1433,8 +1443,10 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.split = L.split > 1 ? L.split : 1;
+    g.c_split = L.c_split;
     const int m_tiles = (L.m_cap + 255) / 256;
-    const int tiles = m_tiles * (L.N / 128);
+    const int tiles = m_tiles * (L.N / 128) * g.split;
     g.m_tiles_cap = m_tiles;
     int grid = tiles;
     g.persistent = 0;
@@ -1483,6 +1495,12 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
 
 bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
     const int out = L.out_type < 0 ? L.prec : L.out_type;
+    if (L.split > 1) {  // split-K: wide tiles, whole 128-byte stages per slice, host row count
+        const int eb = L.prec == 0 ? 4 : L.prec == 1 ? 2 : 1;
+        if (L.tile < 14 || L.tile > 16 || L.K % L.split != 0 || (L.K / L.split) * eb % 128 != 0 || L.m_dev ||
+            L.R || L.Mk)
+            return false;
+    }
     if (L.prec == 0 && out == 0) return launch_gemm_p<0, 0>(L, s);
     if (L.prec == 1 && out == 1) return launch_gemm_p<1, 1>(L, s);
     if (L.prec == 1 && out == 0) return launch_gemm_p<1, 0>(L, s);

@@ -44,6 +44,11 @@ struct GemmLaunch {
     // Grouped product (ensembles): columns [g*group_n, (g+1)*group_n) of C use
     // A's columns [g*group_k, (g+1)*group_k).  0: one group.
     int group_n = 0, group_k = 0;
+    // Split-K (tile ids 14-16 only; K / split a multiple of one 128-byte
+    // stage): slice s multiplies K elements [s K / split, (s + 1) K / split)
+    // into C + s * c_split elements (partial products, summed by the caller).
+    int split = 1;
+    int64_t c_split = 0;
 };
 
 struct HeadArgs {

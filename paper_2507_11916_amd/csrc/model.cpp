@@ -122,7 +122,7 @@ int choose_tile(const hb_model* m, int64_t M, int N_pad) {
     // results as the large tiles).  Beyond: the biggest tile that still gives
     // every compute unit a block.
     if (M <= 512 && N_pad % 32 == 0) return 4;
-    const int order[3] = {1, 0, 2};
+    const int order[4] = {14, 1, 0, 2};
     for (int id : order) {
         int bm, bn;
         gemm_tile_shape(id, &bm, &bn);
@@ -675,7 +675,7 @@ static hb_status scratch_address(int device, unsigned char** out) {
 int64_t model_noalloc_capacity(const hb_model* m) {
     const int eb = m->opts.prec == HB_FP32 ? 4 : m->opts.prec == HB_BF16 ? 2 : 1;
     const size_t row_bytes = (size_t)m->width_cap * eb;
-    return (int64_t)(kScratchBytes / 2 / row_bytes) / 128 * 128;
+    return (int64_t)(kScratchBytes / 2 / row_bytes) / 256 * 256;  // whole 256-row GEMM tiles
 }
 
 hb_status model_eval_noalloc(hb_model* m, const uint8_t* d_packed, int64_t n, int32_t* d_h, float* d_raw,

@@ -40,32 +40,75 @@ __global__ void fill_kernel(float* p, int64_t n, float v) {
 // x_k > 0 (gradient at the pre-activation of the last hidden layer).  Rows >= n
 // get delta = 0.  dWo, dbo and the loss are reduced over the block's rows in
 // LDS; each block writes its partial sums, which column_sum_kernel adds in
-// block order.
+// block order.  A wave loads all of its rows (4 consecutive values per lane
+// and group, one vector access) before it reduces the first, so the rows'
+// loads are in flight together; the per-row arithmetic and the row order of
+// the accumulations are fixed.
 constexpr int kHeadRowsPerWave = 8;
 constexpr int kHeadMaxGroups = 4;  // K <= 1024
 
+// four consecutive elements (float32 or bfloat16) starting at element i
+template <int T>
+__device__ __forceinline__ void ld4_t(const void* p, size_t i, float (&v)[4]) {
+    if (T == 0) {
+        const float4 q = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(p) + i);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const uint2 q = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(p) + i);
+        v[0] = __uint_as_float(q.x << 16); v[1] = __uint_as_float(q.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(q.y << 16); v[3] = __uint_as_float(q.y & 0xFFFF0000u);
+    }
+}
+template <int T>
+__device__ __forceinline__ void st4_t(void* p, size_t i, const float (&v)[4]) {
+    if (T == 0) {
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(p) + i) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        uint2 q;
+        q.x = (uint32_t)tr_f32_to_bf16(v[0]) | ((uint32_t)tr_f32_to_bf16(v[1]) << 16);
+        q.y = (uint32_t)tr_f32_to_bf16(v[2]) | ((uint32_t)tr_f32_to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(p) + i) = q;
+    }
+}
+
 template <int T>
 __global__ __launch_bounds__(256) void head_train_kernel(HeadTrainArgs a) {
+    constexpr int RW = kHeadRowsPerWave;
     __shared__ float s_w[4][kHeadMaxGroups * 256];
     __shared__ float s_b[4], s_l[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int groups = (a.K + 255) / 256;  // lanes own 4 columns per group; columns >= K are skipped
-    float accw[kHeadMaxGroups][4];
-    for (int gi = 0; gi < kHeadMaxGroups; gi++)
-        for (int e = 0; e < 4; e++) accw[gi][e] = 0.f;
+    // Loads are unconditional (clamped addresses) and out-of-range values are
+    // zeroed afterwards, so no load waits behind a branch.  K % 4 == 0: a
+    // lane's four columns are all in range or all out.
+    float accw[kHeadMaxGroups][4], w[kHeadMaxGroups][4];
+    _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++) {
+        const int k0 = gi * 256 + lane * 4;
+        _Pragma("unroll") for (int e = 0; e < 4; e++) accw[gi][e] = 0.f;
+        ld4_t<T>(a.W, min(k0, a.K - 4), w[gi]);
+        if (k0 >= a.K) _Pragma("unroll") for (int e = 0; e < 4; e++) w[gi][e] = 0.f;
+    }
     float accb = 0.f, accl = 0.f;
-    const int row0 = (blockIdx.x * 4 + wave) * kHeadRowsPerWave;
-    for (int rr = 0; rr < kHeadRowsPerWave; rr++) {
+    const int row0 = (blockIdx.x * 4 + wave) * RW;
+    float x[RW][kHeadMaxGroups][4];
+    _Pragma("unroll") for (int rr = 0; rr < RW; rr++) {
+        const int r = min(row0 + rr, a.m_pad - 1);
+        _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
+            ld4_t<T>(a.X, (size_t)r * a.ldx + min(gi * 256 + lane * 4, a.K - 4), x[rr][gi]);
+    }
+    _Pragma("unroll") for (int rr = 0; rr < RW; rr++)
+        _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
+            if (gi * 256 + lane * 4 >= a.K) _Pragma("unroll") for (int e = 0; e < 4; e++) x[rr][gi][e] = 0.f;
+    // (every array index below is a compile-time constant, so x, w and accw stay
+    // in registers; `groups` only masks whole unrolled iterations)
+    _Pragma("unroll") for (int rr = 0; rr < RW; rr++) {
         const int r = row0 + rr;
-        if (r >= a.m_pad) break;
-        float x[kHeadMaxGroups][4];
+        if (r >= a.m_pad) continue;  // uniform
         float part = 0.f;
-        for (int gi = 0; gi < groups; gi++)
-            for (int e = 0; e < 4; e++) {
-                const int k = gi * 256 + lane * 4 + e;
-                x[gi][e] = k < a.K ? ld_t<T>(a.X, (size_t)r * a.ldx + k) : 0.f;
-                if (k < a.K) part += x[gi][e] * ld_t<T>(a.W, k);
-            }
+        _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
+            if (gi < groups)
+                _Pragma("unroll") for (int e = 0; e < 4; e++)
+                    if (gi * 256 + lane * 4 + e < a.K) part += x[rr][gi][e] * w[gi][e];
         for (int s = 32; s >= 1; s >>= 1) part += __shfl_xor(part, s, 64);
         float dy = 0.f;
         if (r < a.n) {
@@ -77,17 +120,19 @@ __global__ __launch_bounds__(256) void head_train_kernel(HeadTrainArgs a) {
             accb += dy;
             if (a.y_out && lane == 0) a.y_out[r] = y;
         }
-        for (int gi = 0; gi < groups; gi++)
-            for (int e = 0; e < 4; e++) {
-                const int k = gi * 256 + lane * 4 + e;
-                if (k >= a.K) continue;
-                const float dlt = x[gi][e] > 0.f ? dy * ld_t<T>(a.W, k) : 0.f;
-                st_t<T>(a.delta, (size_t)r * a.ldx + k, dlt);
-                accw[gi][e] += x[gi][e] * dy;
+        _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++) {
+            const int k0 = gi * 256 + lane * 4;
+            if (gi >= groups || k0 >= a.K) continue;
+            float dl[4];
+            _Pragma("unroll") for (int e = 0; e < 4; e++) {
+                dl[e] = x[rr][gi][e] > 0.f ? dy * w[gi][e] : 0.f;
+                accw[gi][e] += x[rr][gi][e] * dy;
             }
+            st4_t<T>(a.delta, (size_t)r * a.ldx + k0, dl);
+        }
     }
-    for (int gi = 0; gi < kHeadMaxGroups; gi++)
-        for (int e = 0; e < 4; e++) s_w[wave][gi * 256 + lane * 4 + e] = accw[gi][e];
+    _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
+        _Pragma("unroll") for (int e = 0; e < 4; e++) s_w[wave][gi * 256 + lane * 4 + e] = accw[gi][e];
     if (lane == 0) { s_b[wave] = accb; s_l[wave] = accl; }
     __syncthreads();
     // the block's partial sums (output weights, bias, loss) into its row of
@@ -131,24 +176,40 @@ __global__ __launch_bounds__(1024) void column_sum_kernel(const float* part, int
 }
 
 // ------------------------------------------------------------- transpose
-// out[c][r] = in[r][c] for r < R, c < C through a 64 x 64 LDS tile; with
-// colpart, the block's column sums over rows < rows_sum go to row blockIdx.y
-// of colpart (row stride C), for column_sum_kernel.
+// out[c][r] = in[r][c] for r < R, c < C through a 64 x 64 LDS tile, four
+// consecutive elements per thread and access (16 x 16 threads); with colpart,
+// the block's column sums over rows < rows_sum go to row blockIdx.y of colpart
+// (row stride C), for column_sum_kernel.  ld_in and ld_out are multiples of 4.
 template <int T>
 __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
     __shared__ float tile[64][65];
     const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-    for (int i = ty; i < 64; i += 4) {
-        const int r = r0 + i, c = c0 + tx;
-        tile[i][tx] = (r < a.R && c < a.C) ? ld_t<T>(a.in, (size_t)r * a.ld_in + c) : 0.f;
+    const int tq = threadIdx.x & 15, tr = threadIdx.x >> 4;
+    for (int i = tr; i < 64; i += 16) {
+        const int r = r0 + i, c = c0 + 4 * tq;
+        float v[4];
+        if (r < a.R && c + 3 < a.C) {
+            ld4_t<T>(a.in, (size_t)r * a.ld_in + c, v);
+        } else {
+            _Pragma("unroll") for (int e = 0; e < 4; e++)
+                v[e] = (r < a.R && c + e < a.C) ? ld_t<T>(a.in, (size_t)r * a.ld_in + c + e) : 0.f;
+        }
+        _Pragma("unroll") for (int e = 0; e < 4; e++) tile[i][4 * tq + e] = v[e];
     }
     __syncthreads();
-    for (int i = ty; i < 64; i += 4) {
-        const int c = c0 + i, r = r0 + tx;
-        if (c < a.C && r < a.R) st_t<T>(a.out, (size_t)c * a.ld_out + r, tile[tx][i]);
+    for (int i = tr; i < 64; i += 16) {
+        const int c = c0 + i, r = r0 + 4 * tq;
+        float v[4];
+        _Pragma("unroll") for (int e = 0; e < 4; e++) v[e] = tile[4 * tq + e][i];
+        if (c < a.C && r + 3 < a.R) {
+            st4_t<T>(a.out, (size_t)c * a.ld_out + r, v);
+        } else if (c < a.C) {
+            _Pragma("unroll") for (int e = 0; e < 4; e++)
+                if (r + e < a.R) st_t<T>(a.out, (size_t)c * a.ld_out + r + e, v[e]);
+        }
     }
-    if (a.colpart && ty == 0) {
+    if (a.colpart && threadIdx.x < 64) {
+        const int tx = threadIdx.x;
         float s = 0.f;
         for (int i = 0; i < 64; i++)
             if (r0 + i < a.rows_sum) s += tile[i][tx];
@@ -166,8 +227,9 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
 // its states in order, so every partial is a fixed sequence of additions.
 // Per state a wave reads all of its cells' rows (distinct rows), then adds
 // and writes them back: one LDS round trip per state instead of one per cell.
-// (LDS float atomics measured several times slower than these plain
-// read-modify-writes.)  Pass 2 (scatter_reduce_kernel) sums the chunks'
+// (LDS float atomic adds measured several times slower than these plain
+// read-modify-writes, also without a returned value and with no two waves
+// sharing a word: 708 against 75 us per BF16 step.)  Pass 2 (scatter_reduce_kernel) sums the chunks'
 // partials in chunk order into the gradient rows.  No global atomics: the
 // gradient is bitwise repeatable.
 template <int DOM>
@@ -409,6 +471,37 @@ void launch_transpose(const TransposeArgs& a, int t, hipStream_t s) {
     if (t == 0) hipLaunchKernelGGL(transpose_kernel<0>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(transpose_kernel<1>, grid, dim3(256), 0, s, a);
     if (a.colpart) launch_column_sum(a.colpart, (a.rows_sum + 63) / 64, a.C, a.C, a.colsum, s);
+}
+
+// out[r][c] = sum over slices s < split of part[s * stride + r * ldp + c], added
+// in slice order (the fixed-order second pass of a split-K weight gradient).
+// cols, ldp and ldo are multiples of 4.
+__global__ __launch_bounds__(256) void splitk_sum_kernel(const float* __restrict__ part, int split, int64_t stride,
+                                                         int rows, int cols, int ldp, float* __restrict__ out, int ldo) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int c4 = cols / 4;
+    const int64_t total = (int64_t)rows * c4;
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int r = (int)(i / c4), c = (int)(i % c4) * 4;
+        const float* p = part + (size_t)r * ldp + c;
+        f4 v[8];
+        f4 acc = *reinterpret_cast<const f4*>(p);
+        for (int s0 = 1; s0 < split; s0 += 8) {  // up to eight slices' loads in flight, added in order
+            const int cnt = min(8, split - s0);
+            _Pragma("unroll") for (int u = 0; u < 8; u++)
+                if (u < cnt) v[u] = *reinterpret_cast<const f4*>(p + (size_t)(s0 + u) * stride);
+            _Pragma("unroll") for (int u = 0; u < 8; u++)
+                if (u < cnt) acc += v[u];
+        }
+        *reinterpret_cast<f4*>(out + (size_t)r * ldo + c) = acc;
+    }
+}
+
+void launch_splitk_sum(const float* part, int split, int64_t stride, int rows, int cols, int ldp, float* out, int ldo,
+                       hipStream_t s) {
+    const int64_t work = (int64_t)rows * (cols / 4);
+    const int blocks = (int)std::min<int64_t>(2048, (work + 255) / 256);
+    hipLaunchKernelGGL(splitk_sum_kernel, dim3(blocks), dim3(256), 0, s, part, split, stride, rows, cols, ldp, out, ldo);
 }
 
 void launch_column_sum(const float* part, int rows, int cols, int ld, float* out, hipStream_t s) {

@@ -51,6 +51,9 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 bool launch_head_train(const HeadTrainArgs& a, int t, hipStream_t s);
 int head_train_blocks(int m_pad);
 void launch_column_sum(const float* part, int rows, int cols, int ld, float* out, hipStream_t s);
+// Fixed-order sum of `split` partial matrices (split-K weight gradients).
+void launch_splitk_sum(const float* part, int split, int64_t stride, int rows, int cols, int ldp, float* out, int ldo,
+                       hipStream_t s);
 void launch_transpose(const TransposeArgs& a, int t, hipStream_t s);
 // Layer-1 weight and bias gradients (transpose of the gather-sum), in a fixed
 // summation order: bitwise repeatable.

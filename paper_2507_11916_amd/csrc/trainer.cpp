@@ -25,6 +25,7 @@ namespace hb {
 namespace {
 
 constexpr int kScatterChunks = 32;  // state chunks of the layer-1 scatter (its blocks: chunks x N1 / 64)
+constexpr int kSplitMax = 8;       // K slices of a split-K weight gradient
 
 struct TLayer {
     int K, N, K_pad, N_pad;
@@ -57,6 +58,8 @@ struct hb_trainer {
     int dom = 1, trows = 256;                    // trows: gathered table rows (cube: 48 x 6, centres folded)
     float* l1_bias_work = nullptr;               // cube: bias + the six centre rows (the gather's bias)
     float* partial = nullptr;                    // layer-1 scatter: per-chunk partial sums
+    float* wsplit = nullptr;                     // split-K weight-gradient partials (BF16 training)
+    int64_t wsplit_elems = 0;
     float* head_part = nullptr;                  // output layer: per-block partial gradients and loss
     float* colpart = nullptr;                    // bias gradients: per-row-block column sums
     hb::AdamTensor* d_adam = nullptr;            // every parameter tensor's Adam descriptor (device)
@@ -129,14 +132,36 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
     g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.a_scale = g.r_scale = g.out_inv_scale = 1.f;
     g.relu = relu;
-    // 128x256 or 64x128.  Weight gradients (K, the batch, far longer than M and
-    // N): FP32 takes the one-wave 32x32 tile (8x the tiles of 64x128 on a 1000 x
-    // 1000 output; 12% faster per FP32 step), BF16 the 64x128 tile with a
+    // Forward and input-gradient products: the 8-wave 256x128 ring tile, or
+    // 64x128 for small batches.  Weight gradients (K, the batch, far longer than
+    // M and N): FP32 takes the one-wave 32x32 tile (8x the tiles of 64x128 on a
+    // 1000 x 1000 output; 12% faster per FP32 step), BF16 the 64x128 tile with a
     // 4-stage LDS ring (more of the long K in flight; 8% faster per BF16 step).
     const bool wgrad = K >= 4 * std::max(M, N);
-    g.tile = wgrad ? (tr->t == 0 ? 4 : 8) : (N % 256 == 0 && M >= 2048) ? 1 : 2;
+    g.tile = wgrad ? (tr->t == 0 ? 4 : 8) : (N % 128 == 0 && M >= 2048) ? 14 : 2;
+    // BF16 weight gradients of wide layers: split-K on the 256x128 tile (the
+    // 1000 x 1000 output alone is 32 such tiles), partial products in wsplit,
+    // then summed in slice order (deterministic).
+    int split = 0;
+    if (wgrad && tr->t == 1 && tr->wsplit && M % 256 == 0 && N % 128 == 0 && out_type == 0 && !R && !Mk &&
+        (int64_t)M * N <= tr->wsplit_elems / kSplitMax) {
+        for (int sp = kSplitMax; sp >= 2; sp /= 2)
+            if (K % (sp * 64) == 0 && (M / 256) * (N / 128) * sp <= 512) { split = sp; break; }
+    }
+    if (split) {
+        g.tile = 14;
+        g.split = split;
+        g.C = tr->wsplit;
+        g.ldc = N;
+        g.c_split = (int64_t)M * N;
+        g.bias = nullptr;
+    }
     if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM for this precision");
     HB_HIP(hipGetLastError());
+    if (split) {
+        launch_splitk_sum(tr->wsplit, split, (int64_t)M * N, M, N, N, static_cast<float*>(C), ldc, s);
+        HB_HIP(hipGetLastError());
+    }
     return HB_OK;
 }
 
@@ -343,7 +368,7 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     T->N1_pad = pad(T->N1);
     T->H = spec.dims.back();
     T->H_pad = pad(T->H);
-    T->M_pad = (int)round_up(o.max_batch, 128);
+    T->M_pad = (int)round_up(o.max_batch, 256);  // whole 256-row GEMM tiles
     int wmax = T->N1_pad;
     for (int d : spec.dims) wmax = std::max(wmax, pad(d));
     T->W_pad = wmax;
@@ -431,6 +456,10 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
         return st;
     if ((st = dalloc_t(T, (size_t)(T->M_pad / 64 + 1) * T->W_pad, &T->colpart)) != HB_OK) return st;
     if ((st = dalloc_t(T, (size_t)kScatterChunks * (T->trows + 1) * T->N1_pad, &T->partial)) != HB_OK) return st;
+    if (T->t == 1) {
+        T->wsplit_elems = (int64_t)kSplitMax * round_up(T->W_pad, 256) * T->W_pad;
+        if ((st = dalloc_t(T, (size_t)T->wsplit_elems, &T->wsplit)) != HB_OK) return st;
+    }
     if ((st = upload_adam_table(T)) != HB_OK) return st;
     *out = tr.release();
     return HB_OK;
