@@ -105,6 +105,11 @@ def main():
     ap.add_argument("--train-steps", type=int, default=0,
                     help="instead of the benchmark line: this many training steps of the 15-puzzle network (BF16, "
                          "batch 8192), for a profiler's kernel breakdown")
+    ap.add_argument("--config5", action="store_true",
+                    help="instead of the benchmark line: the learned 15-puzzle heuristic at full scale (10^7 "
+                         "training states labelled by the 7-8 additive PDB minus Manhattan distance, BF16 weights, "
+                         "FP32 master, Adam, batch 8192), its over-estimate rate on held-out states and Batch IDA* "
+                         "with it against IDA* with Manhattan distance and with the PDB; prints its own JSON line")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -173,6 +178,9 @@ def main():
 
     if args.size_sweep:
         size_sweep(args, hb, synth, netcfg, torch, d_packed, B, timed_loop, tmp)
+        return
+    if args.config5:
+        print(json.dumps(config5(hb, synth, torch, tmp)))
         return
     if args.train_steps > 0:
         TB = 8192
@@ -518,6 +526,127 @@ def main():
         "training": training,
     }
     print(json.dumps(line))
+
+
+def config5(hb, synth, torch, tmp, n_train=10_000_000, epochs=6, n_starts=20, start_len=56, workers=None,
+            train_seed=5005, delta_seed=6006, held_seed=7007, progress=None):
+    """The configuration's learned heuristic at its stated scale.
+
+    Training states: n_train random walks of 0-200 moves from the goal (seed
+    train_seed), labelled by the 7-8 additive PDB minus Manhattan distance (the
+    paper's sliding-tile model learns what a PDB adds to Manhattan distance).
+    The config-2 network (256-1000-1000-2 residual blocks-1) is trained with the
+    library's kernels: BF16 operands, FP32 master weights, Adam, batch 8192,
+    `epochs` passes of random batches.  Served as MD + max(0, floor(y - delta))
+    with delta set on a held-out set so that h exceeds the PDB label on at most
+    0.1% of it; the over-estimate rate is then measured on a second held-out set.
+    Search: Batch IDA* with the learned heuristic against IDA* with Manhattan
+    distance (optimal costs) and with the PDB itself, on n_starts walks of
+    start_len moves."""
+    say = progress or log
+    workers = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    out = {"workload": f"15-puzzle, residual MLP 256-1000-1000-2x(1000,1000)-1 trained on {n_train} states "
+                       "(0-200 move walks) labelled by the 7-8 additive PDB minus Manhattan distance; BF16 weights, "
+                       "FP32 master, Adam, batch 8192",
+           "workers": workers}
+    t0 = time.time()
+    pdb = hb.Pdb(groups=[range(1, 8), range(8, 16)])
+    out["pdb_build_s"] = time.time() - t0
+    say(f"[config5] 7-8 PDB built in {out['pdb_build_s']:.1f} s")
+
+    def states_of(seed, count):
+        from concurrent.futures import ThreadPoolExecutor
+        mv = synth.stp_walk_moves_parallel(4, synth.throughput_seeds(count, seed), 0, 201, workers)
+        st = np.empty((count, 16), dtype=np.uint8)
+        step = (count + workers - 1) // workers
+        with ThreadPoolExecutor(workers) as ex:  # the library call releases the interpreter lock
+            def job(i):
+                st[i:i + step] = hb.hb_apply_moves(hb.HB_STP4, mv[i:i + step])
+            list(ex.map(job, range(0, count, step)))
+        md = hb.hb_manhattan(hb.HB_STP4, st)
+        return st, md, (pdb.lookup(st) - md).astype(np.float32)
+
+    t0 = time.time()
+    st, md, lab = states_of(train_seed, n_train)
+    out["data_s"] = time.time() - t0
+    out["label_mean"] = float(lab.mean())
+    say(f"[config5] {n_train} training states and labels in {out['data_s']:.1f} s (mean PDB - MD {lab.mean():.2f})")
+    path = os.path.join(tmp, "config5.hbw")
+    synth.write_weights(path, "stp4_res", seed=21, head_bias=float(lab.mean()), scale=0.5)
+    TB = 8192
+    tr = hb.Trainer(path, prec=hb.HB_BF16, max_batch=TB, lr=1e-3)
+    d_st = torch.from_numpy(hb.hb_encode(hb.HB_STP4, st)).cuda()
+    d_lab = torch.from_numpy(lab).cuda()
+    del st
+    g = torch.Generator(device="cuda").manual_seed(77)
+    steps = epochs * n_train // TB
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(steps):
+        idx = torch.randint(0, n_train, (TB,), device="cuda", generator=g)
+        loss = tr.step(d_st[idx].contiguous(), d_lab[idx].contiguous(), want_loss=(i % 200 == 0 or i == steps - 1))
+        if loss is not None:
+            losses.append((i, loss))
+    torch.cuda.synchronize()
+    out["train"] = {"steps": steps, "epochs": epochs, "batch": TB, "wall_s": time.time() - t0,
+                    "loss_first": losses[0][1], "loss_last": losses[-1][1], "loss_curve": losses}
+    say(f"[config5] {steps} steps in {out['train']['wall_s']:.1f} s, loss {losses[0][1]:.3f} -> {losses[-1][1]:.3f}")
+    trained = os.path.join(tmp, "config5_trained.hbw")
+    tr.save(trained)
+    tr.close()
+    del d_st, d_lab
+
+    def raw(model, s):
+        d_h = torch.zeros(len(s), dtype=torch.int32, device="cuda")
+        d_y = torch.zeros(len(s), dtype=torch.float32, device="cuda")
+        model.eval_batch(torch.from_numpy(hb.hb_encode(hb.HB_STP4, s)).cuda(), d_h, d_y)
+        torch.cuda.synchronize()
+        return d_h.cpu().numpy(), d_y.cpu().numpy().astype(np.float64)
+
+    m = hb.Model(trained, prec=hb.HB_BF16, max_batch=65536)
+    sa, mda, laba = states_of(delta_seed, 1 << 20)
+    _, ya = raw(m, sa)
+    m.close()
+    delta = max(0.0, float(np.quantile(ya - laba - 1.0, 0.999)) + 1e-3)  # floor(y - delta) <= label on 99.9%
+    served = hb.Model(trained, prec=hb.HB_BF16, combine_md=3, offset=delta, max_batch=65536)
+    sb, mdb, labb = states_of(held_seed, 1 << 20)
+    hbv, yb = raw(served, sb)
+    pdbv = mdb + labb
+    out["held_out"] = {"states": int(len(sb)), "delta": delta,
+                       "over_estimate_rate_vs_pdb": float(np.mean(hbv > pdbv)),
+                       "rmse_y_vs_label": float(np.sqrt(np.mean((yb - labb) ** 2))),
+                       "mean_h": float(hbv.mean()), "mean_md": float(mdb.mean()), "mean_pdb": float(pdbv.mean()),
+                       "h_below_md": int(np.sum(hbv < mdb))}
+    say(f"[config5] held-out: delta {delta:.3f}, h > PDB on {100 * out['held_out']['over_estimate_rate_vs_pdb']:.3f}%, "
+        f"mean h {hbv.mean():.2f} (MD {mdb.mean():.2f}, PDB {pdbv.mean():.2f})")
+
+    starts = synth.stp_walks(4, synth.config_seeds(5, n_starts), lengths=start_len)
+    rows = []
+    p_nn = hb.default_params(batch_size=4000, work_num=32, node_limit=50_000_000, time_limit_s=120.0)
+    p_cl = hb.default_params(batch_size=4000, work_num=32, node_limit=2_000_000_000, time_limit_s=300.0)
+    threads = workers
+    for i, s0 in enumerate(starts):
+        r_nn = hb.cbdfs_solve(hb.HB_STP4, s0, model=served, combine=hb.HB_H_NN, threads=threads, params=p_nn,
+                              raise_on_error=False)
+        r_md = hb.cbdfs_solve(hb.HB_STP4, s0, combine=hb.HB_H_CLASSIC, classic=hb.HB_CLASSIC_MD, threads=threads,
+                              params=p_cl, raise_on_error=False)
+        r_pdb = hb.cbdfs_solve(hb.HB_STP4, s0, combine=hb.HB_H_CLASSIC, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                               threads=threads, params=p_cl, raise_on_error=False)
+        rows.append({"start": i, "cost_md": r_md["cost"], "cost_learned": r_nn["cost"], "cost_pdb": r_pdb["cost"],
+                     "status": [r_nn["status"], r_md["status"], r_pdb["status"]],
+                     "expanded_learned": r_nn["expanded"], "expanded_md": r_md["expanded"],
+                     "expanded_pdb": r_pdb["expanded"], "wall_learned_s": r_nn["wall_s"]})
+        say(f"[config5] start {i}: cost MD {r_md['cost']} learned {r_nn['cost']} PDB {r_pdb['cost']}; expanded "
+            f"learned {r_nn['expanded']} MD {r_md['expanded']} PDB {r_pdb['expanded']}")
+    served.close()
+    pdb.close()
+    exp = {k: int(sum(r[f"expanded_{k}"] for r in rows)) for k in ("learned", "md", "pdb")}
+    out["search"] = {"starts": n_starts, "walk_moves": start_len, "expanded": exp,
+                     "learned_vs_md_ratio": exp["md"] / max(1, exp["learned"]),
+                     "cost_differs": [r["start"] for r in rows if r["cost_learned"] != r["cost_md"]],
+                     "all_solved": all(st_ == [0, 0, 0] for st_ in (r["status"] for r in rows)), "per_start": rows}
+    return out
 
 
 def puzzle8_states():

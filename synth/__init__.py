@@ -120,6 +120,79 @@ def stp_walks(n: int, seeds, lengths=None, length_base=None, length_span=None) -
     return states
 
 
+def stp_walk_moves(n: int, seeds, lengths=None, length_base=None, length_span=None) -> np.ndarray:
+    """The moves of the walks stp_walks takes (same streams, same draws), as
+    int8 [count, max length] blank moves (0 up, 1 left, 2 right, 3 down), each
+    row ended by -1 where the walk is shorter.  Only the blank's cell is
+    tracked, so this is fast for millions of walks; applying the rows to the
+    goal gives stp_walks' states.
+    """
+    seeds = np.asarray(list(seeds) if not isinstance(seeds, np.ndarray) else seeds, dtype=np.uint64)
+    cnt = seeds.shape[0]
+    st = seeds.copy()
+    if lengths is None:
+        st, r = _sm64_vec(st)
+        lengths = (np.uint64(length_base) + r % np.uint64(length_span)).astype(np.int64)
+    lengths = np.asarray(lengths, dtype=np.int64)
+    if lengths.ndim == 0:
+        lengths = np.full(cnt, int(lengths), dtype=np.int64)
+    L = int(lengths.max(initial=0))
+    # allowed[cell, prev + 1] lists the moves that stay on the board and do not
+    # undo prev, in move order; kcount holds their number
+    allowed = np.zeros((n * n, 5, 4), dtype=np.int8)
+    kcount = np.zeros((n * n, 5), dtype=np.uint64)
+    for cell in range(n * n):
+        br, bc = divmod(cell, n)
+        on = [br > 0, bc > 0, bc < n - 1, br < n - 1]
+        for prev in range(-1, 4):
+            ms = [m for m in range(4) if on[m] and m != 3 - prev]
+            allowed[cell, prev + 1, :len(ms)] = ms
+            kcount[cell, prev + 1] = len(ms)
+    allowed_f = allowed.reshape(-1, 4)
+    kcount_f = kcount.reshape(-1)
+    dcell = np.array([-n, -1, 1, n], dtype=np.int16)
+    out = np.full((cnt, max(L, 1)), -1, dtype=np.int8)
+    # blocks of walks small enough to stay in cache; a finished walk's stream,
+    # blank and previous move are never read again, so they are not masked
+    for c0 in range(0, cnt, 1 << 16):
+        c1 = min(cnt, c0 + (1 << 16))
+        sc = st[c0:c1].copy()
+        lc = lengths[c0:c1]
+        key = np.zeros(c1 - c0, dtype=np.int64)  # blank * 5 + prev + 1
+        blank = np.zeros(c1 - c0, dtype=np.int64)
+        for step in range(int(lc.max(initial=0))):
+            sc, r = _sm64_vec(sc)
+            pick = (r % kcount_f[key]).astype(np.int64)
+            move = allowed_f[key, pick]
+            out[c0:c1, step] = np.where(step < lc, move, -1)
+            blank += dcell[move]
+            key = blank * 5 + move + 1
+    return out
+
+
+def _walk_moves_job(args):
+    n, seeds, length_base, length_span = args
+    return stp_walk_moves(n, seeds, length_base=length_base, length_span=length_span)
+
+
+def stp_walk_moves_parallel(n: int, seeds, length_base: int, length_span: int, workers: int) -> np.ndarray:
+    """stp_walk_moves split over `workers` fresh processes (spawned, so a
+    parent that has initialised a GPU is not forked); same rows."""
+    import multiprocessing as mp
+    seeds = np.asarray(seeds, dtype=np.uint64)
+    if workers <= 1 or len(seeds) < 65536:
+        return stp_walk_moves(n, seeds, length_base=length_base, length_span=length_span)
+    chunks = np.array_split(seeds, workers * 2)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        parts = pool.map(_walk_moves_job, [(n, c, length_base, length_span) for c in chunks])
+    out = np.full((len(seeds), max(p.shape[1] for p in parts)), -1, dtype=np.int8)
+    r0 = 0
+    for part in parts:
+        out[r0:r0 + part.shape[0], :part.shape[1]] = part
+        r0 += part.shape[0]
+    return out
+
+
 # --------------------------------------------------------------- Rubik's cube
 def rc_walk_moves(seeds, lengths=None, length_base=None, length_span=None) -> list:
     """Random move sequences under canonical pruning, one stream per walk.

@@ -289,3 +289,19 @@ def test_eight_tile_group_of_the_paper_split():
     """Tiles 8-15, the second half of the paper's 7-8 additive PDB (518,918,400
     placements: index arithmetic at the library's largest group size)."""
     _big_group_pins(list(range(8, 16)), range(8, 14), 8)
+
+
+def test_walk_moves_reproduce_the_walks():
+    """synth.stp_walk_moves (blank-only tracking, used to build millions of
+    training states) takes exactly stp_walks' walks: applying its rows to the
+    goal with the library gives the same states, serially and in parallel."""
+    seeds = synth.throughput_seeds(3000, 31337)
+    ref = synth.stp_walks(4, seeds, length_base=0, length_span=201)
+    mv = synth.stp_walk_moves(4, seeds, length_base=0, length_span=201)
+    assert mv.shape[1] == 200 and np.all((mv >= -1) & (mv <= 3))
+    np.testing.assert_array_equal(hb.hb_apply_moves(hb.HB_STP4, mv), ref)
+    ref3 = synth.stp_walks(3, seeds[:500], lengths=40)
+    np.testing.assert_array_equal(hb.hb_apply_moves(hb.HB_STP3, synth.stp_walk_moves(3, seeds[:500], lengths=40)), ref3)
+    big = synth.throughput_seeds(70000, 4)
+    np.testing.assert_array_equal(synth.stp_walk_moves_parallel(4, big, 0, 201, 2),
+                                  synth.stp_walk_moves(4, big, length_base=0, length_span=201))
