@@ -110,6 +110,9 @@ def main():
                          "training states labelled by the 7-8 additive PDB minus Manhattan distance, BF16 weights, "
                          "FP32 master, Adam, batch 8192), its over-estimate rate on held-out states and Batch IDA* "
                          "with it against IDA* with Manhattan distance and with the PDB; prints its own JSON line")
+    ap.add_argument("--table2", action="store_true",
+                    help="instead of the benchmark line: only the real-valued cube leg (trained regression net, "
+                         "Batch IDA* against Batch BTS); prints its own JSON line")
     ap.add_argument("--library-gemm", action="store_true",
                     help="instead of the benchmark line: time the vendor GEMM (torch.matmul FP32/BF16, "
                          "torch._scaled_mm FP8) on one layer's shape (M = batch, K = N = 1024) for comparison")
@@ -181,6 +184,9 @@ def main():
         return
     if args.config5:
         print(json.dumps(config5(hb, synth, torch, tmp)))
+        return
+    if args.table2:
+        print(json.dumps(table2_cube(hb, synth, torch, tmp, min(32, max(4, len(os.sched_getaffinity(0)))))))
         return
     if args.train_steps > 0:
         TB = 8192
@@ -396,30 +402,10 @@ def main():
         pdb.close()
         search["cube"] = cube
 
-        # real-valued regression heuristic (the paper's regression experiment):
-        # the 8-puzzle network's y - 2.2 used without rounding, Batch IDA* against
-        # Batch BTS on ten starts (node limit 2M each)
-        rpath = os.path.join(tmp, "stp3_small.hbw")
-        synth.write_weights(rpath, "stp3_small", **netcfg.DEFAULTS["stp3_small"])
-        rm = hb.Model(rpath, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=2.2, max_batch=4096)
-        real = {"workload": "8-puzzle, regression net 81-128-128-1, h = max(0, y - 2.2) unrounded, 10 starts "
-                            "(30-60 move walks), 8 threads, batch 64, node limit 500K per start"}
-        for algo_name, algo in (("ida", hb.HB_IDA), ("bts", hb.HB_BTS)):
-            tot = {"iterations": 0, "expanded": 0, "wall_s": 0.0, "solved": 0}
-            for s0 in synth.stp3_instances(10):
-                p = hb.default_params(batch_size=64, work_num=4, node_limit=500_000, time_limit_s=5.0,
-                                      bts_b0=1000)
-                r = hb.cbdfs_solve(hb.HB_STP3, s0, model=rm, combine=hb.HB_H_NN_REAL, algo=algo, threads=8,
-                                   params=p, raise_on_error=False)
-                tot["iterations"] += len(r["iters"])
-                tot["expanded"] += r["expanded"]
-                tot["wall_s"] += r["wall_s"]
-                tot["solved"] += int(r["status"] == hb.HB_OK)
-            real[algo_name] = tot
-            log(f"[bench] real-valued h, {algo_name}: {tot['iterations']} iterations, {tot['expanded']} expanded, "
-                f"{tot['wall_s']:.2f} s, {tot['solved']}/10 solved")
-        rm.close()
-        search["real_valued_8puzzle"] = real
+        # real-valued regression heuristic on the cube (the paper's regression
+        # experiment, Table 2): a trained regression net used as y - 2.2 without
+        # rounding, Batch IDA* against Batch BTS on walks of 8 and 9 turns
+        search["real_valued_cube"] = table2_cube(hb, synth, torch, tmp, threads)
 
     # training step of the learned heuristic: same network shape, BF16 operands,
     # FP32 master weights and Adam, batch 8192 (labels: walk lengths)
@@ -646,6 +632,84 @@ def config5(hb, synth, torch, tmp, n_train=10_000_000, epochs=6, n_starts=20, st
                      "learned_vs_md_ratio": exp["md"] / max(1, exp["learned"]),
                      "cost_differs": [r["start"] for r in rows if r["cost_learned"] != r["cost_md"]],
                      "all_solved": all(st_ == [0, 0, 0] for st_ in (r["status"] for r in rows)), "per_start": rows}
+    return out
+
+
+def table2_cube(hb, synth, torch, tmp, threads, n_train=1 << 19, epochs=4, lengths=(8, 8, 8, 9, 9),
+                ida_limit=3_000_000, progress=None):
+    """Batch IDA* against Batch BTS with a real-valued learned heuristic (the
+    paper's regression experiment).  A cube regression network (324-1000-1000-2
+    residual blocks-1) is trained by the library's kernels on the 8-corner PDB
+    value of 2^19 states from walks of 0-20 turns (BF16, FP32 master, Adam,
+    batch 8192), then served in FP32 as h = max(0, y - 2.2) unrounded.  Each
+    start is searched by Batch IDA* (stopped after ida_limit expansions) and by
+    Batch BTS (c1 = 2, c2 = 8, first budget 10,000), batch 2000, work_num 32.
+    With a real-valued h nearly every node has its own f, so IDA*'s bound grows
+    by tiny steps and it re-expands the tree once per step; BTS's budgets grow
+    geometrically."""
+    say = progress or log
+    t0 = time.time()
+    pdb = hb.Pdb(8)
+    mv = synth.rc_walk_moves_array(synth.throughput_seeds(n_train, 8118), length_base=0, length_span=21)
+    st = hb.hb_apply_moves(hb.HB_RUBIK3, mv)
+    lab = pdb.lookup(st).astype(np.float32)
+    pdb.close()
+    spec = dict(domain=2, n_in=324, dims=[1000, 1000], n_res=2, n_out=1, head_kind=0)
+    path = os.path.join(tmp, "rc_reg.hbw")
+    synth.write_weights(path, "rc_cls", seed=44, head_bias=float(lab.mean()), scale=0.5, spec=spec)
+    TB = 8192
+    tr = hb.Trainer(path, prec=hb.HB_BF16, max_batch=TB, lr=1e-3)
+    d_st = torch.from_numpy(hb.hb_encode(hb.HB_RUBIK3, st)).cuda()
+    d_lab = torch.from_numpy(lab).cuda()
+    g = torch.Generator(device="cuda").manual_seed(78)
+    steps = epochs * n_train // TB
+    l0 = l1 = None
+    for i in range(steps):
+        idx = torch.randint(0, n_train, (TB,), device="cuda", generator=g)
+        loss = tr.step(d_st[idx].contiguous(), d_lab[idx].contiguous(), want_loss=(i == 0 or i == steps - 1))
+        if i == 0:
+            l0 = loss
+        if i == steps - 1:
+            l1 = loss
+    trained = os.path.join(tmp, "rc_reg_trained.hbw")
+    tr.save(trained)
+    tr.close()
+    del d_st, d_lab
+    out = {"workload": "cube, regression net 324-1000-1000-2x(1000,1000)-1 trained on the 8-corner PDB of 2^19 "
+                       "walk states, FP32, h = max(0, y - 2.2) unrounded; starts: walks of 8, 8, 8, 9, 9 turns; "
+                       f"batch 2000, work_num 32, {threads} threads; IDA* stopped after {ida_limit} expansions "
+                       "(iterations not capped)",
+           "train": {"steps": steps, "loss_first": l0, "loss_last": l1, "setup_s": time.time() - t0}}
+    say(f"[bench] cube regression net: {steps} training steps, loss {l0:.3f} -> {l1:.3f}")
+    m = hb.Model(trained, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=2.2, max_batch=4000)
+    starts = [hb.hb_apply_moves(hb.HB_RUBIK3, synth.rc_walk_moves_array([8800 + i], lengths=L))[0]
+              for i, L in enumerate(lengths)]
+    rows = []
+    for i, (L, s0) in enumerate(zip(lengths, starts)):
+        row = {"turns": L}
+        for name, algo, limit in (("ida", hb.HB_IDA, ida_limit), ("bts", hb.HB_BTS, 0)):
+            p = hb.default_params(batch_size=2000, work_num=32, node_limit=limit, time_limit_s=60.0,
+                                  max_iters=1_000_000)
+            r = hb.cbdfs_solve(hb.HB_RUBIK3, s0, model=m, combine=hb.HB_H_NN_REAL, classic=hb.HB_CLASSIC_ZERO,
+                               algo=algo, threads=threads, params=p, raise_on_error=False)
+            if r["status"] not in (hb.HB_OK, hb.HB_E_BUDGET):
+                raise RuntimeError(f"cube real-valued search: status {r['status']}: {r['error']}")
+            row[name] = {"solved": r["status"] == hb.HB_OK, "cost": r["cost"], "iterations": len(r["iters"]),
+                         "expanded": r["expanded"], "generated": r["generated"], "wall_s": r["wall_s"],
+                         "last_bound": r["iters"][-1]["bound_real"] if r["iters"] else None}
+        rows.append(row)
+        say(f"[bench] real-valued cube start {i} ({L} turns): IDA* {'solved' if row['ida']['solved'] else 'stopped'} "
+            f"after {row['ida']['iterations']} iterations, {row['ida']['expanded']} expanded, "
+            f"{row['ida']['wall_s']:.2f} s; BTS {'solved' if row['bts']['solved'] else 'stopped'} "
+            f"(cost {row['bts']['cost']}) after {row['bts']['iterations']} iterations, {row['bts']['expanded']} "
+            f"expanded, {row['bts']['wall_s']:.2f} s")
+    m.close()
+    out["starts"] = rows
+    for name in ("ida", "bts"):
+        out[name] = {"solved": sum(r[name]["solved"] for r in rows),
+                     "expanded": int(sum(r[name]["expanded"] for r in rows)),
+                     "iterations": int(sum(r[name]["iterations"] for r in rows)),
+                     "wall_s": float(sum(r[name]["wall_s"] for r in rows))}
     return out
 
 
