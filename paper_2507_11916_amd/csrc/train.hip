@@ -223,8 +223,10 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
 // Pass 1 (scatter_partial_kernel): a block of NW waves (4; 8 for the cube's
 // 48 cells) owns 64 columns and one chunk of states; its LDS holds every table
 // row's 64 partial sums.  Wave w owns the cells p = w, w + NW, ... (so the rows
-// p*S .. p*S + S - 1), and wave 0 also the bias row: no two waves touch one LDS word, and each wave adds
-// its states in order, so every partial is a fixed sequence of additions.
+// p*S .. p*S + S - 1): no two waves touch one LDS word, and each wave adds
+// its states in order, so every partial is a fixed sequence of additions; the
+// bias partial (every state) is summed in a register, in order, and wave 0
+// writes it.
 // Per state a wave reads all of its cells' rows (distinct rows), then adds
 // and writes them back: one LDS round trip per state instead of one per cell.
 // (LDS float atomic adds measured several times slower than these plain
@@ -269,29 +271,33 @@ struct ScatterBatch {
     // add the batch's states, in order, into this wave's rows; recs holds the
     // records of the states from rb on
     __device__ __forceinline__ void add(float* acc, const uint64_t* recs, int rb, int b, int b1, int wave,
-                                        int lane) const {
+                                        int lane, float& bsum) const {
         using D = TrCells<DOM>;
         constexpr int ROWS = D::P * D::S;
-        constexpr int CW = (D::P + D::NW - 1) / D::NW;  // cells per wave (the last waves may own one fewer)
+        constexpr int CW = (D::P + D::NW - 1) / D::NW;  // cells per wave
+        constexpr bool RAGGED = D::P % D::NW != 0;      // the last waves own one cell fewer
         // the batch's records first (one LDS round trip), then one round trip per state
         uint64_t wr[U][D::W];
         _Pragma("unroll") for (int u = 0; u < U; u++)
             _Pragma("unroll") for (int i = 0; i < D::W; i++)
                 wr[u][i] = recs[(size_t)(min(b + u, b1 - 1) - rb) * D::W + i];
         _Pragma("unroll") for (int u = 0; u < U; u++) {
-            if (b + u < b1) {
+            if (b + u < b1) {  // uniform
                 const uint64_t w0 = wr[u][0], w1 = wr[u][D::W > 1 ? 1 : 0], w2 = wr[u][D::W > 2 ? 2 : 0];
-                int row[CW + 1];
-                float cur[CW + 1];
+                // No branches around the LDS accesses: a cell a wave does not
+                // own (only when P is not a multiple of the wave count) goes to
+                // that wave's own spare row.
+                int row[CW];
+                float cur[CW];
                 _Pragma("unroll") for (int j = 0; j < CW; j++) {
                     const int p = wave + D::NW * j;
-                    row[j] = p < D::P ? (p * D::S + D::sym(w0, w1, w2, p)) * 64 + lane : -1;
+                    const bool own = !RAGGED || p < D::P;
+                    row[j] = (own ? p * D::S + D::sym(w0, w1, w2, own ? p : 0) : ROWS + wave) * 64 + lane;
                 }
-                row[CW] = wave == 0 ? ROWS * 64 + lane : -1;  // the bias row
                 const float x = __uint_as_float(T == 0 ? v[u] : v[u] << 16);
-                _Pragma("unroll") for (int j = 0; j <= CW; j++) cur[j] = row[j] >= 0 ? acc[row[j]] : 0.f;
-                _Pragma("unroll") for (int j = 0; j <= CW; j++)
-                    if (row[j] >= 0) acc[row[j]] = cur[j] + x;
+                _Pragma("unroll") for (int j = 0; j < CW; j++) cur[j] = acc[row[j]];
+                _Pragma("unroll") for (int j = 0; j < CW; j++) acc[row[j]] = cur[j] + x;
+                bsum += x;  // the bias gradient: every state, in order
             }
         }
     }
@@ -299,9 +305,16 @@ struct ScatterBatch {
 
 constexpr int kScatterStage = 256;  // states whose packed records are staged in LDS at a time
 
+// LDS rows of a scatter block: the table's rows, plus one spare row per wave
+// when the cells do not divide evenly over the waves.
+template <int DOM>
+constexpr int scatter_lds_rows() {
+    return TrCells<DOM>::P * TrCells<DOM>::S + (TrCells<DOM>::P % TrCells<DOM>::NW ? TrCells<DOM>::NW : 0);
+}
+
 template <int DOM>
 constexpr size_t scatter_lds_bytes() {
-    return (size_t)(TrCells<DOM>::P * TrCells<DOM>::S + 1) * 64 * sizeof(float) +
+    return (size_t)scatter_lds_rows<DOM>() * 64 * sizeof(float) +
            (size_t)kScatterStage * TrCells<DOM>::W * sizeof(uint64_t);
 }
 
@@ -310,11 +323,13 @@ __global__ __launch_bounds__(512) void scatter_partial_kernel(ScatterArgs a) {
     using D = TrCells<DOM>;
     constexpr int ROWS = D::P * D::S;
     constexpr int U = D::W == 1 ? 32 : 16;  // states per batch; the next batch loads while one is added
-    extern __shared__ float acc[];          // [(ROWS + 1) * 64], then the staged records
-    uint64_t* recs = reinterpret_cast<uint64_t*>(acc + (ROWS + 1) * 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int LROWS = scatter_lds_rows<DOM>();
+    extern __shared__ float acc[];          // [LROWS * 64], then the staged records
+    uint64_t* recs = reinterpret_cast<uint64_t*>(acc + LROWS * 64);
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = blockIdx.x * 64 + lane;
-    for (int i = threadIdx.x; i < (ROWS + 1) * 64; i += 64 * D::NW) acc[i] = 0.f;
+    for (int i = threadIdx.x; i < LROWS * 64; i += 64 * D::NW) acc[i] = 0.f;
+    float bsum = 0.f;
     const uint64_t* packed = reinterpret_cast<const uint64_t*>(a.packed);
     const int b0 = blockIdx.y * a.chunk, b1 = min(b0 + a.chunk, a.n);
     for (int sb = b0; sb < b1; sb += kScatterStage) {
@@ -325,14 +340,15 @@ __global__ __launch_bounds__(512) void scatter_partial_kernel(ScatterArgs a) {
         x.load(a, sb, sb1, c);
         for (int b = sb; b < sb1; b += 2 * U) {
             y.load(a, b + U, sb1, c);
-            x.add(acc, recs, sb, b, sb1, wave, lane);
+            x.add(acc, recs, sb, b, sb1, wave, lane, bsum);
             x.load(a, b + 2 * U, sb1, c);
-            y.add(acc, recs, sb, b + U, sb1, wave, lane);
+            y.add(acc, recs, sb, b + U, sb1, wave, lane, bsum);
         }
         __syncthreads();
     }
     float* out = a.partial + (size_t)blockIdx.y * (ROWS + 1) * a.N1 + c;
-    for (int r = wave; r <= ROWS; r += D::NW) out[(size_t)r * a.N1] = acc[r * 64 + lane];
+    for (int r = wave; r < ROWS; r += D::NW) out[(size_t)r * a.N1] = acc[r * 64 + lane];
+    if (wave == 0) out[(size_t)ROWS * a.N1] = bsum;
 }
 
 // Table row -> gradient row (the weight file's order).  Cube: non-centre
