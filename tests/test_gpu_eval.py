@@ -271,6 +271,46 @@ def test_hipgraph_replay_uneven_batches(net_files):
         assert int((d_h[size:] != -7).sum()) == 0, size  # rows past n untouched
 
 
+def test_hipgraph_replays_match_oracle(net_files):
+    """The captured graph against the oracle, not only against the eager path:
+    FP32 replays at uneven sizes (the wide-block 256-row tile forced, so a
+    partial last tile and the device-side tile stride are exercised), 40
+    sampled rows per replay against the FP64 forward pass and the output rule."""
+    path = net_files["stp4_res"]
+    cap = 16384
+    m = hb.Model(path, prec=hb.HB_FP32, combine_md=True, max_batch=cap)
+    m.set_tile(15)
+    net = O.Net(path)
+    st = synth.stp_walks(4, synth.throughput_seeds(cap, 2025), lengths=200)
+    packed = torch.from_numpy(hb.hb_encode(1, st)).cuda()
+    s = torch.cuda.Stream()
+    d_p = torch.zeros((cap, 8), dtype=torch.uint8, device="cuda")
+    d_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    d_h = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    d_y = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(s):
+        m.eval_batch_dev_n(d_p, d_n, cap, d_h, d_y, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        m.eval_batch_dev_n(d_p, d_n, cap, d_h, d_y, stream=s)
+    rng = np.random.default_rng(5)
+    for size in synth.uneven_batch_sizes(78, 4) + [257, 8000]:
+        d_p[:size] = packed[:size]
+        d_n.fill_(size)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        idx = np.unique(np.concatenate([rng.choice(size, min(size, 38), replace=False), [0, size - 1]]))
+        y = d_y[:size].cpu().numpy().astype(np.float64)[idx]
+        y_ref = net.forward(st[idx])[:, 0]
+        assert np.max(np.abs(y - y_ref) / np.maximum(1, np.abs(y_ref))) <= TOL[hb.HB_FP32], size
+        h_ref = net.h(y_ref, 0, classic=O.manhattan(1, st[idx]))
+        amb = np.abs(y_ref - np.round(y_ref)) < 1e-4  # an output within rounding of an integer may floor either way
+        assert np.array_equal(d_h[:size].cpu().numpy()[idx][~amb], h_ref[~amb]), size
+    m.close()
+
+
 def test_full_size_sampled_rows(net_files):
     """B = 16384 (the largest batch) in the benchmark's launch shape; 48 sampled
     rows against the oracle."""
