@@ -110,6 +110,12 @@ def main():
                          "training states labelled by the 7-8 additive PDB minus Manhattan distance, BF16 weights, "
                          "FP32 master, Adam, batch 8192), its over-estimate rate on held-out states and Batch IDA* "
                          "with it against IDA* with Manhattan distance and with the PDB; prints its own JSON line")
+    ap.add_argument("--gpu-depth", type=int, default=None, choices=[1, 2],
+                    help="batches on the GPU at once in the search legs (cbdfs_params.gpu_depth; default: the "
+                         "library's)")
+    ap.add_argument("--search-only", action="store_true",
+                    help="instead of the benchmark line: only the search legs (15-puzzle, 6-6-3 PDB, cube); prints "
+                         "their JSON")
     ap.add_argument("--table2", action="store_true",
                     help="instead of the benchmark line: only the real-valued cube leg (trained regression net, "
                          "Batch IDA* against Batch BTS); prints its own JSON line")
@@ -323,7 +329,7 @@ def main():
     # 8000 per precision (with h agreement against the FP64 oracle on a sample),
     # and the 8-puzzle network at the serial search's batch of 64 and over all
     # 181,440 states
-    other = other_configs(args, hb, synth, netcfg, O, torch, stream, tmp)
+    other = other_configs(args, hb, synth, netcfg, O, torch, stream, tmp) if not args.search_only else None
 
     # search nodes/s: Batch IDA* on a 15-puzzle start (200-move walk), fixed-tree
     # mode (network evaluated on every generated state, Manhattan pruning), at
@@ -331,6 +337,7 @@ def main():
     # thread) 64: the 15-puzzle's low branching factor leaves batches of about
     # 120 states at workNum 8, where a forward pass costs the same as at 1000.
     search = None
+    gd = {"gpu_depth": args.gpu_depth} if args.gpu_depth else {}
     if not args.no_search:
         start = synth.stp4_instances(1)[0]
         threads = min(32, max(4, len(os.sched_getaffinity(0))))
@@ -338,7 +345,7 @@ def main():
                               "work_num 64, 1M expansions", "threads": threads,
                   "host_cores": len(os.sched_getaffinity(0))}
         for name in ("f32", "bf16", "fp8"):
-            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0)
+            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0, **gd)
             r = hb.cbdfs_solve(hb.HB_STP4, start, model=models[name], combine=hb.HB_H_FIXED_TREE,
                                classic=hb.HB_CLASSIC_MD, threads=threads, params=p, raise_on_error=False)
             search[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
@@ -367,7 +374,7 @@ def main():
         sp = {"workload": f"same start, fixed-tree Batch IDA* pruned by the {label} additive PDB, work_num 64, "
                           "1M expansions", "pdb_build_s": apdb_s}
         for name in ("f32", "bf16", "fp8"):
-            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0)
+            p = hb.default_params(batch_size=8000, work_num=64, node_limit=1_000_000, time_limit_s=20.0, **gd)
             r = hb.cbdfs_solve(hb.HB_STP4, start, model=models[name], combine=hb.HB_H_FIXED_TREE,
                                classic=hb.HB_CLASSIC_PDB, pdb=apdb, threads=threads, params=p, raise_on_error=False)
             sp[name] = {"nodes_per_s": r["generated"] / max(1e-9, r["wall_s"]), "generated": r["generated"],
@@ -399,7 +406,7 @@ def main():
             cm = hb.Model(cpath, prec=prec, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4000)
             if prec == hb.HB_FP8_E4M3:
                 cm.calibrate(d_ccal)
-            p = hb.default_params(batch_size=4000, work_num=32, node_limit=300_000, time_limit_s=20.0)
+            p = hb.default_params(batch_size=4000, work_num=32, node_limit=300_000, time_limit_s=20.0, **gd)
             r = hb.cbdfs_solve(hb.HB_RUBIK3, cstart, model=cm, combine=hb.HB_H_FIXED_TREE,
                                classic=hb.HB_CLASSIC_PDB, pdb=pdb, algo=hb.HB_BTS, threads=threads, params=p,
                                raise_on_error=False)
@@ -414,6 +421,9 @@ def main():
         pdb.close()
         search["cube"] = cube
 
+        if args.search_only:
+            print(json.dumps({"gpu_depth": args.gpu_depth, "search": search}))
+            return
         # real-valued regression heuristic on the cube (the paper's regression
         # experiment, Table 2): a trained regression net used as y - 2.2 without
         # rounding, Batch IDA* against Batch BTS on walks of 8 and 9 turns

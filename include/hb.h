@@ -404,6 +404,9 @@ typedef struct {
     int max_iters;         /* safety cap on iterations (default 1000) */
     int use_graphs;        /* replay each GPU batch as a captured hipGraph (copy in, forward, copy out),
                               one per power-of-two size bucket (default 1); 0: direct launches */
+    int gpu_depth;         /* batches on the GPU at once, 1 (default) or 2: with 2 the next batch is
+                              sealed and launched while the previous one is evaluated (the paper's
+                              batch thread keeps several batches in RAM); needs n_slabs >= 3 */
 } cbdfs_params;
 
 /* Fill p with the defaults listed above. */

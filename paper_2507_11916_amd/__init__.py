@@ -63,7 +63,8 @@ class Params(C.Structure):
                 ("n_slabs", C.c_int), ("flush_when_idle", C.c_int), ("node_limit", C.c_int64),
                 ("time_limit_s", C.c_double), ("bts_b0", C.c_int64), ("bts_c1", C.c_int), ("bts_c2", C.c_int),
                 ("bts_root_plus_one", C.c_int), ("dedup_frontier", C.c_int), ("complete_final_iter", C.c_int),
-                ("start_bound", C.c_int32), ("max_iters", C.c_int), ("use_graphs", C.c_int)]
+                ("start_bound", C.c_int32), ("max_iters", C.c_int), ("use_graphs", C.c_int),
+                ("gpu_depth", C.c_int)]
 
 
 class Iter(C.Structure):

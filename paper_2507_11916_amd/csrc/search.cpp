@@ -44,6 +44,7 @@
 #include <climits>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -91,9 +92,12 @@ class Batcher {
 public:
     // flush_mode: 0 full slab or timeout; 1 also when every search thread
     // waits on h; 2 also whenever the batch thread is free (eager).
-    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, int flush_mode, bool graphs)
+    // gpu_depth: batches on the GPU at once (1 or 2); with 2 the next batch is
+    // staged and launched while the previous one is still being evaluated.
+    Batcher(Shared* sh, int cap, int n_slabs, double timeout_s, int flush_mode, bool graphs, int gpu_depth)
         : sh_(sh), cap_(cap), timeout_(timeout_s), idle_flush_(flush_mode >= 1), eager_(flush_mode >= 2),
-          use_graphs_(graphs), n_slabs_(n_slabs) {}
+          use_graphs_(graphs), n_slabs_(n_slabs),
+          depth_(std::max(1, std::min(kMaxGpuDepth, std::min(gpu_depth, n_slabs - 1)))) {}
     hb_status init();
     void start();
     void stop();
@@ -140,16 +144,26 @@ private:
         std::lock_guard<std::mutex> lk(mu_);
         cv_.notify_all();
     }
+    struct Launched {  // a batch on the GPU (batch thread only)
+        Slab* s;
+        int n, k;          // states, buffer set
+    };
     void loop();
-    hb_status process(Slab* s, int n);
+    hb_status process(Slab* s, int n);   // synchronous: evaluate and hand back
+    void hand_back(Slab* s, int n);      // write the values to their owners
+    void complete(Slab* s, hb_status st);  // under mu_: slab free again, errors recorded
+    hb_status gpu_launch(int k, const uint8_t* packed, int n);
+    void gpu_collect(int k, int n, int32_t* h_out);
     hb_status gpu_eval(const uint8_t* packed, int n, int32_t* h_out);
-    hb_status capture(int bi);
+    hb_status capture(int k, int bi);
     Shared* sh_;
     int cap_;
     double timeout_;
     bool idle_flush_, eager_;
     bool use_graphs_;
     int n_slabs_;
+    static constexpr int kMaxGpuDepth = 2;
+    int depth_;
     std::vector<std::unique_ptr<Slab>> slabs_;
     std::vector<Slab*> free_;
     Slab* cur_ = nullptr;
@@ -177,16 +191,23 @@ private:
     int idle_cap_ = 0, n_search_ = 0;
     // GPU side: [count | pad | packed states] staged in pinned memory and
     // copied as one block; h comes back into pinned memory.
+    // One buffer set per batch that may be on the GPU at once; every batch
+    // runs on the one stream, so they are evaluated in launch order and share
+    // the model's activation workspace.
     static constexpr int kHdr = 256;
-    uint8_t* stage_ = nullptr;    // pinned, kHdr + cap * pb
-    int32_t* h_stage_ = nullptr;  // pinned, cap
-    uint8_t* d_stage_ = nullptr;  // device, kHdr + cap * pb
-    int32_t* d_h_ = nullptr;
-    float* d_raw_ = nullptr;      // device, cap: the network's y - offset (real-valued h)
+    uint8_t* stage_[kMaxGpuDepth] = {};    // pinned, kHdr + cap * pb
+    int32_t* h_stage_[kMaxGpuDepth] = {};  // pinned, cap
+    uint8_t* d_stage_[kMaxGpuDepth] = {};  // device, kHdr + cap * pb
+    int32_t* d_h_[kMaxGpuDepth] = {};
+    float* d_raw_[kMaxGpuDepth] = {};      // device, cap: the network's y - offset (real-valued h)
+    hipEvent_t done_[kMaxGpuDepth] = {};   // recorded after a batch's copy back
     hipStream_t stream_ = nullptr;
-    std::vector<int> buckets_;              // ascending batch capacities, the last is cap
-    std::vector<hipGraphExec_t> execs_;     // per bucket, null until captured
+    std::vector<int> buckets_;                          // ascending batch capacities, the last is cap
+    std::vector<hipGraphExec_t> execs_[kMaxGpuDepth];   // per buffer set and bucket, null until captured
     bool graphs_ok_ = true;
+    std::deque<Launched> launched_;  // oldest first
+    int next_k_ = 0;
+    double busy_from_ = 0;           // start of the GPU's current busy period
 };
 
 struct Shared {
@@ -243,16 +264,19 @@ hb_status Batcher::init() {
     if (sh_->uses_gpu) {
         HB_HIP(hipSetDevice(sh_->model->device));
         HB_HIP(hipStreamCreate(&stream_));
-        HB_HIP(hipHostMalloc((void**)&stage_, kHdr + (size_t)cap_ * pb, hipHostMallocDefault));
-        HB_HIP(hipHostMalloc((void**)&h_stage_, (size_t)cap_ * 4, hipHostMallocDefault));
-        HB_HIP(hipMalloc((void**)&d_stage_, kHdr + (size_t)cap_ * pb));
-        HB_HIP(hipMalloc((void**)&d_h_, (size_t)cap_ * 4));
-        if (sh_->real) HB_HIP(hipMalloc((void**)&d_raw_, (size_t)cap_ * 4));
+        for (int k = 0; k < depth_; k++) {
+            HB_HIP(hipHostMalloc((void**)&stage_[k], kHdr + (size_t)cap_ * pb, hipHostMallocDefault));
+            HB_HIP(hipHostMalloc((void**)&h_stage_[k], (size_t)cap_ * 4, hipHostMallocDefault));
+            HB_HIP(hipMalloc((void**)&d_stage_[k], kHdr + (size_t)cap_ * pb));
+            HB_HIP(hipMalloc((void**)&d_h_[k], (size_t)cap_ * 4));
+            if (sh_->real) HB_HIP(hipMalloc((void**)&d_raw_[k], (size_t)cap_ * 4));
+            HB_HIP(hipEventCreateWithFlags(&done_[k], hipEventDisableTiming));
+        }
         hb_status st = model_prepare(sh_->model, stream_);  // workspace exists before any capture
         if (st != HB_OK) return st;
         for (int b = 32; b < cap_; b *= 2) buckets_.push_back(b);
         buckets_.push_back(cap_);
-        execs_.assign(buckets_.size(), nullptr);
+        for (int k = 0; k < depth_; k++) execs_[k].assign(buckets_.size(), nullptr);
     }
     return HB_OK;
 }
@@ -270,13 +294,16 @@ Batcher::~Batcher() {
     }
     if (sh_->uses_gpu) {
         if (stream_) (void)hipStreamSynchronize(stream_);
-        for (hipGraphExec_t e : execs_)
-            if (e) (void)hipGraphExecDestroy(e);
-        (void)hipHostFree(stage_);
-        (void)hipHostFree(h_stage_);
-        (void)hipFree(d_stage_);
-        (void)hipFree(d_h_);
-        (void)hipFree(d_raw_);
+        for (int k = 0; k < kMaxGpuDepth; k++) {
+            for (hipGraphExec_t e : execs_[k])
+                if (e) (void)hipGraphExecDestroy(e);
+            (void)hipHostFree(stage_[k]);
+            (void)hipHostFree(h_stage_[k]);
+            (void)hipFree(d_stage_[k]);
+            (void)hipFree(d_h_[k]);
+            (void)hipFree(d_raw_[k]);
+            if (done_[k]) (void)hipEventDestroy(done_[k]);
+        }
         if (stream_) (void)hipStreamDestroy(stream_);
     }
 }
@@ -318,28 +345,29 @@ void Batcher::drain() {
     draining_ = false;
 }
 
-// Captures copy-in, forward pass and copy-out for batches of up to
-// buckets_[bi] states; the state count is read on the device.
-hb_status Batcher::capture(int bi) {
+// Captures copy-in, forward pass and copy-out of buffer set k for batches of
+// up to buckets_[bi] states; the state count is read on the device.
+hb_status Batcher::capture(int k, int bi) {
     const int B = buckets_[bi];
     const int pb = sh_->D->packed_bytes;
     hipGraph_t g = nullptr;
     HB_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)B * pb, hipMemcpyHostToDevice, stream_);
-    hb_status st = e == hipSuccess ? model_eval(sh_->model, d_stage_ + kHdr, 0, reinterpret_cast<const int32_t*>(d_stage_),
-                                                B, d_h_, d_raw_, stream_, nullptr)
+    hipError_t e = hipMemcpyAsync(d_stage_[k], stage_[k], kHdr + (size_t)B * pb, hipMemcpyHostToDevice, stream_);
+    hb_status st = e == hipSuccess ? model_eval(sh_->model, d_stage_[k] + kHdr, 0,
+                                                reinterpret_cast<const int32_t*>(d_stage_[k]), B, d_h_[k], d_raw_[k],
+                                                stream_, nullptr)
                                    : fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
     if (st == HB_OK) {
-        const void* src = sh_->real ? (const void*)d_raw_ : (const void*)d_h_;
-        e = hipMemcpyAsync(h_stage_, src, (size_t)B * 4, hipMemcpyDeviceToHost, stream_);
+        const void* src = sh_->real ? (const void*)d_raw_[k] : (const void*)d_h_[k];
+        e = hipMemcpyAsync(h_stage_[k], src, (size_t)B * 4, hipMemcpyDeviceToHost, stream_);
         if (e != hipSuccess) st = fail(HB_E_DEVICE, "capture: %s", hipGetErrorString(e));
     }
     const hipError_t ee = hipStreamEndCapture(stream_, &g);
     if (st == HB_OK && ee != hipSuccess) st = fail(HB_E_DEVICE, "end capture: %s", hipGetErrorString(ee));
     if (st == HB_OK) {
-        e = hipGraphInstantiate(&execs_[bi], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&execs_[k][bi], g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            execs_[bi] = nullptr;
+            execs_[k][bi] = nullptr;
             st = fail(HB_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
         }
     }
@@ -347,41 +375,67 @@ hb_status Batcher::capture(int bi) {
     return st;
 }
 
-// One batch on the GPU: a graph launch when graphs are on, else the same
-// copy / forward / copy sequence issued directly.
-hb_status Batcher::gpu_eval(const uint8_t* packed, int n, int32_t* h_out) {
+// Stages a batch in buffer set k and launches it (a graph launch when graphs
+// are on, else the same copy / forward / copy sequence issued directly); done_[k]
+// is recorded behind it.  Returns without waiting.
+hb_status Batcher::gpu_launch(int k, const uint8_t* packed, int n) {
     const int pb = sh_->D->packed_bytes;
-    const double t0 = now_s();
-    std::memcpy(stage_ + kHdr, packed, (size_t)n * pb);
-    *reinterpret_cast<int32_t*>(stage_) = n;
+    std::memcpy(stage_[k] + kHdr, packed, (size_t)n * pb);
+    *reinterpret_cast<int32_t*>(stage_[k]) = n;
     bool launched = false;
     if (use_graphs_ && graphs_ok_ && !sh_->model->profiling) {
         const int bi = (int)(std::lower_bound(buckets_.begin(), buckets_.end(), n) - buckets_.begin());
-        if (!execs_[bi] && capture(bi) != HB_OK) {
+        if (!execs_[k][bi] && capture(k, bi) != HB_OK) {
             graphs_ok_ = false;  // keep searching with direct launches
             (void)hipGetLastError();
         }
-        if (execs_[bi]) {
-            HB_HIP(hipGraphLaunch(execs_[bi], stream_));
+        if (execs_[k][bi]) {
+            HB_HIP(hipGraphLaunch(execs_[k][bi], stream_));
             launched = true;
         }
     }
     if (!launched) {
-        HB_HIP(hipMemcpyAsync(d_stage_, stage_, kHdr + (size_t)n * pb, hipMemcpyHostToDevice, stream_));
-        hb_status st = model_eval(sh_->model, d_stage_ + kHdr, n, nullptr, 0, d_h_, d_raw_, stream_, nullptr);
+        HB_HIP(hipMemcpyAsync(d_stage_[k], stage_[k], kHdr + (size_t)n * pb, hipMemcpyHostToDevice, stream_));
+        hb_status st = model_eval(sh_->model, d_stage_[k] + kHdr, n, nullptr, 0, d_h_[k], d_raw_[k], stream_, nullptr);
         if (st != HB_OK) return st;
-        const void* src = sh_->real ? (const void*)d_raw_ : (const void*)d_h_;
-        HB_HIP(hipMemcpyAsync(h_stage_, src, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
+        const void* src = sh_->real ? (const void*)d_raw_[k] : (const void*)d_h_[k];
+        HB_HIP(hipMemcpyAsync(h_stage_[k], src, (size_t)n * 4, hipMemcpyDeviceToHost, stream_));
     }
-    HB_HIP(hipStreamSynchronize(stream_));
+    HB_HIP(hipEventRecord(done_[k], stream_));
+    return HB_OK;
+}
+
+// The values of a finished batch in buffer set k (done_[k] has completed).
+void Batcher::gpu_collect(int k, int n, int32_t* h_out) {
     if (sh_->real) {
-        const float* v = reinterpret_cast<const float*>(h_stage_);
+        const float* v = reinterpret_cast<const float*>(h_stage_[k]);
         for (int i = 0; i < n; i++) h_out[i] = real_bits(v[i]);
     } else {
-        std::memcpy(h_out, h_stage_, (size_t)n * 4);
+        std::memcpy(h_out, h_stage_[k], (size_t)n * 4);
     }
+}
+
+// One batch, waited for (the main thread's evaluation of the initial tree).
+hb_status Batcher::gpu_eval(const uint8_t* packed, int n, int32_t* h_out) {
+    const double t0 = now_s();
+    hb_status st = gpu_launch(0, packed, n);
+    if (st != HB_OK) return st;
+    HB_HIP(hipEventSynchronize(done_[0]));
+    gpu_collect(0, n, h_out);
     gpu_busy += now_s() - t0;
     return HB_OK;
+}
+
+void Batcher::hand_back(Slab* s, int n) {
+    gen_.fetch_add(1);  // before any value becomes visible: idle marks taken so far are stale
+    for (int i = 0; i < n; i++) {
+        NodeRec* r = s->owners[i];
+        int32_t v = s->h[i];
+        if (sh_->combine == HB_H_MIN_NN_CLASSIC) v = std::min(v, r->hc);
+        r->h.store(v, std::memory_order_release);
+    }
+    evals += n;
+    batches += 1;
 }
 
 hb_status Batcher::process(Slab* s, int n) {
@@ -396,76 +450,137 @@ hb_status Batcher::process(Slab* s, int n) {
             s->h[i] = sh_->classic_h(st);
         }
     }
-    gen_.fetch_add(1);  // before any value becomes visible: idle marks taken so far are stale
-    for (int i = 0; i < n; i++) {
-        NodeRec* r = s->owners[i];
-        int32_t v = s->h[i];
-        if (sh_->combine == HB_H_MIN_NN_CLASSIC) v = std::min(v, r->hc);
-        r->h.store(v, std::memory_order_release);
-    }
-    evals += n;
-    batches += 1;
+    hand_back(s, n);
     return HB_OK;
 }
 
+void Batcher::complete(Slab* s, hb_status st) {
+    if (st != HB_OK && error == HB_OK) {
+        error = st;
+        error_text = hb_last_error();
+    }
+    s->reserved = 0;
+    s->committed.store(0, std::memory_order_relaxed);
+    if (!cur_) cur_ = s;
+    else free_.push_back(s);
+    in_flight_--;
+}
+
+// The batch thread.  It seals the filling slab when it is full, its oldest
+// record has waited `timeout`, every search thread waits on h (idle flush),
+// or (eager) whenever it may launch, as long as fewer than depth_ batches are
+// on the GPU; it hands back the oldest launched batch as soon as its values
+// have arrived.  With depth 1 each batch is evaluated and handed back before
+// the next is sealed.
 void Batcher::loop() {
     if (sh_->uses_gpu) (void)hipSetDevice(sh_->model->device);
+    const bool pipelined = sh_->uses_gpu && depth_ > 1;
     std::unique_lock<std::mutex> lk(mu_);
+    int spin = 0;
     for (;;) {
-        Slab* s = nullptr;
-        int n = 0;
-        int spin = 0;
-        while (!stop_) {
-            if (cur_ && cur_->reserved > 0) {
-                const bool full = cur_->reserved == cap_;
-                const double left = cur_->t_first + timeout_ - now_s();
-                const bool idle = idle_flush_ && all_idle();
-                // eager: the GPU is free now, so whatever arrived while it
-                // evaluated the previous batch goes at once
-                if (full || left <= 0 || idle || eager_ || draining_) break;
-                // Poll briefly first (a sleeping batch thread adds a wake-up
-                // to every round trip), then sleep until notified by reserve()
-                // (full slab), mark_idle() or thread_done(), or the timeout.
-                if (idle_flush_ && spin < kSpin) {
-                    lk.unlock();
-                    for (int i = 0; i < 16 && !all_idle(); i++) std::this_thread::yield();
-                    lk.lock();
-                    spin++;
-                    continue;
+        if (stop_ || error != HB_OK) {
+            // drain() has handed back every batch before a regular stop; after an
+            // error the launched batches are waited for and dropped
+            if (!launched_.empty()) {
+                lk.unlock();
+                (void)hipStreamSynchronize(stream_);
+                lk.lock();
+                while (!launched_.empty()) {
+                    complete(launched_.front().s, HB_OK);
+                    launched_.pop_front();
                 }
-                cv_.wait_for(lk, std::chrono::microseconds(std::max<int64_t>(1, std::min<int64_t>(1000, (int64_t)(left * 1e6)))));
-            } else {
-                cv_.wait_for(lk, std::chrono::microseconds(200));
+            }
+            stop_ = true;
+            cv_.notify_all();
+            return;
+        }
+        if (!launched_.empty()) {
+            const hipError_t q = hipEventQuery(done_[launched_.front().k]);
+            if (q != hipErrorNotReady) {
+                const Launched f = launched_.front();
+                launched_.pop_front();
+                lk.unlock();
+                const double t = now_s();
+                gpu_busy += t - busy_from_;
+                busy_from_ = t;
+                hb_status st = HB_OK;
+                if (q == hipSuccess) {
+                    gpu_collect(f.k, f.n, f.s->h);
+                    hand_back(f.s, f.n);
+                } else {
+                    st = fail(HB_E_DEVICE, "batch evaluation: %s", hipGetErrorString(q));
+                }
+                lk.lock();
+                complete(f.s, st);
+                cv_.notify_all();
+                spin = 0;
+                continue;
             }
         }
-        if (stop_) return;
-        s = cur_;
-        n = s->reserved;
-        if (!free_.empty()) {
-            cur_ = free_.back();
-            free_.pop_back();
+        const bool can_seal = (int)launched_.size() < (pipelined ? depth_ : 1) && cur_ && cur_->reserved > 0;
+        if (can_seal) {
+            const bool full = cur_->reserved == cap_;
+            const double left = cur_->t_first + timeout_ - now_s();
+            const bool idle = idle_flush_ && all_idle();
+            // eager: the GPU may take a batch now, so whatever arrived goes at once
+            if (full || left <= 0 || idle || eager_ || draining_) {
+                Slab* s = cur_;
+                const int n = s->reserved;
+                if (!free_.empty()) {
+                    cur_ = free_.back();
+                    free_.pop_back();
+                } else {
+                    cur_ = nullptr;
+                }
+                in_flight_++;
+                lk.unlock();
+                cv_.notify_all();
+                while (s->committed.load(std::memory_order_acquire) < n) std::this_thread::yield();
+                hb_status st = HB_OK;
+                if (pipelined) {
+                    const int k = next_k_;
+                    if (launched_.empty()) busy_from_ = now_s();
+                    st = gpu_launch(k, s->packed, n);
+                    lk.lock();
+                    if (st == HB_OK) {
+                        launched_.push_back(Launched{s, n, k});
+                        next_k_ = (k + 1) % depth_;
+                    } else {
+                        complete(s, st);
+                        cv_.notify_all();
+                    }
+                } else {
+                    st = process(s, n);
+                    lk.lock();
+                    complete(s, st);
+                    cv_.notify_all();
+                }
+                spin = 0;
+                continue;
+            }
+        }
+        if (!launched_.empty()) {
+            // a batch is on the GPU: poll it (and the flush conditions) without sleeping
+            lk.unlock();
+            for (int i = 0; i < 4; i++) std::this_thread::yield();
+            lk.lock();
+            continue;
+        }
+        if (cur_ && cur_->reserved > 0) {
+            // Poll briefly first (a sleeping batch thread adds a wake-up to every
+            // round trip), then sleep until notified by reserve() (full slab),
+            // mark_idle() or thread_done(), or the timeout.
+            if (idle_flush_ && spin < kSpin) {
+                lk.unlock();
+                for (int i = 0; i < 16 && !all_idle(); i++) std::this_thread::yield();
+                lk.lock();
+                spin++;
+                continue;
+            }
+            const double left = cur_->t_first + timeout_ - now_s();
+            cv_.wait_for(lk, std::chrono::microseconds(std::max<int64_t>(1, std::min<int64_t>(1000, (int64_t)(left * 1e6)))));
         } else {
-            cur_ = nullptr;
-        }
-        in_flight_++;
-        lk.unlock();
-        cv_.notify_all();
-        while (s->committed.load(std::memory_order_acquire) < n) std::this_thread::yield();
-        hb_status st = process(s, n);
-        lk.lock();
-        if (st != HB_OK && error == HB_OK) {
-            error = st;
-            error_text = hb_last_error();
-        }
-        s->reserved = 0;
-        s->committed.store(0, std::memory_order_relaxed);
-        if (!cur_) cur_ = s;
-        else free_.push_back(s);
-        in_flight_--;
-        cv_.notify_all();
-        if (error != HB_OK) {
-            stop_ = true;
-            return;
+            cv_.wait_for(lk, std::chrono::microseconds(200));
         }
     }
 }
@@ -921,6 +1036,7 @@ void cbdfs_params_default(cbdfs_params* p) {
     p->timeout_us = 4000;
     p->n_slabs = 4;
     p->flush_when_idle = 1;
+    p->gpu_depth = 1;
     p->node_limit = 0;
     p->time_limit_s = 0;
     p->bts_b0 = 10000;
@@ -958,7 +1074,7 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
     cbdfs_params_default(&P);
     if (p_in) P = *p_in;
     if (P.batch_size < 1 || P.work_num < 1 || P.n_slabs < 2 || P.timeout_us < 0 || P.max_iters < 1 ||
-        P.flush_when_idle < 0 || P.flush_when_idle > 2)
+        P.flush_when_idle < 0 || P.flush_when_idle > 2 || P.gpu_depth < 1 || P.gpu_depth > 2)
         return fail(HB_E_INVAL, "bad parameters");
     if (algo == HB_BTS && (P.bts_b0 < 1 || P.bts_c1 < 1 || P.bts_c2 <= P.bts_c1))
         return fail(HB_E_INVAL, "bad BTS parameters (need b0 >= 1, c2 > c1 >= 1)");
@@ -996,7 +1112,7 @@ hb_status cbdfs_solve(hb_domain d, const uint8_t* start, const hb_heuristic* h, 
         int cap = P.batch_size;
         if (nn) cap = std::min(cap, h->model->opts.max_batch);
         S->batcher = std::make_unique<Batcher>(&S->sh, cap, P.n_slabs, P.timeout_us * 1e-6, P.flush_when_idle,
-                                               P.use_graphs != 0);
+                                               P.use_graphs != 0, P.gpu_depth);
         hb_status st = S->batcher->init();
         if (st != HB_OK) return st;
     }

@@ -201,3 +201,76 @@ def test_real_valued_cube_search_matches_oracle(tmp_path):
         assert _complete_counts(r["iters"]) == [(int(np.floor(it["bound"])), it["expanded"], it["generated"])
                                                 for it in o["iters"] if it["complete"]]
     m.close()
+
+
+def test_two_batches_on_the_gpu_take_the_oracles_iterations(net_files, tmp_path):
+    """gpu_depth = 2 (the next batch is sealed and launched while the previous
+    one is on the GPU, values handed back in launch order): the searches still
+    take the oracle's iterations and counts exactly - the 8-puzzle network
+    search, the fixed-tree 15-puzzle search at BF16, the cube's fixed-tree BTS
+    and the real-valued cube search."""
+    path = net_files["stp3_small"]
+    allst = O.all8()
+    net = O.Net(path)
+    h_ref = net.h(net.forward(allst), 0, classic=O.manhattan(0, allst))
+    ranks = np.array([O.lib().orc_perm9_rank(np.ascontiguousarray(s).ctypes.data) for s in allst])
+    table = np.zeros(362880, dtype=np.int32)
+    table[ranks] = h_ref
+    m = hb.Model(path, prec=hb.HB_FP32, combine_md=True, max_batch=4096)
+    for i, s in enumerate(synth.stp3_instances(24)):
+        p = hb.default_params(batch_size=64, work_num=4, complete_final_iter=1, gpu_depth=2)
+        r = hb.cbdfs_solve(0, s, model=m, combine=hb.HB_H_NN, threads=4, params=p)
+        o = O.ida(0, s, hkind=O.H_TABLE8, table8=table, complete_final=True)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
+        assert np.array_equal(_follow(0, s, r["path"]), O.goal(0))
+    m.close()
+
+    m = hb.Model(net_files["stp4_res"], prec=hb.HB_BF16, combine_md=True, max_batch=8000)
+    for s in synth.stp_walks(4, synth.config_seeds(2, 3), lengths=46):
+        p = hb.default_params(batch_size=1000, work_num=8, gpu_depth=2)
+        r = hb.cbdfs_solve(1, s, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_MD, threads=16, params=p)
+        o = O.ida(1, s, hkind=O.H_MD)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"][:-1])
+    m.close()
+
+    k = 4
+    pdb = hb.Pdb(k)
+    tab, _ = O.corner_pdb(k)
+    m = hb.Model(net_files["rc_cls"], prec=hb.HB_BF16, out=hb.HB_OUT_CLS_QUANTILE, q=0.99, max_batch=4000)
+    for s in O.apply_moves(2, synth.rc_walk_moves_array(synth.config_seeds(3, 2), length_base=6, length_span=2)):
+        p = hb.default_params(batch_size=4000, work_num=8, bts_b0=2000, gpu_depth=2)
+        r = hb.cbdfs_solve(2, s, model=m, combine=hb.HB_H_FIXED_TREE, classic=hb.HB_CLASSIC_PDB, pdb=pdb,
+                           algo=hb.HB_BTS, threads=16, params=p)
+        o = O.bts(2, s, hkind=O.H_PDB, pdb=tab, pdb_k=k, b0=2000)
+        assert r["cost"] == o["cost"]
+        assert [(i["bound"], i["limit"], i["complete"]) for i in r["iters"]] == \
+               [(i["bound"], i["limit"], i["complete"]) for i in o["iters"]]
+        assert _complete_counts(r["iters"]) == _complete_counts(o["iters"])
+    m.close()
+    pdb.close()
+
+    cpath = str(tmp_path / "cube_mis.hbw")
+    nets.write_cube_misplaced_net(cpath, 1.0 / 16)
+    cnet = O.Net(cpath)
+    m = hb.Model(cpath, prec=hb.HB_FP32, out=hb.HB_OUT_REG_REAL, offset=0.0, max_batch=4096)
+    for i, L in enumerate((4, 5)):
+        s = O.apply_moves(2, synth.rc_walk_moves_array([3400 + i], length_base=L, length_span=1))[0]
+        p = hb.default_params(batch_size=256, work_num=4, complete_final_iter=1, gpu_depth=2)
+        r = hb.cbdfs_solve(2, s, model=m, combine=hb.HB_H_NN_REAL, classic=hb.HB_CLASSIC_ZERO, threads=4, params=p)
+        o = O.ida_real_net(cnet, s, complete_final=True)
+        assert r["status"] == hb.HB_OK and r["cost"] == o["cost"] == L
+        assert [(it["bound_real"], it["expanded"], it["generated"]) for it in r["iters"]] == \
+               [(it["bound"], it["expanded"], it["generated"]) for it in o["iters"]]
+    m.close()
+
+
+def test_gpu_depth_out_of_range_is_refused(net_files):
+    m = hb.Model(net_files["stp3_small"], prec=hb.HB_FP32, combine_md=True, max_batch=256)
+    s = synth.stp3_instances(1)[0]
+    for d in (0, 3):
+        r = hb.cbdfs_solve(0, s, model=m, combine=hb.HB_H_NN, threads=2,
+                           params=hb.default_params(batch_size=64, gpu_depth=d), raise_on_error=False)
+        assert r["status"] == hb.HB_E_INVAL
+    m.close()
