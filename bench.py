@@ -42,7 +42,8 @@ TILE_KERNELS = {1: "gemm_kernel<{p}, {p}, 128, 128>", 2: "gemm_kernel<{p}, {p}, 
                 7: "gemm_ring_kernel<{p}, {p}, 128, 128, 3>", 8: "gemm_ring_kernel<{p}, {p}, 128, 256, 3>",
                 9: "gemm_ring_kernel<{p}, {p}, 64, 128, 4>", 10: "gemm_w8_kernel<{p}, {p}>",
                 15: "gemm_wide_kernel<{p}, {p}, 8, 2>", 16: "gemm_wide_kernel<{p}, {p}, 8, 3>",
-                17: "gemm_wide_kernel<{p}, {p}, 16, 2>"}
+                17: "gemm_wide_kernel<{p}, {p}, 16, 2>", 18: "gemm_wide_kernel<{p}, {p}, 8, 2>",
+                19: "gemm_kernel<{p}, {p}, 128, 128>"}
 PREC_ARG = {"f32": 0, "bf16": 1, "fp8": 2}
 
 

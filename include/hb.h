@@ -258,8 +258,12 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
  *   (HB_E_UNSUPPORTED);
  * 15 256x128 (2-stage ring), 16 256x128 (3-stage ring): LDS ring filled by
  *   direct loads, each stage's operands read whole before its MFMAs, 8 waves;
- * 17 256x128 (2-stage ring), the same with 16 waves (4 x 4, 64x32 each).
- * All shapes give bitwise equal results.  HB_E_INVAL outside 0..17.  See hb_model_tune. */
+ * 17 256x128 (2-stage ring), the same with 16 waves (4 x 4, 64x32 each);
+ * 18 the 15 kernel as a persistent grid of one block per compute unit, 19 the 1
+ *   kernel as a persistent grid of two blocks per compute unit: a block's tiles
+ *   after its first come off an atomic counter (per stream, reset by each
+ *   launch's last block; no block waits on another).
+ * All shapes give bitwise equal results.  HB_E_INVAL outside 0..19.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
 /* Autotuner for one batch size: times every tile shape on the n packed states
  * (device) and keeps the fastest for batches in n's power-of-two bucket

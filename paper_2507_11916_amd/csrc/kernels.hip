@@ -269,7 +269,25 @@ struct GemmArgs {
     // [s K / split, (s + 1) K / split) into C + s * c_split elements
     int split = 1;
     int64_t c_split = 0;
+    // dynamic tile schedule (a persistent grid): tiles after a block's first
+    // come off tile_ctr[0]; tile_ctr[1] counts the blocks that have left
+    int* tile_ctr = nullptr;
 };
+
+// Dynamic tile schedule.  A block's first tile is its own (the XCD-aware order
+// below), later ones come off an atomic counter: tile_fetch is issued by thread
+// 0 when a tile starts, so its latency hides behind that tile.  Nothing ever
+// waits on another block: the last block to leave resets the counter pair, so
+// the next launch on the stream finds both at zero.
+__device__ __forceinline__ int tile_fetch(const GemmArgs& g, int grid) {
+    return __hip_atomic_fetch_add(g.tile_ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + grid;
+}
+__device__ __forceinline__ void tile_sched_exit(const GemmArgs& g) {
+    if (__hip_atomic_fetch_add(g.tile_ctr + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1) {
+        __hip_atomic_store(g.tile_ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(g.tile_ctr + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // Column offset in A of the group that output column n0 belongs to.
 __device__ __forceinline__ size_t group_a_col(const GemmArgs& g, int n0) {
@@ -436,7 +454,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     int first = blockIdx.x;
     if (blockIdx.x < grid8) first = (blockIdx.x & 7) * (grid8 >> 3) + (blockIdx.x >> 3);
 
-    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+    const bool dyn = g.tile_ctr != nullptr;
+    __shared__ int s_next;
+    const int t_end = g.persistent ? total : (first < total ? first + 1 : 0);
+    for (int t = first; dyn ? t < total : t < t_end;) {
+        int nxt = 0;
+        if (dyn && tid == 0) nxt = tile_fetch(g, grid);
         const int tm = t / n_tiles, tn = t % n_tiles;
         const int m0 = tm * BM, n0 = tn * BN;
         const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0)) * EB;
@@ -498,6 +521,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             _Pragma("unroll") for (int i = 0; i < TI; i++)
                 epi_tile<OUTT>(g, acc[i][j], sn, bn, (m0 + wm * (BM / 2) + i * 32 + 4 * half) * g.ldc + n);
         }
+        if (dyn) {
+            __syncthreads();
+            if (tid == 0) s_next = nxt;
+            __syncthreads();
+            t = s_next;
+        } else {
+            t += grid;
+        }
+    }
+    if (dyn) {
+        __syncthreads();
+        if (tid == 0) tile_sched_exit(g);
     }
 }
 
@@ -785,7 +820,12 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
     const int lrow = lane >> 3;
     (void)NT;
 
-    for (int t = first; t < (g.persistent ? total : (first < total ? first + 1 : 0)); t += grid) {
+    const bool dyn = g.tile_ctr != nullptr;
+    __shared__ int s_next;
+    const int t_end = g.persistent ? total : (first < total ? first + 1 : 0);
+    for (int t = first; dyn ? t < total : t < t_end;) {
+        int nxt = 0;
+        if (dyn && tid == 0) nxt = tile_fetch(g, grid);
         const int sl = t / tiles_mn, tt = t - sl * tiles_mn;
         const int m0 = (tt / n_tiles) * BM, n0 = (tt % n_tiles) * BN;
         const uint8_t* Ag = g.A + ((size_t)m0 * g.lda + group_a_col(g, n0) + (size_t)sl * kslice) * EB;
@@ -838,6 +878,18 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
             _Pragma("unroll") for (int i = 0; i < TI; i++)
                 epi_tile<OUTT>(gs, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
         }
+        if (dyn) {
+            __syncthreads();
+            if (tid == 0) s_next = nxt;
+            __syncthreads();
+            t = s_next;
+        } else {
+            t += grid;
+        }
+    }
+    if (dyn) {
+        __syncthreads();
+        if (tid == 0) tile_sched_exit(g);
     }
 }
 
@@ -1375,7 +1427,11 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     g.m_tiles_cap = m_tiles;
     int grid = tiles;
     g.persistent = 0;
-    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) {
+        grid = L.persistent_grid;
+        g.persistent = 1;
+        g.tile_ctr = L.tile_ctr;  // dynamic schedule when the caller supplies the counters
+    }
     if (L.m_dev) g.persistent = 1;  // tile count known only on the device: stride over the cap
     const size_t lds = 2 * (size_t)(BM + BN) * 128;
     hipLaunchKernelGGL((gemm_kernel<PREC, OUTT, BM, BN>), dim3(grid), dim3(256), lds, s, g);
@@ -1450,7 +1506,11 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     g.m_tiles_cap = m_tiles;
     int grid = tiles;
     g.persistent = 0;
-    if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
+    if (L.persistent_grid > 0 && L.persistent_grid < tiles) {
+        grid = L.persistent_grid;
+        g.persistent = 1;
+        g.tile_ctr = L.tile_ctr;
+    }
     if (L.m_dev) g.persistent = 1;
     hipLaunchKernelGGL((gemm_wide_kernel<PREC, OUTT, NW, NS>), dim3(grid), dim3(NW * 64), (size_t)NS * (256 + 128) * 128,
                        s, g);
@@ -1462,15 +1522,30 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
 // forward kernel (one-wave 32 x 32 tiles; 2, 4, 8 or 12 waves per compute
 // unit), which replaces the whole forward pass rather than one layer;
 // 14-16 the wide-block ring kernels (8 waves with a 2- or 3-stage ring, 16
-// waves with a 2-stage ring).
-int gemm_tile_count() { return 17; }
+// waves with a 2-stage ring); 17 and 18 persistent grids (one 8-wave wide
+// block per compute unit, two 128x128 blocks per compute unit) taking tiles
+// off an atomic counter when the caller supplies one.
+int gemm_tile_count() { return 19; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[17][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+    static const int T[19][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
                                  {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128},
                                  {32, 32}, {32, 32}, {32, 32}, {32, 32},
-                                 {256, 128}, {256, 128}, {256, 128}};
+                                 {256, 128}, {256, 128}, {256, 128}, {256, 128}, {128, 128}};
     *bm = T[id][0];
     *bn = T[id][1];
+}
+
+// Compute units of the current device (cached per device).
+static int compute_units() {
+    static int cu[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!cu[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cu[dev] = n;
+    }
+    return cu[dev];
 }
 
 template <int PREC, int OUTT>
@@ -1489,6 +1564,18 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 14: launch_gemm_wide<PREC, OUTT, 8, 2>(L, s); return true;
         case 15: launch_gemm_wide<PREC, OUTT, 8, 3>(L, s); return true;
         case 16: launch_gemm_wide<PREC, OUTT, 16, 2>(L, s); return true;
+        case 17: {
+            GemmLaunch P = L;
+            P.persistent_grid = compute_units();
+            launch_gemm_wide<PREC, OUTT, 8, 2>(P, s);
+            return true;
+        }
+        case 18: {
+            GemmLaunch P = L;
+            P.persistent_grid = 2 * compute_units();
+            launch_gemm_t<PREC, OUTT, 128, 128>(P, s);
+            return true;
+        }
     }
     return false;
 }
@@ -1497,7 +1584,7 @@ bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
     const int out = L.out_type < 0 ? L.prec : L.out_type;
     if (L.split > 1) {  // split-K: wide tiles, whole 128-byte stages per slice, host row count
         const int eb = L.prec == 0 ? 4 : L.prec == 1 ? 2 : 1;
-        if (L.tile < 14 || L.tile > 16 || L.K % L.split != 0 || (L.K / L.split) * eb % 128 != 0 || L.m_dev ||
+        if (L.tile < 14 || L.tile > 17 || L.K % L.split != 0 || (L.K / L.split) * eb % 128 != 0 || L.m_dev ||
             L.R || L.Mk)
             return false;
     }

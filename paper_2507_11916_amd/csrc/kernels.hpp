@@ -49,6 +49,10 @@ struct GemmLaunch {
     // into C + s * c_split elements (partial products, summed by the caller).
     int split = 1;
     int64_t c_split = 0;
+    // Two zeroed ints per stream: with a persistent grid, blocks take tiles
+    // after their first off tile_ctr[0] (each launch leaves both at zero).
+    // Null: a persistent grid strides over the tiles statically.
+    int* tile_ctr = nullptr;
 };
 
 struct HeadArgs {

@@ -344,7 +344,8 @@ static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
     w.rows_cap = (int)round_up(m->opts.max_batch, 256);
     const size_t bytes = (size_t)w.rows_cap * m->width_cap * eb;
     w.rb_cap = w.rows_cap / 32;
-    const size_t sync_bytes = (4 + (size_t)(fused_max_layers() + 1) * w.rb_cap) * sizeof(int);
+    const size_t sync_ints = 4 + (size_t)(fused_max_layers() + 1) * w.rb_cap;
+    const size_t sync_bytes = (sync_ints + 2) * sizeof(int);  // then the GEMMs' tile counter pair
     if (hipMalloc(&w.x, bytes) != hipSuccess || hipMalloc(&w.t, bytes) != hipSuccess ||
         hipMalloc((void**)&w.absmax, 64 * sizeof(unsigned)) != hipSuccess ||
         hipMalloc((void**)&w.sync, sync_bytes) != hipSuccess) {
@@ -353,8 +354,10 @@ static hb_status get_ws(hb_model* m, hipStream_t s, Workspace** out) {
         (void)hipFree(w.absmax);
         return fail(HB_E_NOMEM, "workspace allocation of 2 x %zu bytes failed", bytes);
     }
-    // the fused kernel's counters start at zero; each launch leaves them zero
+    // the fused kernel's counters and the tile counters start at zero; each
+    // launch leaves them zero
     HB_HIP(hipMemset(w.sync, 0, sync_bytes));
+    w.tile_ctr = w.sync + sync_ints;
     auto r = m->ws.emplace(s, w);
     *out = &r.first->second;
     return HB_OK;
@@ -576,6 +579,7 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         g.r_scale = L.res_act >= 0 ? m->act_scale[L.res_act] : 1.f;
         g.out_inv_scale = 1.f / m->act_scale[L.out_act];
         g.relu = 1;
+        g.tile_ctr = w->tile_ctr;  // used by the persistent-grid tiles
         pi = timed ? prof_begin(m, 1, s) : -1;
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());

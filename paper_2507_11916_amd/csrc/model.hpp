@@ -36,6 +36,7 @@ struct Workspace {
     unsigned* absmax = nullptr;  // calibration scratch (n_act entries)
     int* sync = nullptr;         // counters of the fused forward kernel (zero between launches), or null
     int rb_cap = 0;              // 32-row blocks the counters cover
+    int* tile_ctr = nullptr;     // two zeroed ints: the GEMMs' dynamic tile schedule, or null
 };
 
 struct ActCopy {  // copy of one stored activation tensor (hb_model_activation)

@@ -195,7 +195,7 @@ def test_tile_shapes_give_identical_results(net_files, prec):
     packed = hb.hb_encode(1, st)
     calib = _dev(hb.hb_encode(1, synth.stp_walks(4, synth.throughput_seeds(1024, 4242), lengths=200)))
     outs = []
-    for tile in list(range(1, 11)) + [15, 16, 17]:
+    for tile in list(range(1, 11)) + [15, 16, 17, 18, 19]:
         m = hb.Model(path, prec=prec)
         if prec == hb.HB_FP8_E4M3:
             m.calibrate(calib)
@@ -215,7 +215,7 @@ def test_chunking_beyond_max_batch(net_files):
     np.testing.assert_array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("tile", [0, 1, 5, 6, 9, 10, 15, 16, 17])
+@pytest.mark.parametrize("tile", [0, 1, 5, 6, 9, 10, 15, 16, 17, 18, 19])
 def test_device_count_variant_matches(net_files, tile):
     """The device-count entry point (grid sized for max_n, tiles strided on the
     device) equals the host-count evaluation, for each kernel family."""
@@ -271,15 +271,40 @@ def test_hipgraph_replay_uneven_batches(net_files):
         assert int((d_h[size:] != -7).sum()) == 0, size  # rows past n untouched
 
 
-def test_hipgraph_replays_match_oracle(net_files):
+def test_persistent_grids_take_every_tile_once(net_files):
+    """Tiles 18 and 19 (persistent grids taking tiles off the stream's atomic
+    counter) at batches with more tiles than blocks, several launches in a row
+    (each launch's last block resets the counter): bitwise equal to the
+    one-block-per-tile kernels, including the rows of the last partial tile."""
+    path = net_files["stp4_res"]
+    st = synth.stp_walks(4, synth.throughput_seeds(16384, 909), lengths=200)
+    packed = hb.hb_encode(1, st)
+    ref = hb.Model(path, prec=hb.HB_BF16, max_batch=16384)
+    ref.set_tile(15)
+    for n in (16384, 12345, 16384):
+        h0, y0 = _eval(ref, packed[:n], 1)
+        for tile in (18, 19):
+            m = hb.Model(path, prec=hb.HB_BF16, max_batch=16384)
+            m.set_tile(tile)
+            for _ in range(3):
+                h, y = _eval(m, packed[:n], 1)
+                np.testing.assert_array_equal(y, y0)
+                np.testing.assert_array_equal(h, h0)
+            m.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("tile", [15, 18])
+def test_hipgraph_replays_match_oracle(net_files, tile):
     """The captured graph against the oracle, not only against the eager path:
     FP32 replays at uneven sizes (the wide-block 256-row tile forced, so a
-    partial last tile and the device-side tile stride are exercised), 40
-    sampled rows per replay against the FP64 forward pass and the output rule."""
+    partial last tile and the device-side tile count are exercised; tile 18 as a
+    persistent grid taking tiles off the counter on every replay), 40 sampled
+    rows per replay against the FP64 forward pass and the output rule."""
     path = net_files["stp4_res"]
     cap = 16384
     m = hb.Model(path, prec=hb.HB_FP32, combine_md=True, max_batch=cap)
-    m.set_tile(15)
+    m.set_tile(tile)
     net = O.Net(path)
     st = synth.stp_walks(4, synth.throughput_seeds(cap, 2025), lengths=200)
     packed = torch.from_numpy(hb.hb_encode(1, st)).cuda()
@@ -392,5 +417,5 @@ def test_switched_off_fused_tiles_are_refused(net_files):
         assert e.value.status == hb.HB_E_UNSUPPORTED
     st = synth.stp_walks(4, synth.throughput_seeds(300, 5), lengths=200)
     report = m.tune(_dev(hb.hb_encode(1, st)))
-    assert report and all(1 <= t <= 10 or 15 <= t <= 17 for t, _ in report)
+    assert report and all(1 <= t <= 10 or 15 <= t <= 19 for t, _ in report)
     m.close()
