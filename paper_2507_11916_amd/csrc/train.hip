@@ -219,27 +219,15 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs a) {
 
 // ------------------------------------------------------------ layer 1
 // dW1[row][c] = sum over states b whose one-hot input has `row` of dz[b][c]
-// (the transpose of the gather-sum), db1[c] = sum_b dz[b][c].
-// Pass 1 (scatter_partial_kernel): a block of NW waves (4; 8 for the cube's
-// 48 cells) owns 64 columns and one chunk of states; its LDS holds every table
-// row's 64 partial sums.  Wave w owns the cells p = w, w + NW, ... (so the rows
-// p*S .. p*S + S - 1): no two waves touch one LDS word, and each wave adds
-// its states in order, so every partial is a fixed sequence of additions; the
-// bias partial (every state) is summed in a register, in order, and wave 0
-// writes it.
-// Per state a wave reads all of its cells' rows (distinct rows), then adds
-// and writes them back: one LDS round trip per state instead of one per cell.
-// (LDS float atomic adds measured several times slower than these plain
-// read-modify-writes, also without a returned value and with no two waves
-// sharing a word: 708 against 75 us per BF16 step.)  Pass 2 (scatter_reduce_kernel) sums the chunks'
-// partials in chunk order into the gradient rows.  No global atomics: the
-// gradient is bitwise repeatable.
+// (the transpose of the gather-sum), db1[c] = sum_b dz[b][c].  Two passes:
+// per-chunk partial sums (scatter_bucket_kernel), then the chunks' partials
+// added in chunk order (scatter_sum_kernel).  No atomics: the gradient is
+// bitwise repeatable.
 template <int DOM>
 struct TrCells {
     static constexpr int P = DOM == 0 ? 9 : DOM == 1 ? 16 : 48;  // gathered cells
     static constexpr int S = DOM == 0 ? 9 : DOM == 1 ? 16 : 6;
     static constexpr int W = DOM == 2 ? 3 : 1;                   // 64-bit words per packed state
-    static constexpr int NW = DOM == 2 ? 8 : 4;                  // waves of a scatter block
     // symbol of cell p of a packed state given as its words (by value, so the
     // words stay in registers; the word is selected, p varies per wave)
     __device__ static int sym(uint64_t w0, uint64_t w1, uint64_t w2, int p) {
@@ -251,104 +239,150 @@ struct TrCells {
 
 int scatter_table_rows(int domain) { return domain == 0 ? 81 : domain == 1 ? 256 : 288; }
 
-// The gradient values of one batch of states for this lane, kept as loaded
-// (raw bits) so that all of the batch's loads are in flight at once; they are
-// converted when added.  The states' packed records are read from LDS.
-template <int T, int DOM, int U>
-struct ScatterBatch {
-    uint32_t v[U];
-    // States past b1 load row b1 - 1 (in bounds; add() skips them), so the
-    // loads are unconditional; the scheduling barrier keeps them ahead of the
-    // previous batch's additions.
-    __device__ __forceinline__ void load(const ScatterArgs& a, int b, int b1, int c) {
-        _Pragma("unroll") for (int u = 0; u < U; u++) {
-            const size_t i = (size_t)min(b + u, b1 - 1) * a.ld + c;
-            v[u] = T == 0 ? reinterpret_cast<const uint32_t*>(a.dz)[i]
-                          : (uint32_t)reinterpret_cast<const uint16_t*>(a.dz)[i];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    // add the batch's states, in order, into this wave's rows; recs holds the
-    // records of the states from rb on
-    __device__ __forceinline__ void add(float* acc, const uint64_t* recs, int rb, int b, int b1, int wave,
-                                        int lane, float& bsum) const {
-        using D = TrCells<DOM>;
-        constexpr int ROWS = D::P * D::S;
-        constexpr int CW = (D::P + D::NW - 1) / D::NW;  // cells per wave
-        constexpr bool RAGGED = D::P % D::NW != 0;      // the last waves own one cell fewer
-        // the batch's records first (one LDS round trip), then one round trip per state
-        uint64_t wr[U][D::W];
-        _Pragma("unroll") for (int u = 0; u < U; u++)
-            _Pragma("unroll") for (int i = 0; i < D::W; i++)
-                wr[u][i] = recs[(size_t)(min(b + u, b1 - 1) - rb) * D::W + i];
-        _Pragma("unroll") for (int u = 0; u < U; u++) {
-            if (b + u < b1) {  // uniform
-                const uint64_t w0 = wr[u][0], w1 = wr[u][D::W > 1 ? 1 : 0], w2 = wr[u][D::W > 2 ? 2 : 0];
-                // No branches around the LDS accesses: a cell a wave does not
-                // own (only when P is not a multiple of the wave count) goes to
-                // that wave's own spare row.
-                int row[CW];
-                float cur[CW];
-                _Pragma("unroll") for (int j = 0; j < CW; j++) {
-                    const int p = wave + D::NW * j;
-                    const bool own = !RAGGED || p < D::P;
-                    row[j] = (own ? p * D::S + D::sym(w0, w1, w2, own ? p : 0) : ROWS + wave) * 64 + lane;
-                }
-                const float x = __uint_as_float(T == 0 ? v[u] : v[u] << 16);
-                _Pragma("unroll") for (int j = 0; j < CW; j++) cur[j] = acc[row[j]];
-                _Pragma("unroll") for (int j = 0; j < CW; j++) acc[row[j]] = cur[j] + x;
-                bsum += x;  // the bias gradient: every state, in order
-            }
-        }
-    }
+// Pass 1 (scatter_bucket_kernel): a block owns 128 columns of
+// one chunk of states and takes the chunk SUB states at a time: their gradient
+// rows (these 128 columns, as float32) and packed records are staged in LDS,
+// after one all-zero row.  Wave w owns the cells p = w, w + NW, ...; per cell
+// it sorts the staged states by the cell's symbol (a stable counting sort on
+// wave ballots), each symbol's bucket padded with the zero row to a multiple
+// of 8 entries, then walks each bucket in order, adding the staged rows into
+// that symbol's two column sums, which stay in registers across the chunk
+// (adding the zero row leaves a sum's bits unchanged).  Each row's partial is
+// thus added in state order; wave 0 also sums every state's row, in order, for
+// the bias.
+template <int DOM>
+struct TrBucket {
+    static constexpr int P = TrCells<DOM>::P, S = TrCells<DOM>::S, W = TrCells<DOM>::W;
+    static constexpr int NW = P < 16 ? P : 16;   // waves of a block
+    static constexpr int CPW = P / NW;           // cells per wave
+    static constexpr int SUB = DOM == 2 ? 128 : 256;  // states staged at a time
+    static constexpr int LIST = SUB + 8 * S;     // a cell's list entries (u16)
+    static constexpr int RB = 512;               // bytes of a staged row (128 float32)
+    static_assert(P % NW == 0, "cells split evenly over the waves");
 };
 
-constexpr int kScatterStage = 256;  // states whose packed records are staged in LDS at a time
-
-// LDS rows of a scatter block: the table's rows, plus one spare row per wave
-// when the cells do not divide evenly over the waves.
 template <int DOM>
-constexpr int scatter_lds_rows() {
-    return TrCells<DOM>::P * TrCells<DOM>::S + (TrCells<DOM>::P % TrCells<DOM>::NW ? TrCells<DOM>::NW : 0);
-}
-
-template <int DOM>
-constexpr size_t scatter_lds_bytes() {
-    return (size_t)scatter_lds_rows<DOM>() * 64 * sizeof(float) +
-           (size_t)kScatterStage * TrCells<DOM>::W * sizeof(uint64_t);
+constexpr size_t scatter_bucket_lds_bytes() {
+    using B = TrBucket<DOM>;
+    return (size_t)(B::SUB + 1) * B::RB + (size_t)B::SUB * B::W * 8 + (size_t)B::P * B::LIST * 2;
 }
 
 template <int T, int DOM>
-__global__ __launch_bounds__(512) void scatter_partial_kernel(ScatterArgs a) {
+__global__ __launch_bounds__(64 * TrBucket<DOM>::NW) void scatter_bucket_kernel(ScatterArgs a) {
     using D = TrCells<DOM>;
-    constexpr int ROWS = D::P * D::S;
-    constexpr int U = D::W == 1 ? 32 : 16;  // states per batch; the next batch loads while one is added
-    constexpr int LROWS = scatter_lds_rows<DOM>();
-    extern __shared__ float acc[];          // [LROWS * 64], then the staged records
-    uint64_t* recs = reinterpret_cast<uint64_t*>(acc + LROWS * 64);
+    using B = TrBucket<DOM>;
+    constexpr int ROWS = D::P * D::S, S = B::S, SUB = B::SUB, CPW = B::CPW, NW = B::NW, RB = B::RB;
+    extern __shared__ __attribute__((aligned(16))) uint8_t sm[];
+    uint8_t* rows = sm;                                                        // [SUB + 1][RB], row SUB all zero
+    uint64_t* recs = reinterpret_cast<uint64_t*>(sm + (size_t)(SUB + 1) * RB);  // [SUB][W]
+    uint16_t* lists = reinterpret_cast<uint16_t*>(sm + (size_t)(SUB + 1) * RB + (size_t)SUB * B::W * 8);  // [P][LIST]
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c = blockIdx.x * 64 + lane;
-    for (int i = threadIdx.x; i < LROWS * 64; i += 64 * D::NW) acc[i] = 0.f;
-    float bsum = 0.f;
-    const uint64_t* packed = reinterpret_cast<const uint64_t*>(a.packed);
+    const int col0 = blockIdx.x * 128;
     const int b0 = blockIdx.y * a.chunk, b1 = min(b0 + a.chunk, a.n);
-    for (int sb = b0; sb < b1; sb += kScatterStage) {
-        const int sb1 = min(sb + kScatterStage, b1);
-        for (int i = threadIdx.x; i < (sb1 - sb) * D::W; i += 64 * D::NW) recs[i] = packed[(size_t)sb * D::W + i];
-        __syncthreads();
-        ScatterBatch<T, DOM, U> x, y;
-        x.load(a, sb, sb1, c);
-        for (int b = sb; b < sb1; b += 2 * U) {
-            y.load(a, b + U, sb1, c);
-            x.add(acc, recs, sb, b, sb1, wave, lane, bsum);
-            x.load(a, b + 2 * U, sb1, c);
-            y.add(acc, recs, sb, b + U, sb1, wave, lane, bsum);
+    if (threadIdx.x < RB / 4) reinterpret_cast<float*>(rows + (size_t)SUB * RB)[threadIdx.x] = 0.f;
+    float acc[CPW][S][2];
+    _Pragma("unroll") for (int j = 0; j < CPW; j++)
+        _Pragma("unroll") for (int v = 0; v < S; v++) acc[j][v][0] = acc[j][v][1] = 0.f;
+    float bs0 = 0.f, bs1 = 0.f;
+    for (int sb = b0; sb < b1; sb += SUB) {
+        const int ns = min(SUB, b1 - sb);
+        // stage the rows as float32 (16-byte pieces of the source, every load in
+        // flight before the first store; rows past the chunk repeat its last
+        // row) and the records
+        constexpr int EPP = T == 0 ? 4 : 8;               // elements per 16-byte source piece
+        constexpr int PPR = 128 / EPP;                    // pieces per row
+        constexpr int PT = (SUB * PPR + 64 * NW - 1) / (64 * NW);  // pieces per thread
+        uint4 pc[PT];
+        _Pragma("unroll") for (int k = 0; k < PT; k++) {
+            const int i = min((int)threadIdx.x + k * 64 * NW, SUB * PPR - 1);
+            const int r = min(i / PPR, ns - 1), q = i % PPR;
+            pc[k] = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(a.dz) +
+                                                    ((size_t)(sb + r) * a.ld + col0 + q * EPP) * (T == 0 ? 4 : 2));
+        }
+        for (int i = threadIdx.x; i < ns * D::W; i += 64 * NW)
+            recs[i] = reinterpret_cast<const uint64_t*>(a.packed)[(size_t)sb * D::W + i];
+        _Pragma("unroll") for (int k = 0; k < PT; k++) {
+            const int i = (int)threadIdx.x + k * 64 * NW;
+            if (i < SUB * PPR) {
+                float* dst = reinterpret_cast<float*>(rows + (size_t)(i / PPR) * RB) + (i % PPR) * EPP;
+                if (T == 0) {
+                    *reinterpret_cast<uint4*>(dst) = pc[k];
+                } else {
+                    const uint32_t w[4] = {pc[k].x, pc[k].y, pc[k].z, pc[k].w};
+                    float4 lo, hi;
+                    lo.x = __uint_as_float(w[0] << 16); lo.y = __uint_as_float(w[0] & 0xffff0000u);
+                    lo.z = __uint_as_float(w[1] << 16); lo.w = __uint_as_float(w[1] & 0xffff0000u);
+                    hi.x = __uint_as_float(w[2] << 16); hi.y = __uint_as_float(w[2] & 0xffff0000u);
+                    hi.z = __uint_as_float(w[3] << 16); hi.w = __uint_as_float(w[3] & 0xffff0000u);
+                    reinterpret_cast<float4*>(dst)[0] = lo;
+                    reinterpret_cast<float4*>(dst)[1] = hi;
+                }
+            }
         }
         __syncthreads();
+        _Pragma("unroll") for (int j = 0; j < CPW; j++) {
+            const int p = wave + NW * j;
+            uint16_t* list = lists + (size_t)p * B::LIST;
+            // counting sort of the staged states by cell p's symbol
+            int cnt[S];
+            _Pragma("unroll") for (int v = 0; v < S; v++) cnt[v] = 0;
+            _Pragma("unroll") for (int q = 0; q < SUB / 64; q++) {
+                const int b = q * 64 + lane;
+                const uint64_t* rc = recs + (size_t)min(b, ns - 1) * D::W;
+                const int sy = b < ns ? D::sym(rc[0], rc[D::W > 1 ? 1 : 0], rc[D::W > 2 ? 2 : 0], p) : S;
+                _Pragma("unroll") for (int v = 0; v < S; v++) cnt[v] += __popcll(__ballot(sy == v));
+            }
+            int off[S + 1];
+            off[0] = 0;
+            _Pragma("unroll") for (int v = 0; v < S; v++) off[v + 1] = off[v] + ((cnt[v] + 7) & ~7);
+            _Pragma("unroll") for (int v = 0; v < S; v++)  // the padding: the zero row
+                if (lane < off[v + 1] - off[v] - cnt[v]) list[off[v] + cnt[v] + lane] = (uint16_t)SUB;
+            int run[S];
+            _Pragma("unroll") for (int v = 0; v < S; v++) run[v] = off[v];
+            _Pragma("unroll") for (int q = 0; q < SUB / 64; q++) {
+                const int b = q * 64 + lane;
+                const uint64_t* rc = recs + (size_t)min(b, ns - 1) * D::W;
+                const int sy = b < ns ? D::sym(rc[0], rc[D::W > 1 ? 1 : 0], rc[D::W > 2 ? 2 : 0], p) : S;
+                int pos = 0;
+                _Pragma("unroll") for (int v = 0; v < S; v++) {
+                    const uint64_t m = __ballot(sy == v);
+                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                    pos = sy == v ? run[v] + below : pos;
+                    run[v] += __popcll(m);
+                }
+                if (sy < S) list[pos] = (uint16_t)b;
+            }
+            // each bucket in order, eight staged rows in flight
+            _Pragma("unroll") for (int v = 0; v < S; v++) {
+                for (int k = off[v]; k < off[v + 1]; k += 8) {
+                    float2 x[8];
+                    _Pragma("unroll") for (int i = 0; i < 8; i++)
+                        x[i] = *reinterpret_cast<const float2*>(rows + (size_t)list[k + i] * RB + lane * 8);
+                    _Pragma("unroll") for (int i = 0; i < 8; i++) {
+                        acc[j][v][0] += x[i].x;
+                        acc[j][v][1] += x[i].y;
+                    }
+                }
+            }
+        }
+        if (wave == 0) {  // the bias partial: every staged state, in order
+            for (int b = 0; b < ns; b += 8) {
+                float2 x[8];
+                _Pragma("unroll") for (int i = 0; i < 8; i++)
+                    x[i] = *reinterpret_cast<const float2*>(rows + (size_t)(b + i < ns ? b + i : SUB) * RB + lane * 8);
+                _Pragma("unroll") for (int i = 0; i < 8; i++) {
+                    bs0 += x[i].x;
+                    bs1 += x[i].y;
+                }
+            }
+        }
+        __syncthreads();  // the next stage overwrites rows, records and lists
     }
-    float* out = a.partial + (size_t)blockIdx.y * (ROWS + 1) * a.N1 + c;
-    for (int r = wave; r < ROWS; r += D::NW) out[(size_t)r * a.N1] = acc[r * 64 + lane];
-    if (wave == 0) out[(size_t)ROWS * a.N1] = bsum;
+    float* out = a.partial + (size_t)blockIdx.y * (ROWS + 1) * a.N1 + col0 + 2 * lane;
+    _Pragma("unroll") for (int j = 0; j < CPW; j++)
+        _Pragma("unroll") for (int v = 0; v < S; v++)
+            *reinterpret_cast<float2*>(out + (size_t)((wave + NW * j) * S + v) * a.N1) = make_float2(acc[j][v][0], acc[j][v][1]);
+    if (wave == 0) *reinterpret_cast<float2*>(out + (size_t)ROWS * a.N1) = make_float2(bs0, bs1);
 }
 
 // Table row -> gradient row (the weight file's order).  Cube: non-centre
@@ -360,35 +394,37 @@ __device__ __forceinline__ int grad_row(int r) {
     return (q + q / 8 + (q % 8 >= 4 ? 1 : 0)) * 6 + col;
 }
 
-// A block takes 64 columns of one row; its 16 groups of 64 threads each add
-// an equal run of chunks in order, then the group sums are added in group
-// order (a fixed summation order).
+// Pass 2: a thread takes four columns of one row and adds the chunks'
+// partials in chunk order (eight loads in flight), then writes the gradient
+// row (the bias row to db1).
 template <int DOM>
-__global__ __launch_bounds__(1024) void scatter_reduce_kernel(ScatterArgs a, int chunks) {
+__global__ __launch_bounds__(256) void scatter_sum_kernel(ScatterArgs a, int chunks) {
     using D = TrCells<DOM>;
     constexpr int ROWS = D::P * D::S;
-    __shared__ float gs[16][64];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int per = (chunks + 15) / 16, k0 = ty * per, k1 = min(chunks, k0 + per);
-    const int cblocks = a.N1 / 64;
-    for (int blk = blockIdx.x; blk < (ROWS + 1) * cblocks; blk += gridDim.x) {
-        const int r = blk / cblocks, c = (blk % cblocks) * 64 + tx;
-        float part = 0.f;
-        for (int k = k0; k < k1; k++) part += a.partial[((size_t)k * (ROWS + 1) + r) * a.N1 + c];
-        gs[ty][tx] = part;
-        __syncthreads();
-        float s = 0.f;
-        if (ty == 0)
-            for (int g = 0; g < 16; g++) s += gs[g][tx];
-        __syncthreads();
-        if (ty != 0) continue;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int c4 = a.N1 / 4;
+    const int64_t total = (int64_t)(ROWS + 1) * c4;
+    for (int64_t t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+        const int r = (int)(t / c4), c = (int)(t % c4) * 4;
+        const float* p = a.partial + (size_t)r * a.N1 + c;
+        const size_t stride = (size_t)(ROWS + 1) * a.N1;
+        f4 acc = *reinterpret_cast<const f4*>(p);
+        for (int k0 = 1; k0 < chunks; k0 += 8) {
+            const int cnt = min(8, chunks - k0);
+            f4 v[8];
+            _Pragma("unroll") for (int u = 0; u < 8; u++)
+                if (u < cnt) v[u] = *reinterpret_cast<const f4*>(p + (size_t)(k0 + u) * stride);
+            _Pragma("unroll") for (int u = 0; u < 8; u++)
+                if (u < cnt) acc += v[u];
+        }
         if (r < ROWS) {
-            a.dW1[(size_t)grad_row<DOM>(r) * a.ld_w + c] = s;
+            *reinterpret_cast<f4*>(a.dW1 + (size_t)grad_row<DOM>(r) * a.ld_w + c) = acc;
         } else {
-            a.db1[c] = s;
+            *reinterpret_cast<f4*>(a.db1 + c) = acc;
             if (DOM == 2)  // centre f always shows colour f: its row's gradient is the bias gradient
                 for (int f = 0; f < 6; f++)
-                    for (int col = 0; col < 6; col++) a.dW1[(size_t)((9 * f + 4) * 6 + col) * a.ld_w + c] = col == f ? s : 0.f;
+                    for (int col = 0; col < 6; col++)
+                        *reinterpret_cast<f4*>(a.dW1 + (size_t)((9 * f + 4) * 6 + col) * a.ld_w + c) = col == f ? acc : f4{0.f, 0.f, 0.f, 0.f};
         }
     }
 }
@@ -527,14 +563,14 @@ void launch_column_sum(const float* part, int rows, int cols, int ld, float* out
 
 template <int T, int DOM>
 static void launch_scatter_t(const ScatterArgs& a, int chunks, hipStream_t s) {
-    const size_t lds = scatter_lds_bytes<DOM>();
-    hipLaunchKernelGGL((scatter_partial_kernel<T, DOM>), dim3(a.N1 / 64, chunks), dim3(64 * TrCells<DOM>::NW), lds, s, a);
-    const int blocks = std::min(2048, (scatter_table_rows(DOM) + 1) * (a.N1 / 64));
-    hipLaunchKernelGGL((scatter_reduce_kernel<DOM>), dim3(blocks), dim3(1024), 0, s, a, chunks);
+    hipLaunchKernelGGL((scatter_bucket_kernel<T, DOM>), dim3(a.N1 / 128, chunks), dim3(64 * TrBucket<DOM>::NW),
+                       scatter_bucket_lds_bytes<DOM>(), s, a);
+    const int blocks = (int)std::min<int64_t>(2048, ((int64_t)(scatter_table_rows(DOM) + 1) * (a.N1 / 4) + 255) / 256);
+    hipLaunchKernelGGL((scatter_sum_kernel<DOM>), dim3(blocks), dim3(256), 0, s, a, chunks);
 }
 
 bool launch_scatter_l1(const ScatterArgs& a, int t, int domain, int chunks, hipStream_t s) {
-    if (a.N1 % 64 || chunks < 1 || domain < 0 || domain > 2 || t < 0 || t > 1) return false;
+    if (a.N1 % 128 || chunks < 1 || domain < 0 || domain > 2 || t < 0 || t > 1) return false;
     switch (domain * 2 + t) {
         case 0: launch_scatter_t<0, 0>(a, chunks, s); break;
         case 1: launch_scatter_t<1, 0>(a, chunks, s); break;
@@ -555,8 +591,8 @@ void launch_multi_adam(const AdamTensor* d_tensors, int count, float lr, float b
 
 template <int T, int DOM>
 static hipError_t set_scatter_attr() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&scatter_partial_kernel<T, DOM>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_lds_bytes<DOM>());
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&scatter_bucket_kernel<T, DOM>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)scatter_bucket_lds_bytes<DOM>());
 }
 
 // The layer-1 scatter holds up to 289 x 64 floats and 256 staged records of LDS per block.

@@ -38,7 +38,7 @@ struct ScatterArgs {
     const void* dz;      // [n][ld] gradient at layer 1's pre-activation (type t)
     int ld;
     const void* packed;  // [n] packed states (hb_encode layout)
-    int n, N1;           // N1: padded width, multiple of 64
+    int n, N1;           // N1: padded width, multiple of 128
     float* partial;      // [chunks][table rows + 1][N1] per-chunk sums (last row: bias)
     int chunk;           // states per chunk
     float* dW1;          // [gradient rows][ld_w], the weight file's row order

@@ -24,7 +24,7 @@
 namespace hb {
 namespace {
 
-constexpr int kScatterChunks = 32;  // state chunks of the layer-1 scatter (its blocks: chunks x N1 / 64)
+constexpr int kScatterChunks = 32;  // state chunks of the layer-1 scatter (its blocks: chunks x N1 / 128)
 constexpr int kSplitMax = 8;       // K slices of a split-K weight gradient
 
 struct TLayer {
