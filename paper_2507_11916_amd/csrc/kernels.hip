@@ -272,6 +272,10 @@ struct GemmArgs {
     // dynamic tile schedule (a persistent grid): tiles after a block's first
     // come off tile_ctr[0]; tile_ctr[1] counts the blocks that have left
     int* tile_ctr = nullptr;
+    // optional transposed copy of C (wide tile only): element (m, n) also at
+    // Ct[n * ldct + m]; every row a tile writes is below ldct
+    uint8_t* Ct = nullptr;
+    int ldct = 0;
 };
 
 // Dynamic tile schedule.  A block's first tile is its own (the XCD-aware order
@@ -332,8 +336,9 @@ __device__ __forceinline__ float load_at(const uint8_t* p, uint32_t byte_off, fl
     return fp8_to_f32(p[byte_off]) * fp8_scale;
 }
 
+// epi_tile_v returns the values it stored (the wide tile's transposed copy).
 template <int OUTT, bool COH = false>
-__device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc, float sn, float bn, int o0) {
+__device__ __forceinline__ floatx16 epi_tile_v(const GemmArgs& g, const floatx16& acc, float sn, float bn, int o0) {
     constexpr uint32_t EO = OUTT == 0 ? 4 : OUTT == 1 ? 2 : 1;
     const uint32_t b0 = (uint32_t)o0 * EO, row = (uint32_t)g.ldc * EO;
     float rv[16], mk[16];
@@ -345,12 +350,14 @@ __device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc,
         _Pragma("unroll") for (int e = 0; e < 16; e++)
             mk[e] = load_at<OUTT>(g.Mk, b0 + (8 * (e >> 2) + (e & 3)) * row, 1.f);
     }
+    floatx16 vt;
     _Pragma("unroll") for (int e = 0; e < 16; e++) {
         const uint32_t o = b0 + (8 * (e >> 2) + (e & 3)) * row;
         float v = acc[e] * sn + bn;
         if (g.R) v += rv[e];
         if (g.relu) v = fmaxf(v, 0.f);
         if (g.Mk) v = mk[e] > 0.f ? v : 0.f;
+        vt[e] = v;
         if (COH) {
             if (OUTT == 0) st_coh(reinterpret_cast<uint32_t*>(g.C + o), __float_as_uint(v));
             else if (OUTT == 1) st_coh(reinterpret_cast<uint16_t*>(g.C + o), f32_to_bf16(v));
@@ -364,6 +371,12 @@ __device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc,
         }
     }
     asm volatile("" ::: "memory");  // one tile's loads at a time: bounded register use
+    return vt;
+}
+
+template <int OUTT, bool COH = false>
+__device__ __forceinline__ void epi_tile(const GemmArgs& g, const floatx16& acc, float sn, float bn, int o0) {
+    (void)epi_tile_v<OUTT, COH>(g, acc, sn, bn, o0);
 }
 
 // MFMAs of one 128-byte K stage held in LDS (a_s: BM rows, b_s: BN rows, both
@@ -792,7 +805,7 @@ __device__ __forceinline__ void mma_stage_pre(const uint8_t* a_s, const uint8_t*
 // a SIMD the one with operands in registers goes first instead of both reading
 // LDS and then both multiplying.  Same per-element MFMA sequence and epilogue
 // as the other tiles: bitwise equal results.
-template <int PREC, int OUTT, int NW, int NS>
+template <int PREC, int OUTT, int NW, int NS, bool TC = false>
 __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
     constexpr int BM = 256, BN = 128, NT = NW * 64;
     constexpr int EB = Ty<PREC>::EB;
@@ -871,12 +884,45 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
         const int half = lane >> 5, c32 = lane & 31;
         GemmArgs gs = g;  // slice sl writes its own C
         if (sl) gs.C = g.C + (size_t)sl * g.c_split * (OUTT == 0 ? 4 : OUTT == 1 ? 2 : 1);
+        floatx16 vt[TI][TJ];
         _Pragma("unroll") for (int j = 0; j < TJ; j++) {
             const int n = n0 + wn * (TJ * 32) + j * 32 + c32;
             const float bn = g.bias ? g.bias[n] : 0.f;
             const float sn = PREC == 2 ? g.colscale[n] * g.a_scale : 1.f;
-            _Pragma("unroll") for (int i = 0; i < TI; i++)
-                epi_tile<OUTT>(gs, acc[i][j], sn, bn, (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n);
+            _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                const int o0 = (m0 + wm * 64 + i * 32 + 4 * half) * g.ldc + n;
+                if (TC) vt[i][j] = epi_tile_v<OUTT>(gs, acc[i][j], sn, bn, o0);
+                else epi_tile<OUTT>(gs, acc[i][j], sn, bn, o0);
+            }
+        }
+        if (TC && OUTT != 2) {
+            // Transposed copy through LDS: each wave turns its 64 x (TJ 32)
+            // region into rows of Ct (MR rows of C, 128 bytes, per pass), so
+            // every store is 16 bytes and a row gets whole 128-byte lines.
+            constexpr int EO = OUTT == 0 ? 4 : 2, MR = 128 / EO, RS = 144;  // LDS row stride: 128 bytes + 16
+            __syncthreads();  // every wave is done with the ring
+            uint8_t* reg = smem + (size_t)wave * (TJ * 32) * RS;
+            _Pragma("unroll") for (int rd = 0; rd < 64 / MR; rd++) {
+                _Pragma("unroll") for (int i = rd * (MR / 32); i < (rd + 1) * (MR / 32); i++)
+                    _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                        _Pragma("unroll") for (int a4 = 0; a4 < 4; a4++) {
+                            const floatx16& v = vt[i][j];
+                            uint8_t* d = reg + (32 * j + c32) * RS + ((i - rd * (MR / 32)) * 32 + 8 * a4 + 4 * half) * EO;
+                            if (OUTT == 0) {
+                                *reinterpret_cast<float4*>(d) = make_float4(v[4 * a4], v[4 * a4 + 1], v[4 * a4 + 2], v[4 * a4 + 3]);
+                            } else {
+                                const uint32_t lo = f32_to_bf16(v[4 * a4]) | ((uint32_t)f32_to_bf16(v[4 * a4 + 1]) << 16);
+                                const uint32_t hi = f32_to_bf16(v[4 * a4 + 2]) | ((uint32_t)f32_to_bf16(v[4 * a4 + 3]) << 16);
+                                *reinterpret_cast<uint2*>(d) = make_uint2(lo, hi);
+                            }
+                        }
+                _Pragma("unroll") for (int q = 0; q < TJ * 4; q++) {
+                    const int cidx = q * 64 + lane, n = cidx >> 3, part = cidx & 7;
+                    const u32x4 val = *reinterpret_cast<const u32x4*>(reg + n * RS + part * 16);
+                    uint8_t* dst = g.Ct + ((size_t)(n0 + wn * (TJ * 32) + n) * g.ldct + m0 + wm * 64 + rd * MR) * EO + part * 16;
+                    *reinterpret_cast<u32x4*>(dst) = val;
+                }
+            }
         }
         if (dyn) {
             __syncthreads();
@@ -1422,6 +1468,7 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;
@@ -1446,6 +1493,7 @@ static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
     hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
@@ -1460,6 +1508,7 @@ static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;
@@ -1480,6 +1529,7 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     const int m_tiles = (L.m_cap + 255) / 256;
     const int tiles = m_tiles * (L.N / 128);
     g.m_tiles_cap = m_tiles;
@@ -1490,7 +1540,7 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL((gemm_w8_kernel<PREC, OUTT>), dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, g);
 }
 
-template <int PREC, int OUTT, int NW, int NS>
+template <int PREC, int OUTT, int NW, int NS, bool TC = false>
 static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     GemmArgs g;
     g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
@@ -1499,6 +1549,7 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     g.split = L.split > 1 ? L.split : 1;
     g.c_split = L.c_split;
     const int m_tiles = (L.m_cap + 255) / 256;
@@ -1512,8 +1563,8 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
         g.tile_ctr = L.tile_ctr;
     }
     if (L.m_dev) g.persistent = 1;
-    hipLaunchKernelGGL((gemm_wide_kernel<PREC, OUTT, NW, NS>), dim3(grid), dim3(NW * 64), (size_t)NS * (256 + 128) * 128,
-                       s, g);
+    hipLaunchKernelGGL((gemm_wide_kernel<PREC, OUTT, NW, NS, TC>), dim3(grid), dim3(NW * 64),
+                       (size_t)NS * (256 + 128) * 128, s, g);
 }
 
 // Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the
@@ -1561,7 +1612,13 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
         case 7: launch_gemm_ring<PREC, OUTT, 128, 256, 3>(L, s); return true;
         case 8: launch_gemm_ring<PREC, OUTT, 64, 128, 4>(L, s); return true;
         case 9: launch_gemm_w8<PREC, OUTT>(L, s); return true;
-        case 14: launch_gemm_wide<PREC, OUTT, 8, 2>(L, s); return true;
+        case 14:
+            if (L.Ct) {
+                if constexpr (OUTT != 2) launch_gemm_wide<PREC, OUTT, 8, 2, true>(L, s);
+            } else {
+                launch_gemm_wide<PREC, OUTT, 8, 2>(L, s);
+            }
+            return true;
         case 15: launch_gemm_wide<PREC, OUTT, 8, 3>(L, s); return true;
         case 16: launch_gemm_wide<PREC, OUTT, 16, 2>(L, s); return true;
         case 17: {
@@ -1586,6 +1643,11 @@ bool launch_gemm(const GemmLaunch& L, hipStream_t s) {
         const int eb = L.prec == 0 ? 4 : L.prec == 1 ? 2 : 1;
         if (L.tile < 14 || L.tile > 17 || L.K % L.split != 0 || (L.K / L.split) * eb % 128 != 0 || L.m_dev ||
             L.R || L.Mk)
+            return false;
+    }
+    if (L.Ct) {  // transposed copy: tile 14, float32 or bf16 C, host row count, whole tiles below ldct
+        if (L.tile != 14 || out == 2 || L.split > 1 || L.m_dev || L.persistent_grid > 0 || L.ldct % 8 ||
+            L.ldct < (L.m_cap + 255) / 256 * 256)
             return false;
     }
     if (L.prec == 0 && out == 0) return launch_gemm_p<0, 0>(L, s);
@@ -1621,6 +1683,7 @@ static GemmArgs gemm_args_of(const GemmLaunch& L) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
     return g;
@@ -1695,8 +1758,13 @@ static hipError_t set_ring_attr() {
 
 template <int PREC, int OUTT, int NW, int NS>
 static hipError_t set_wide_attr() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_wide_kernel<PREC, OUTT, NW, NS>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, NS * (256 + 128) * 128);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_wide_kernel<PREC, OUTT, NW, NS>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, NS * (256 + 128) * 128);
+    if constexpr (OUTT != 2 && NW == 8 && NS == 2)
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_wide_kernel<PREC, OUTT, NW, NS, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, NS * (256 + 128) * 128);
+    return e;
 }
 
 template <int PREC, int OUTT>

@@ -53,6 +53,12 @@ struct GemmLaunch {
     // after their first off tile_ctr[0] (each launch leaves both at zero).
     // Null: a persistent grid strides over the tiles statically.
     int* tile_ctr = nullptr;
+    // Optional transposed copy of C (tile 14, float32 or bf16 outputs, no
+    // split or persistent grid): element (m, n) also written at
+    // Ct[n * ldct + m]; ldct a multiple of 8 and at least M rounded up to 256
+    // (the rows the tiles cover).  Null: none.
+    void* Ct = nullptr;
+    int ldct = 0;
 };
 
 struct HeadArgs {

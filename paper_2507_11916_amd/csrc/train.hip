@@ -513,8 +513,12 @@ bool launch_head_train(const HeadTrainArgs& a, int t, hipStream_t s) {
     if (t == 0) hipLaunchKernelGGL(head_train_kernel<0>, dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(head_train_kernel<1>, dim3(blocks), dim3(256), 0, s, a);
     // output-weight gradient, bias gradient and loss: the blocks' partials in order
-    launch_column_sum(a.part, blocks, a.K, a.K + 2, a.dWo, s);
-    launch_column_sum(a.part + a.K, blocks, 2, a.K + 2, a.dbo_loss, s);
+    if (a.dbo_loss == a.dWo + a.K) {  // contiguous: one launch
+        launch_column_sum(a.part, blocks, a.K + 2, a.K + 2, a.dWo, s);
+    } else {
+        launch_column_sum(a.part, blocks, a.K, a.K + 2, a.dWo, s);
+        launch_column_sum(a.part + a.K, blocks, 2, a.K + 2, a.dbo_loss, s);
+    }
     return true;
 }
 
@@ -523,6 +527,52 @@ void launch_transpose(const TransposeArgs& a, int t, hipStream_t s) {
     if (t == 0) hipLaunchKernelGGL(transpose_kernel<0>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(transpose_kernel<1>, grid, dim3(256), 0, s, a);
     if (a.colpart) launch_column_sum(a.colpart, (a.rows_sum + 63) / 64, a.C, a.C, a.colsum, s);
+}
+
+// out[r] = sum over b < n of X[r * ld + b] (X float32 or bf16, ld a multiple
+// of 8), for r < rows: the bias gradient from a transposed gradient.  A block
+// of four waves takes one row, wave w the w-th quarter of the 16-byte pieces
+// (pieces w, w + 4, ... per lane-position); a lane adds its pieces in order
+// (eight loads in flight), the lanes' sums meet in a fixed butterfly and the
+// four wave sums are added in wave order, so the result is bitwise repeatable.
+template <int T>
+__global__ __launch_bounds__(256) void row_sum_kernel(const void* X, int ld, int rows, int n, float* out) {
+    __shared__ float ws[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = blockIdx.x;
+    const size_t base = (size_t)r * ld;
+    constexpr int E = T == 0 ? 4 : 8;  // elements per 16-byte load
+    float acc = 0.f;
+    for (int b0 = E * (wave * 64 + lane); b0 < n; b0 += 8 * 256 * E) {
+        float x[8][E];
+        _Pragma("unroll") for (int u = 0; u < 8; u++) {
+            const int b = min(b0 + u * 256 * E, ld - E);  // in bounds; elements at or past n are masked
+            const uint4 v = T == 0 ? *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(X) + base + b)
+                                   : *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(X) + base + b);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            _Pragma("unroll") for (int i = 0; i < 4; i++) {
+                if (T == 0) {
+                    x[u][i] = __uint_as_float(w[i]);
+                } else {
+                    x[u][2 * i] = __uint_as_float(w[i] << 16);
+                    x[u][2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+                }
+            }
+        }
+        _Pragma("unroll") for (int u = 0; u < 8; u++)
+            _Pragma("unroll") for (int i = 0; i < E; i++)
+                acc += b0 + u * 256 * E + i < n ? x[u][i] : 0.f;
+    }
+    _Pragma("unroll") for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) ws[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[r] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+void launch_row_sum(const void* X, int ld, int rows, int n, float* out, int t, hipStream_t s) {
+    const int blocks = rows;
+    if (t == 0) hipLaunchKernelGGL(row_sum_kernel<0>, dim3(blocks), dim3(256), 0, s, X, ld, rows, n, out);
+    else hipLaunchKernelGGL(row_sum_kernel<1>, dim3(blocks), dim3(256), 0, s, X, ld, rows, n, out);
 }
 
 // out[r][c] = sum over slices s < split of part[s * stride + r * ldp + c], added

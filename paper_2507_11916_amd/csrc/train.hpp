@@ -58,6 +58,8 @@ void launch_transpose(const TransposeArgs& a, int t, hipStream_t s);
 // Layer-1 weight and bias gradients (transpose of the gather-sum), in a fixed
 // summation order: bitwise repeatable.
 bool launch_scatter_l1(const ScatterArgs& a, int t, int domain, int chunks, hipStream_t s);
+// out[r] = sum over b < n of X[r * ld + b] (type t), r < rows, in a fixed order.
+void launch_row_sum(const void* X, int ld, int rows, int n, float* out, int t, hipStream_t s);
 
 // Every parameter tensor's Adam step in one launch (one grid row per tensor).
 struct AdamTensor {

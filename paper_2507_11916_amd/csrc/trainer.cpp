@@ -1,11 +1,13 @@
 // On-GPU training of a sliding-tile regression network (hb_trainer, include/hb.h).
 //
-// Step: forward with every activation saved; head kernel (loss, dL/dy,
-// output-layer gradient); backward through residual blocks and dense layers
-// with input-gradient GEMMs (fused ReLU mask and residual add) and weight-
-// gradient GEMMs on transposed activations (FP32 output, bias gradients as
-// column sums fused into the transposes); layer-1 gradient by scatter-add;
-// Adam on FP32 master weights, re-casting the working copies.
+// Step: forward with every activation saved (the products' epilogues also
+// write each activation transposed, the operand layout of the weight
+// gradients); head kernel (loss, dL/dy, output-layer gradient); backward
+// through residual blocks and dense layers with input-gradient GEMMs (fused
+// ReLU mask and residual add, transposed copy) and weight-gradient GEMMs
+// (FP32 output; bias gradients as row sums of the transposed gradients);
+// layer-1 gradient by scatter-add; Adam on FP32 master weights, re-casting
+// the working copies.
 #include <algorithm>
 #include <hip/hip_runtime.h>
 
@@ -76,7 +78,11 @@ struct hb_trainer {
     std::vector<hb::TLayer> L;
     int n_act = 0;
     std::vector<void*> act;
-    void *G = nullptr, *G2 = nullptr, *XT = nullptr, *GT = nullptr;
+    void *G = nullptr, *G2 = nullptr, *GT = nullptr, *GT2 = nullptr;
+    // transposed activations ([W_pad][M_pad]) for the weight-gradient products:
+    // written by the forward products' epilogues (act 0 by a transpose); null
+    // for activations no layer reads
+    std::vector<void*> actT;
     float* d_loss = nullptr;
     int step = 0;
     std::vector<void*> allocs;
@@ -123,7 +129,8 @@ hb_status up_work(hb_trainer* tr, const std::vector<float>& vals, void** d) {
 }
 
 hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, void* C, int ldc, const void* R,
-               const void* Mk, const float* bias, int M, int N, int K, int relu, int out_type, hipStream_t s) {
+               const void* Mk, const float* bias, int M, int N, int K, int relu, int out_type, hipStream_t s,
+               void* Ct = nullptr) {
     GemmLaunch g{};
     g.prec = tr->t;
     g.out_type = out_type;
@@ -132,13 +139,16 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
     g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.a_scale = g.r_scale = g.out_inv_scale = 1.f;
     g.relu = relu;
-    // Forward and input-gradient products: the 8-wave 256x128 ring tile, or
-    // 64x128 for small batches.  Weight gradients (K, the batch, far longer than
+    g.Ct = Ct;  // transposed copy of C (rows below M_pad)
+    g.ldct = tr->M_pad;
+    // Forward and input-gradient products: the 8-wave 256x128 ring tile (the
+    // one that writes a transposed copy), or 64x128 for small batches without
+    // one.  Weight gradients (K, the batch, far longer than
     // M and N): FP32 takes the one-wave 32x32 tile (8x the tiles of 64x128 on a
     // 1000 x 1000 output; 12% faster per FP32 step), BF16 the 64x128 tile with a
     // 4-stage LDS ring (more of the long K in flight; 8% faster per BF16 step).
     const bool wgrad = K >= 4 * std::max(M, N);
-    g.tile = wgrad ? (tr->t == 0 ? 4 : 8) : (N % 128 == 0 && M >= 2048) ? 14 : 2;
+    g.tile = wgrad ? (tr->t == 0 ? 4 : 8) : (Ct || (N % 128 == 0 && M >= 2048)) ? 14 : 2;  // (a transposed copy: tile 14)
     // BF16 weight gradients of wide layers: split-K on the 256x128 tile (the
     // 1000 x 1000 output alone is 32 such tiles), partial products in wsplit,
     // then summed in slice order (deterministic).
@@ -198,7 +208,8 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     hb_status st;
     for (auto& l : tr->L) {
         st = gemm(tr, tr->act[l.in_act], tr->W_pad, l.Wt, l.K_pad, tr->act[l.out_act], tr->W_pad,
-                  l.res_act >= 0 ? tr->act[l.res_act] : nullptr, nullptr, l.bias, Me, l.N_pad, l.K_pad, 1, -1, s);
+                  l.res_act >= 0 ? tr->act[l.res_act] : nullptr, nullptr, l.bias, Me, l.N_pad, l.K_pad, 1, -1, s,
+                  tr->actT[l.out_act]);
         if (st != HB_OK) return st;
     }
     HeadTrainArgs h{};
@@ -219,39 +230,54 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     h.dbo_loss = tr->dbo;  // dbo, then the loss
     if (!launch_head_train(h, t, s)) return fail(HB_E_UNSUPPORTED, "head width");
     HB_HIP(hipGetLastError());
-    // backward: cur holds the gradient at the pre-activation of the current layer output
+    // backward: cur holds the gradient at the pre-activation of the current layer
+    // output, curT its transpose ([N][M_pad], the weight-gradient operand).  The
+    // input-gradient products write both; the head's gradient is transposed
+    // here, its column sums giving the last layer's bias gradient.
+    const int ldT = tr->M_pad;
+    if ((st = transpose(tr, tr->act[0], tr->W_pad, tr->actT[0], ldT, Me, tr->L[0].K_pad, nullptr, 0, s)) != HB_OK)
+        return st;
     void* cur = tr->G;
     void* other = tr->G2;
+    void* curT = tr->GT;
+    void* otherT = tr->GT2;
+    if ((st = transpose(tr, cur, tr->W_pad, curT, ldT, Me, tr->L.back().N_pad, tr->L.back().db, n, s)) != HB_OK) return st;
+    bool db_done = true;
     for (int j = (int)tr->L.size() - 1; j >= 0; j--) {
         TLayer& l = tr->L[j];
         const bool res_b = l.res_act >= 0;
         // weight and bias gradient: dW = X^T cur, db = column sums of cur
-        if ((st = transpose(tr, cur, tr->W_pad, tr->GT, Me, Me, l.N_pad, l.db, n, s)) != HB_OK) return st;
-        if ((st = transpose(tr, tr->act[l.in_act], tr->W_pad, tr->XT, Me, Me, l.K_pad, nullptr, 0, s)) != HB_OK) return st;
-        if ((st = gemm(tr, tr->XT, Me, tr->GT, Me, l.dW, l.N_pad, nullptr, nullptr, nullptr, l.K_pad, l.N_pad, Me, 0, 0, s)) != HB_OK)
+        if (!db_done) {
+            launch_row_sum(curT, ldT, l.N_pad, n, l.db, t, s);
+            HB_HIP(hipGetLastError());
+        }
+        db_done = false;
+        if ((st = gemm(tr, tr->actT[l.in_act], ldT, curT, ldT, l.dW, l.N_pad, nullptr, nullptr, nullptr, l.K_pad, l.N_pad, Me,
+                       0, 0, s)) != HB_OK)
             return st;
         // input gradient, masked by the input activation (post-ReLU, so > 0 marks the active units)
         if (res_b) {
             // t-gradient of a residual block: (cur W_b^T) * [t > 0]; keep cur for the identity path
             if ((st = gemm(tr, cur, tr->W_pad, l.Wkn, l.N_pad, other, tr->W_pad, nullptr, tr->act[l.in_act], nullptr, Me,
-                           l.K_pad, l.N_pad, 0, -1, s)) != HB_OK)
+                           l.K_pad, l.N_pad, 0, -1, s, otherT)) != HB_OK)
                 return st;
             TLayer& la = tr->L[j - 1];
-            if ((st = transpose(tr, other, tr->W_pad, tr->GT, Me, Me, la.N_pad, la.db, n, s)) != HB_OK) return st;
-            if ((st = transpose(tr, tr->act[la.in_act], tr->W_pad, tr->XT, Me, Me, la.K_pad, nullptr, 0, s)) != HB_OK) return st;
-            if ((st = gemm(tr, tr->XT, Me, tr->GT, Me, la.dW, la.N_pad, nullptr, nullptr, nullptr, la.K_pad, la.N_pad, Me, 0, 0, s)) !=
-                HB_OK)
+            launch_row_sum(otherT, ldT, la.N_pad, n, la.db, t, s);
+            HB_HIP(hipGetLastError());
+            if ((st = gemm(tr, tr->actT[la.in_act], ldT, otherT, ldT, la.dW, la.N_pad, nullptr, nullptr, nullptr, la.K_pad,
+                           la.N_pad, Me, 0, 0, s)) != HB_OK)
                 return st;
-            // x-gradient: (t-grad W_a^T + cur) * [x_in > 0], written over cur
+            // x-gradient: (t-grad W_a^T + cur) * [x_in > 0], written over cur (and its transpose when a layer is below)
             if ((st = gemm(tr, other, tr->W_pad, la.Wkn, la.N_pad, cur, tr->W_pad, cur, tr->act[la.in_act], nullptr, Me,
-                           la.K_pad, la.N_pad, 0, -1, s)) != HB_OK)
+                           la.K_pad, la.N_pad, 0, -1, s, j - 1 > 0 ? curT : nullptr)) != HB_OK)
                 return st;
             j--;  // the block's first layer is done
         } else {
             if ((st = gemm(tr, cur, tr->W_pad, l.Wkn, l.N_pad, other, tr->W_pad, nullptr, tr->act[l.in_act], nullptr, Me,
-                           l.K_pad, l.N_pad, 0, -1, s)) != HB_OK)
+                           l.K_pad, l.N_pad, 0, -1, s, j > 0 ? otherT : nullptr)) != HB_OK)
                 return st;
             std::swap(cur, other);
+            std::swap(curT, otherT);
         }
     }
     ScatterArgs sa{};
@@ -443,7 +469,9 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     }
     if ((st = up_f32(T, TS[ti + 1], &T->ho_b)) != HB_OK) return st;
     if ((st = dalloc_t(T, 1, &T->ho_bm)) != HB_OK || (st = dalloc_t(T, 1, &T->ho_bv)) != HB_OK) return st;
-    if ((st = dalloc_t(T, T->H_pad, &T->dWo)) != HB_OK || (st = dalloc_t(T, 2, &T->dbo)) != HB_OK) return st;
+    // dWo [H_pad], then dbo and the loss: one column-sum launch writes all three
+    if ((st = dalloc_t(T, (size_t)T->H_pad + 2, &T->dWo)) != HB_OK) return st;
+    T->dbo = T->dWo + T->H_pad;
     T->d_loss = T->dbo + 1;
     if ((st = dalloc_t(T, (size_t)head_train_blocks(T->M_pad) * (T->H_pad + 2), &T->head_part)) != HB_OK) return st;
     // activations and scratch
@@ -452,8 +480,11 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     for (int a = 0; a < T->n_act; a++)
         if ((st = dalloc(T, abytes, &T->act[a])) != HB_OK) return st;
     if ((st = dalloc(T, abytes, &T->G)) != HB_OK || (st = dalloc(T, abytes, &T->G2)) != HB_OK ||
-        (st = dalloc(T, abytes, &T->XT)) != HB_OK || (st = dalloc(T, abytes, &T->GT)) != HB_OK)
+        (st = dalloc(T, abytes, &T->GT)) != HB_OK || (st = dalloc(T, abytes, &T->GT2)) != HB_OK)
         return st;
+    T->actT.assign(T->n_act, nullptr);
+    for (const auto& l : T->L)
+        if (!T->actT[l.in_act] && (st = dalloc(T, abytes, &T->actT[l.in_act])) != HB_OK) return st;
     if ((st = dalloc_t(T, (size_t)(T->M_pad / 64 + 1) * T->W_pad, &T->colpart)) != HB_OK) return st;
     if ((st = dalloc_t(T, (size_t)kScatterChunks * (T->trows + 1) * T->N1_pad, &T->partial)) != HB_OK) return st;
     if (T->t == 1) {
