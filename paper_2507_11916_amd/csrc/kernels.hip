@@ -276,6 +276,7 @@ struct GemmArgs {
     // Ct[n * ldct + m]; every row a tile writes is below ldct
     uint8_t* Ct = nullptr;
     int ldct = 0;
+    int ct_rows = 0;  // rows of Ct written (columns of C below it); 0: all
 };
 
 // Dynamic tile schedule.  A block's first tile is its own (the XCD-aware order
@@ -918,9 +919,10 @@ __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
                         }
                 _Pragma("unroll") for (int q = 0; q < TJ * 4; q++) {
                     const int cidx = q * 64 + lane, n = cidx >> 3, part = cidx & 7;
+                    const int nr = n0 + wn * (TJ * 32) + n;
                     const u32x4 val = *reinterpret_cast<const u32x4*>(reg + n * RS + part * 16);
-                    uint8_t* dst = g.Ct + ((size_t)(n0 + wn * (TJ * 32) + n) * g.ldct + m0 + wm * 64 + rd * MR) * EO + part * 16;
-                    *reinterpret_cast<u32x4*>(dst) = val;
+                    uint8_t* dst = g.Ct + ((size_t)nr * g.ldct + m0 + wm * 64 + rd * MR) * EO + part * 16;
+                    if (g.ct_rows <= 0 || nr < g.ct_rows) *reinterpret_cast<u32x4*>(dst) = val;
                 }
             }
         }
@@ -1468,7 +1470,7 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;
@@ -1493,7 +1495,7 @@ static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
     hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
@@ -1508,7 +1510,7 @@ static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     const int m_tiles = (L.m_cap + BM - 1) / BM;
     const int tiles = m_tiles * (L.N / BN);
     g.m_tiles_cap = m_tiles;
@@ -1529,7 +1531,7 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     const int m_tiles = (L.m_cap + 255) / 256;
     const int tiles = m_tiles * (L.N / 128);
     g.m_tiles_cap = m_tiles;
@@ -1549,7 +1551,7 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     g.split = L.split > 1 ? L.split : 1;
     g.c_split = L.c_split;
     const int m_tiles = (L.m_cap + 255) / 256;
@@ -1683,7 +1685,7 @@ static GemmArgs gemm_args_of(const GemmLaunch& L) {
     g.N = L.N; g.K = L.K; g.lda = L.lda; g.ldb = L.ldb; g.ldc = L.ldc;
     g.a_scale = L.a_scale; g.r_scale = L.r_scale; g.out_inv_scale = L.out_inv_scale; g.relu = L.relu;
     g.group_n = L.group_n; g.group_k = L.group_k;
-    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct;
+    g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
     return g;

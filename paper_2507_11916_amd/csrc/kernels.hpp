@@ -59,6 +59,7 @@ struct GemmLaunch {
     // (the rows the tiles cover).  Null: none.
     void* Ct = nullptr;
     int ldct = 0;
+    int ct_rows = 0;  // rows of Ct written (the first ct_rows columns of C); 0: all N
 };
 
 struct HeadArgs {

@@ -37,6 +37,10 @@ struct TLayer {
     void* Wkn;                 // [K_pad][N_pad] input-gradient operand
     float* dW;                 // [K_pad][N_pad]
     float* db;                 // [N_pad]
+    // K < K_pad: row K of the input's transposed copy is all ones, so row K of
+    // dW is the bias gradient (dbp points there); else dbp = db, a row sum
+    bool ones = false;
+    float* dbp = nullptr;
     int in_act, out_act, res_act;
 };
 
@@ -130,7 +134,7 @@ hb_status up_work(hb_trainer* tr, const std::vector<float>& vals, void** d) {
 
 hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, void* C, int ldc, const void* R,
                const void* Mk, const float* bias, int M, int N, int K, int relu, int out_type, hipStream_t s,
-               void* Ct = nullptr) {
+               void* Ct = nullptr, int ct_rows = 0) {
     GemmLaunch g{};
     g.prec = tr->t;
     g.out_type = out_type;
@@ -139,8 +143,9 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
     g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
     g.a_scale = g.r_scale = g.out_inv_scale = 1.f;
     g.relu = relu;
-    g.Ct = Ct;  // transposed copy of C (rows below M_pad)
+    g.Ct = Ct;  // transposed copy of C (rows below M_pad), its first ct_rows rows
     g.ldct = tr->M_pad;
+    g.ct_rows = ct_rows;
     // Forward and input-gradient products: the 8-wave 256x128 ring tile (the
     // one that writes a transposed copy), or 64x128 for small batches without
     // one.  Weight gradients (K, the batch, far longer than
@@ -209,7 +214,7 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     for (auto& l : tr->L) {
         st = gemm(tr, tr->act[l.in_act], tr->W_pad, l.Wt, l.K_pad, tr->act[l.out_act], tr->W_pad,
                   l.res_act >= 0 ? tr->act[l.res_act] : nullptr, nullptr, l.bias, Me, l.N_pad, l.K_pad, 1, -1, s,
-                  tr->actT[l.out_act]);
+                  tr->actT[l.out_act], l.N);  // (its padding rows keep their zeros or ones)
         if (st != HB_OK) return st;
     }
     HeadTrainArgs h{};
@@ -235,19 +240,21 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
     // input-gradient products write both; the head's gradient is transposed
     // here, its column sums giving the last layer's bias gradient.
     const int ldT = tr->M_pad;
-    if ((st = transpose(tr, tr->act[0], tr->W_pad, tr->actT[0], ldT, Me, tr->L[0].K_pad, nullptr, 0, s)) != HB_OK)
+    if ((st = transpose(tr, tr->act[0], tr->W_pad, tr->actT[0], ldT, Me, tr->L[0].K, nullptr, 0, s)) != HB_OK)
         return st;
     void* cur = tr->G;
     void* other = tr->G2;
     void* curT = tr->GT;
     void* otherT = tr->GT2;
-    if ((st = transpose(tr, cur, tr->W_pad, curT, ldT, Me, tr->L.back().N_pad, tr->L.back().db, n, s)) != HB_OK) return st;
+    if ((st = transpose(tr, cur, tr->W_pad, curT, ldT, Me, tr->L.back().N_pad, tr->L.back().ones ? nullptr : tr->L.back().db,
+                        n, s)) != HB_OK)
+        return st;
     bool db_done = true;
     for (int j = (int)tr->L.size() - 1; j >= 0; j--) {
         TLayer& l = tr->L[j];
         const bool res_b = l.res_act >= 0;
         // weight and bias gradient: dW = X^T cur, db = column sums of cur
-        if (!db_done) {
+        if (!db_done && !l.ones) {
             launch_row_sum(curT, ldT, l.N_pad, n, l.db, t, s);
             HB_HIP(hipGetLastError());
         }
@@ -262,8 +269,10 @@ hb_status fwd_bwd(hb_trainer* tr, const uint8_t* d_packed, const float* d_labels
                            l.K_pad, l.N_pad, 0, -1, s, otherT)) != HB_OK)
                 return st;
             TLayer& la = tr->L[j - 1];
-            launch_row_sum(otherT, ldT, la.N_pad, n, la.db, t, s);
-            HB_HIP(hipGetLastError());
+            if (!la.ones) {
+                launch_row_sum(otherT, ldT, la.N_pad, n, la.db, t, s);
+                HB_HIP(hipGetLastError());
+            }
             if ((st = gemm(tr, tr->actT[la.in_act], ldT, otherT, ldT, la.dW, la.N_pad, nullptr, nullptr, nullptr, la.K_pad,
                            la.N_pad, Me, 0, 0, s)) != HB_OK)
                 return st;
@@ -313,7 +322,7 @@ hb_status upload_adam_table(hb_trainer* tr) {
     ts.push_back(adam_tensor(tr->l1_bias, tr->l1_bm, tr->l1_bv, tr->db1, 0, 1, 1, tr->N1, nullptr, 0, 0, nullptr, 0, 0));
     for (auto& l : tr->L) {
         ts.push_back(adam_tensor(l.master, l.m, l.v, l.dW, l.N_pad, 1, l.K, l.N, l.Wt, 1, l.K_pad, l.Wkn, l.N_pad, 1));
-        ts.push_back(adam_tensor(l.bias, l.bm, l.bv, l.db, 0, 1, 1, l.N, nullptr, 0, 0, nullptr, 0, 0));
+        ts.push_back(adam_tensor(l.bias, l.bm, l.bv, l.dbp, 0, 1, 1, l.N, nullptr, 0, 0, nullptr, 0, 0));
     }
     ts.push_back(adam_tensor(tr->ho_master, tr->ho_m, tr->ho_v, tr->dWo, 1, 0, tr->H, 1, tr->ho_W, 1, 0, nullptr, 0, 0));
     ts.push_back(adam_tensor(tr->ho_b, tr->ho_bm, tr->ho_bv, tr->dbo, 0, 1, 1, 1, nullptr, 0, 0, nullptr, 0, 0));
@@ -483,8 +492,25 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
         (st = dalloc(T, abytes, &T->GT)) != HB_OK || (st = dalloc(T, abytes, &T->GT2)) != HB_OK)
         return st;
     T->actT.assign(T->n_act, nullptr);
-    for (const auto& l : T->L)
+    for (auto& l : T->L) {
         if (!T->actT[l.in_act] && (st = dalloc(T, abytes, &T->actT[l.in_act])) != HB_OK) return st;
+        l.ones = l.K < l.K_pad;
+        l.dbp = l.ones ? l.dW + (size_t)l.K * l.N_pad : l.db;
+        if (l.ones) {  // row K of the input's transposed copy: ones (no writer touches rows >= K)
+            std::vector<uint8_t> row((size_t)T->M_pad * T->eb);
+            for (int b = 0; b < T->M_pad; b++) {
+                if (T->eb == 4) {
+                    const float one = 1.f;
+                    std::memcpy(&row[(size_t)b * 4], &one, 4);
+                } else {
+                    const uint16_t one = host_bf16(1.f);
+                    std::memcpy(&row[(size_t)b * 2], &one, 2);
+                }
+            }
+            HB_HIP(hipMemcpy(static_cast<uint8_t*>(T->actT[l.in_act]) + (size_t)l.K * T->M_pad * T->eb, row.data(),
+                             row.size(), hipMemcpyHostToDevice));
+        }
+    }
     if ((st = dalloc_t(T, (size_t)(T->M_pad / 64 + 1) * T->W_pad, &T->colpart)) != HB_OK) return st;
     if ((st = dalloc_t(T, (size_t)kScatterChunks * (T->trows + 1) * T->N1_pad, &T->partial)) != HB_OK) return st;
     if (T->t == 1) {
@@ -544,7 +570,7 @@ hb_status hb_train_grad(hb_trainer* t, const uint8_t* d_packed, const float* d_l
     for (auto& l : t->L) {
         if ((st = copy2d(p, l.dW, l.K, l.N, l.N_pad, s)) != HB_OK) return st;
         p += (size_t)l.K * l.N;
-        HB_HIP(hipMemcpyAsync(p, l.db, (size_t)l.N * 4, hipMemcpyDeviceToDevice, s));
+        HB_HIP(hipMemcpyAsync(p, l.dbp, (size_t)l.N * 4, hipMemcpyDeviceToDevice, s));
         p += l.N;
     }
     HB_HIP(hipMemcpyAsync(p, t->dWo, (size_t)t->H * 4, hipMemcpyDeviceToDevice, s));
