@@ -87,6 +87,13 @@ struct hb_trainer {
     // written by the forward products' epilogues (act 0 by a transpose); null
     // for activations no layer reads
     std::vector<void*> actT;
+
+    // releases every device allocation (also when creation fails part way)
+    ~hb_trainer() {
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        for (void* p : allocs) (void)hipFree(p);
+    }
     float* d_loss = nullptr;
     int step = 0;
     std::vector<void*> allocs;
@@ -522,13 +529,7 @@ hb_status hb_trainer_create(const char* path, const hb_train_opts* opts, hb_trai
     return HB_OK;
 }
 
-void hb_trainer_free(hb_trainer* t) {
-    if (!t) return;
-    (void)hipSetDevice(t->device);
-    (void)hipDeviceSynchronize();
-    for (void* p : t->allocs) (void)hipFree(p);
-    delete t;
-}
+void hb_trainer_free(hb_trainer* t) { delete t; }  // (null: nothing)
 
 int64_t hb_trainer_n_params(const hb_trainer* t) {
     if (!t) return -1;
