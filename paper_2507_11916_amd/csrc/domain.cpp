@@ -494,11 +494,22 @@ static void build_group(const std::vector<int>& tiles, int threads, std::vector<
         auto work = [&](int64_t lo, int64_t hi) {
             int64_t local = 0;
             int cell[8];
+            const uint64_t cc8 = 0x0101010101010101ull * (uint64_t)c;
             for (int64_t r = lo; r < hi; r++) {
                 uint8_t* row = D + r * 16;
+                // the row as two relaxed 64-bit loads (other threads lower
+                // cells meanwhile); a byte equals c exactly where its XOR with
+                // c is zero, found word-wide without carries between bytes
+                uint64_t w[2] = {__atomic_load_n(reinterpret_cast<uint64_t*>(row), __ATOMIC_RELAXED),
+                                 __atomic_load_n(reinterpret_cast<uint64_t*>(row) + 1, __ATOMIC_RELAXED)};
                 uint32_t at_c = 0;
-                for (int b = 0; b < 16; b++)
-                    if (__atomic_load_n(&row[b], __ATOMIC_RELAXED) == c) at_c |= 1u << b;
+                for (int h = 0; h < 2; h++) {
+                    const uint64_t x = w[h] ^ cc8;
+                    const uint64_t z = ~(((x & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full) | x | 0x7F7F7F7F7F7F7F7Full);
+                    if (!z) continue;
+                    for (int b = 0; b < 8; b++)
+                        if (z & (0x80ull << (8 * b))) at_c |= 1u << (8 * h + b);
+                }
                 if (!at_c) continue;
                 placement_unrank(k, r, cell);
                 uint32_t occ = 0;

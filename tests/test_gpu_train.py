@@ -51,8 +51,11 @@ def _gpu_grad(path, prec, states, labels, asym):
     return loss, d_g.cpu().numpy().astype(np.float64), tr, d_p, d_l
 
 
+# Widths: 1000 leaves a padding row in the transposed input copy (the bias
+# gradient comes out of the weight-gradient product); 128 and 256 do not (row
+# sums); [1000, 256] mixes both in one net.
 @pytest.mark.parametrize("dom,dims,n_res,n", [(1, [128, 128], 1, 300), (0, [128], 2, 200), (1, [1000, 1000], 2, 96),
-                                             (2, [256, 128], 1, 200)])
+                                             (2, [256, 128], 1, 200), (1, [1000, 256], 1, 150)])
 def test_fp32_gradients_match_oracle(tmp_path, dom, dims, n_res, n):
     path = _net(str(tmp_path / "n.hbw"), dom, dims, n_res, 4)
     st = _states(dom, n, 55)
@@ -69,8 +72,9 @@ def test_fp32_gradients_match_oracle(tmp_path, dom, dims, n_res, n):
             off += r * c
 
 
-def test_bf16_gradients_match_oracle(tmp_path):
-    path = _net(str(tmp_path / "n.hbw"), 1, [1000, 1000], 2, 6)
+@pytest.mark.parametrize("dims,n_res", [([1000, 1000], 2), ([1000, 256], 1)])
+def test_bf16_gradients_match_oracle(tmp_path, dims, n_res):
+    path = _net(str(tmp_path / "n.hbw"), 1, dims, n_res, 6)
     st = synth.stp_walks(4, synth.throughput_seeds(128, 77), lengths=60)
     labels = (np.arange(128) % 41 + 1).astype(np.float64)
     net = O.Net(path)
