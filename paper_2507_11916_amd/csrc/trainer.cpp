@@ -159,7 +159,7 @@ hb_status gemm(hb_trainer* tr, const void* A, int lda, const void* Bt, int ldb, 
     // M and N): FP32 takes the one-wave 32x32 tile (8x the tiles of 64x128 on a
     // 1000 x 1000 output; 12% faster per FP32 step), BF16 the 64x128 tile with a
     // 4-stage LDS ring (more of the long K in flight; 8% faster per BF16 step).
-    const bool wgrad = K >= 4 * std::max(M, N);
+    const bool wgrad = out_type == 0 && K >= 4 * std::max(M, N);  // (the weight-gradient calls ask for FP32 C)
     g.tile = wgrad ? (tr->t == 0 ? 4 : 8) : (Ct || (N % 128 == 0 && M >= 2048)) ? 14 : 2;  // (a transposed copy: tile 14)
     // BF16 weight gradients of wide layers: split-K on the 256x128 tile (the
     // 1000 x 1000 output alone is 32 such tiles), partial products in wsplit,
