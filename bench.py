@@ -8,7 +8,8 @@ with the floor/min-Manhattan output rule).  BF16 and FP8 are measured on the sam
 network and inputs and reported with their h agreement against the FP64 oracle.
 
 Also reported: the dominant kernel's roofline (GEMM; algorithmic FLOPs per launch
-over its average event-timed duration), the end-to-end rate through pinned host
+over its average duration, timed with two HIP events that each launch records at
+the kernel's own start and end on its stream), the end-to-end rate through pinned host
 memory, search nodes/s of Batch IDA* in fixed-tree mode, and the CPU oracle's
 evals/s on a bounded sample (baseline only).
 

@@ -11,6 +11,7 @@
 // Every kernel computes each row independently and in a fixed order, so a
 // state's heuristic does not depend on the batch it is evaluated in.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 
@@ -1461,6 +1462,16 @@ bool launch_gather(const GatherLaunch& L, hipStream_t s) {
     return false;
 }
 
+// A GEMM launch; with the caller's timing events, the kernel's own start and
+// end are recorded on them.
+template <typename K>
+static void launch_k(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const GemmLaunch& L, const GemmArgs& g) {
+    if (L.ev_start && L.ev_stop)
+        hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)lds, s, L.ev_start, L.ev_stop, 0, g);
+    else
+        hipLaunchKernelGGL(kern, grid, block, lds, s, g);
+}
+
 template <int PREC, int OUTT, int BM, int BN>
 static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     GemmArgs g;
@@ -1483,7 +1494,7 @@ static void launch_gemm_t(const GemmLaunch& L, hipStream_t s) {
     }
     if (L.m_dev) g.persistent = 1;  // tile count known only on the device: stride over the cap
     const size_t lds = 2 * (size_t)(BM + BN) * 128;
-    hipLaunchKernelGGL((gemm_kernel<PREC, OUTT, BM, BN>), dim3(grid), dim3(256), lds, s, g);
+    launch_k(gemm_kernel<PREC, OUTT, BM, BN>, dim3(grid), dim3(256), lds, s, L, g);
 }
 
 template <int PREC, int OUTT>
@@ -1498,7 +1509,7 @@ static void launch_gemm_small(const GemmLaunch& L, hipStream_t s) {
     g.Ct = (uint8_t*)L.Ct; g.ldct = L.ldct; g.ct_rows = L.ct_rows;
     g.m_tiles_cap = (L.m_cap + 31) / 32;
     g.persistent = 0;
-    hipLaunchKernelGGL((gemm_small_kernel<PREC, OUTT>), dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, g);
+    launch_k(gemm_small_kernel<PREC, OUTT>, dim3(g.m_tiles_cap * (L.N / 32)), dim3(64), 0, s, L, g);
 }
 
 template <int PREC, int OUTT, int BM, int BN, int NS>
@@ -1519,7 +1530,7 @@ static void launch_gemm_ring(const GemmLaunch& L, hipStream_t s) {
     if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
     if (L.m_dev) g.persistent = 1;
     const size_t lds = (size_t)NS * (BM + BN) * 128;
-    hipLaunchKernelGGL((gemm_ring_kernel<PREC, OUTT, BM, BN, NS>), dim3(grid), dim3(256), lds, s, g);
+    launch_k(gemm_ring_kernel<PREC, OUTT, BM, BN, NS>, dim3(grid), dim3(256), lds, s, L, g);
 }
 
 template <int PREC, int OUTT>
@@ -1539,7 +1550,7 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     g.persistent = 0;
     if (L.persistent_grid > 0 && L.persistent_grid < tiles) { grid = L.persistent_grid; g.persistent = 1; }
     if (L.m_dev) g.persistent = 1;
-    hipLaunchKernelGGL((gemm_w8_kernel<PREC, OUTT>), dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, g);
+    launch_k(gemm_w8_kernel<PREC, OUTT>, dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, L, g);
 }
 
 template <int PREC, int OUTT, int NW, int NS, bool TC = false>
@@ -1565,8 +1576,8 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
         g.tile_ctr = L.tile_ctr;
     }
     if (L.m_dev) g.persistent = 1;
-    hipLaunchKernelGGL((gemm_wide_kernel<PREC, OUTT, NW, NS, TC>), dim3(grid), dim3(NW * 64),
-                       (size_t)NS * (256 + 128) * 128, s, g);
+    launch_k(gemm_wide_kernel<PREC, OUTT, NW, NS, TC>, dim3(grid), dim3(NW * 64), (size_t)NS * (256 + 128) * 128, s, L,
+             g);
 }
 
 // Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the

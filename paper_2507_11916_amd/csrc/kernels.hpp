@@ -60,6 +60,10 @@ struct GemmLaunch {
     void* Ct = nullptr;
     int ldct = 0;
     int ct_rows = 0;  // rows of Ct written (the first ct_rows columns of C); 0: all N
+    // Optional timing: the launch records the kernel's own start and end on
+    // these two events (hipExtLaunchKernelGGL), so their elapsed time excludes
+    // the dispatch.  Null: a plain launch.
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 struct HeadArgs {

@@ -369,22 +369,29 @@ hb_status model_prepare(hb_model* m, hipStream_t s) {
     return get_ws(m, s, &w);
 }
 
-// Per-kernel timing (hb_model_profile): events bracket each launch on its stream.
-static int prof_begin(hb_model* m, int kind, hipStream_t s) {
+// Per-kernel timing (hb_model_profile): events bracket each launch on its
+// stream, or (GEMMs: `attach` given) are handed to the launch, which records
+// the kernel's own start and end on them.
+static int prof_begin(hb_model* m, int kind, hipStream_t s, GemmLaunch* attach = nullptr) {
     if (!m->profiling) return -1;
     hb_model::Timed t{kind, nullptr, nullptr, 0.0};
     if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) return -1;
-    (void)hipEventRecord(t.a, s);
+    if (attach) {
+        attach->ev_start = t.a;
+        attach->ev_stop = t.b;
+    } else {
+        (void)hipEventRecord(t.a, s);
+    }
     std::lock_guard<std::mutex> lk(m->mu);
     m->timed.push_back(t);
     return (int)m->timed.size() - 1;
 }
 
-static void prof_end(hb_model* m, int idx, double flops, hipStream_t s) {
+static void prof_end(hb_model* m, int idx, double flops, hipStream_t s, bool attached = false) {
     if (idx < 0) return;
     std::lock_guard<std::mutex> lk(m->mu);
     m->timed[idx].flops = flops;
-    (void)hipEventRecord(m->timed[idx].b, s);
+    if (!attached) (void)hipEventRecord(m->timed[idx].b, s);
 }
 
 hb_status model_profile(hb_model* m, bool enable) {
@@ -580,10 +587,10 @@ static hb_status eval_chunk(hb_model* m, Workspace* w, const uint8_t* d_packed, 
         g.out_inv_scale = 1.f / m->act_scale[L.out_act];
         g.relu = 1;
         g.tile_ctr = w->tile_ctr;  // used by the persistent-grid tiles
-        pi = timed ? prof_begin(m, 1, s) : -1;
+        pi = timed ? prof_begin(m, 1, s, &g) : -1;
         if (!launch_gemm(g, s)) return fail(HB_E_UNSUPPORTED, "no GEMM kernel for this precision/tile");
         HB_HIP(hipGetLastError());
-        prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N * L.groups, s);
+        prof_end(m, pi, 2.0 * (d_n ? m_cap : n) * L.K * L.N * L.groups, s, true);
         if (hb_status st = copy_act(L.out_act, g.C, L.N_pad * L.groups); st != HB_OK) return st;
         if (cap) launch_absmax((const float*)g.C, n, L.N_pad * L.groups, m->width_cap, w->absmax + L.out_act, s);
         if (!L.res_in_place && !res_first) std::swap(X, Tb);
