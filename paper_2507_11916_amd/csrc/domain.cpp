@@ -489,13 +489,30 @@ static void build_group(const std::vector<int>& tiles, int threads, std::vector<
         for (int b = 0; b < 16; b++)
             if (region & (1u << b)) D[r * 16 + b] = 0;
     }
+    // Rows to visit at the next level: a bit per placement, set when a cell of
+    // the row receives the next level's distance (only such rows can hold
+    // cells at that level; a row whose cells were lowered further meanwhile
+    // is skipped by its row test).
+    const int64_t nwords = (n + 63) / 64;
+    std::vector<uint64_t> cur_rows((size_t)nwords, 0), next_rows((size_t)nwords, 0);
+    {
+        int cell[8];
+        for (int i = 0; i < k; i++) cell[i] = tiles[i];
+        const int64_t r = placement_rank(k, cell);
+        cur_rows[(size_t)(r >> 6)] |= 1ull << (r & 63);
+    }
     for (int c = 0; c < 254; c++) {
         std::atomic<int64_t> added{0};
-        auto work = [&](int64_t lo, int64_t hi) {
+        uint64_t* NR = next_rows.data();
+        auto work = [&](int64_t wlo, int64_t whi) {
             int64_t local = 0;
             int cell[8];
             const uint64_t cc8 = 0x0101010101010101ull * (uint64_t)c;
-            for (int64_t r = lo; r < hi; r++) {
+            for (int64_t wi = wlo; wi < whi; wi++) {
+                uint64_t bits = cur_rows[(size_t)wi];
+                while (bits) {
+                const int64_t r = wi * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
                 uint8_t* row = D + r * 16;
                 // the row as two relaxed 64-bit loads (other threads lower
                 // cells meanwhile); a byte equals c exactly where its XOR with
@@ -538,6 +555,10 @@ static void build_group(const std::vector<int>& tiles, int threads, std::vector<
                 for (int b = 0; b < 16; b++)
                     if ((region & (1u << b)) && lower_to(&row[b], (uint8_t)c)) local++;
                 // one pattern-tile move: the tile next to the blank slides into it
+                // (all of the row's targets are found and prefetched first, so
+                // their cache misses overlap)
+                int64_t tgt[64];
+                int nt = 0;
                 for (int b = 0; b < 16; b++) {
                     if (!(region & (1u << b))) continue;
                     const int rr = b >> 2, cc = b & 3;
@@ -550,20 +571,30 @@ static void build_group(const std::vector<int>& tiles, int threads, std::vector<
                         for (int i = 0; i < k; i++) moved[i] = cell[i];
                         moved[t] = b;  // the tile takes the blank's cell, the blank takes the tile's
                         const int64_t nr = placement_rank(k, moved);
-                        if (lower_to(&D[nr * 16 + nb4[e]], (uint8_t)(c + 1))) local++;
+                        tgt[nt++] = nr * 16 + nb4[e];
+                        __builtin_prefetch(&D[nr * 16], 1);
+                    }
+                }
+                for (int q = 0; q < nt; q++)
+                    if (lower_to(&D[tgt[q]], (uint8_t)(c + 1))) {
+                        local++;
+                        const int64_t nr = tgt[q] >> 4;
+                        __atomic_fetch_or(&NR[nr >> 6], 1ull << (nr & 63), __ATOMIC_RELAXED);
                     }
                 }
             }
             added += local;
         };
         std::vector<std::thread> pool;
-        const int64_t chunk = (n + threads - 1) / threads;
+        const int64_t chunk = (nwords + threads - 1) / threads;
         for (int t = 0; t < threads; t++) {
-            const int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+            const int64_t lo = t * chunk, hi = std::min(nwords, lo + chunk);
             if (lo < hi) pool.emplace_back(work, lo, hi);
         }
         for (auto& th : pool) th.join();
         if (added.load() == 0) break;
+        cur_rows.swap(next_rows);
+        std::fill(next_rows.begin(), next_rows.end(), 0ull);
     }
     table->assign((size_t)n, 255);
     for (int64_t r = 0; r < n; r++) {
