@@ -42,9 +42,9 @@ TILE_KERNELS = {1: "gemm_kernel<{p}, {p}, 128, 128>", 2: "gemm_kernel<{p}, {p}, 
                 5: "gemm_small_kernel<{p}, {p}>", 6: "gemm_ring_kernel<{p}, {p}, 256, 128, 3>",
                 7: "gemm_ring_kernel<{p}, {p}, 128, 128, 3>", 8: "gemm_ring_kernel<{p}, {p}, 128, 256, 3>",
                 9: "gemm_ring_kernel<{p}, {p}, 64, 128, 4>", 10: "gemm_w8_kernel<{p}, {p}>",
-                15: "gemm_wide_kernel<{p}, {p}, 8, 2, false>", 16: "gemm_wide_kernel<{p}, {p}, 8, 3, false>",
-                17: "gemm_wide_kernel<{p}, {p}, 16, 2, false>", 18: "gemm_wide_kernel<{p}, {p}, 8, 2, false>",
-                19: "gemm_kernel<{p}, {p}, 128, 128>"}
+                15: "gemm_wide_kernel<{p}, {p}, 8, 2, false, 128>", 16: "gemm_wide_kernel<{p}, {p}, 8, 3, false, 128>",
+                17: "gemm_wide_kernel<{p}, {p}, 16, 2, false, 128>", 18: "gemm_wide_kernel<{p}, {p}, 8, 2, false, 128>",
+                19: "gemm_kernel<{p}, {p}, 128, 128>", 20: "gemm_wide_kernel<{p}, {p}, 8, 2, false, 256>"}
 PREC_ARG = {"f32": 0, "bf16": 1, "fp8": 2}
 
 

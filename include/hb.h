@@ -262,8 +262,11 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
  * 18 the 15 kernel as a persistent grid of one block per compute unit, 19 the 1
  *   kernel as a persistent grid of two blocks per compute unit: a block's tiles
  *   after its first come off an atomic counter (per stream, reset by each
- *   launch's last block; no block waits on another).
- * All shapes give bitwise equal results.  HB_E_INVAL outside 0..19.  See hb_model_tune. */
+ *   launch's last block; no block waits on another);
+ * 20 256x256 (2-stage ring), 8 waves of 64x128: a third fewer operand bytes per
+ *   MFMA than 256x128, for large batches (layers whose padded width is a
+ *   multiple of 256).
+ * All shapes give bitwise equal results.  HB_E_INVAL outside 0..20.  See hb_model_tune. */
 hb_status hb_model_set_tile(hb_model* m, int tile_id);
 /* Autotuner for one batch size: times every tile shape on the n packed states
  * (device) and keeps the fastest for batches in n's power-of-two bucket

@@ -750,51 +750,64 @@ __device__ __forceinline__ void mma_stage_pre(const uint8_t* a_s, const uint8_t*
                                               int ar0, int br0, int lane) {
     const int half = lane >> 5, r32 = lane & 31;
     if (PREC == 2) {
-        intx8 af[2][TI], bfr[2][TJ];
-        _Pragma("unroll") for (int kg = 0; kg < 2; kg++) {
-            _Pragma("unroll") for (int i = 0; i < TI; i++) {
-                const int row = ar0 + i * 32 + r32;
-                const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
-                const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
-                af[kg][i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        constexpr int KB = TI * TJ > 4 ? 1 : 2;  // 64-element K groups read per batch (as below)
+        _Pragma("unroll") for (int k0 = 0; k0 < 2; k0 += KB) {
+            intx8 af[KB][TI], bfr[KB][TJ];
+            _Pragma("unroll") for (int q = 0; q < KB; q++) {
+                const int kg = k0 + q;
+                _Pragma("unroll") for (int i = 0; i < TI; i++) {
+                    const int row = ar0 + i * 32 + r32;
+                    const u32x4 lo = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half));
+                    const u32x4 hi = *reinterpret_cast<const u32x4*>(a_s + swz(row, 4 * kg + 2 * half + 1));
+                    af[q][i] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                }
+                _Pragma("unroll") for (int j = 0; j < TJ; j++) {
+                    const int row = br0 + j * 32 + r32;
+                    const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
+                    const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
+                    bfr[q][j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+                }
             }
-            _Pragma("unroll") for (int j = 0; j < TJ; j++) {
-                const int row = br0 + j * 32 + r32;
-                const u32x4 lo = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half));
-                const u32x4 hi = *reinterpret_cast<const u32x4*>(b_s + swz(row, 4 * kg + 2 * half + 1));
-                bfr[kg][j] = intx8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        _Pragma("unroll") for (int kg = 0; kg < 2; kg++)
-            _Pragma("unroll") for (int i = 0; i < TI; i++)
-                _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[kg][i], bfr[kg][j], acc[i][j], 0, 0,
-                                                                               0, 127, 0, 127);
-    } else {
-        u32x4 af[4][TI], bfr[4][TJ];
-        _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
-            _Pragma("unroll") for (int i = 0; i < TI; i++)
-                af[kg][i] = *reinterpret_cast<const u32x4*>(a_s + swz(ar0 + i * 32 + r32, 2 * kg + half));
-            _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                bfr[kg][j] = *reinterpret_cast<const u32x4*>(b_s + swz(br0 + j * 32 + r32, 2 * kg + half));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        _Pragma("unroll") for (int kg = 0; kg < 4; kg++) {
-            if (PREC == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            _Pragma("unroll") for (int q = 0; q < KB; q++)
                 _Pragma("unroll") for (int i = 0; i < TI; i++)
                     _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[kg][i]),
-                                                                            __builtin_bit_cast(bf16x8, bfr[kg][j]),
-                                                                            acc[i][j], 0, 0, 0);
-            } else {
-                _Pragma("unroll") for (int e = 0; e < 4; e++)
+                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af[q][i], bfr[q][j], acc[i][j], 0,
+                                                                                   0, 0, 127, 0, 127);
+            if (KB < 2) __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        // K groups read per batch: all four, or two at a time when the wave's
+        // tile is 64 x 128 (the fragments of four would not fit beside its
+        // accumulators); the MFMA order is the same either way
+        constexpr int KB = TI * TJ > 4 ? 2 : 4;
+        _Pragma("unroll") for (int k0 = 0; k0 < 4; k0 += KB) {
+            u32x4 af[KB][TI], bfr[KB][TJ];
+            _Pragma("unroll") for (int q = 0; q < KB; q++) {
+                const int kg = k0 + q;
+                _Pragma("unroll") for (int i = 0; i < TI; i++)
+                    af[q][i] = *reinterpret_cast<const u32x4*>(a_s + swz(ar0 + i * 32 + r32, 2 * kg + half));
+                _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                    bfr[q][j] = *reinterpret_cast<const u32x4*>(b_s + swz(br0 + j * 32 + r32, 2 * kg + half));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            _Pragma("unroll") for (int q = 0; q < KB; q++) {
+                if (PREC == 1) {
                     _Pragma("unroll") for (int i = 0; i < TI; i++)
                         _Pragma("unroll") for (int j = 0; j < TJ; j++)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(af[kg][i][e]),
-                                                                             __uint_as_float(bfr[kg][j][e]), acc[i][j],
-                                                                             0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[q][i]),
+                                                                                __builtin_bit_cast(bf16x8, bfr[q][j]),
+                                                                                acc[i][j], 0, 0, 0);
+                } else {
+                    _Pragma("unroll") for (int e = 0; e < 4; e++)
+                        _Pragma("unroll") for (int i = 0; i < TI; i++)
+                            _Pragma("unroll") for (int j = 0; j < TJ; j++)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(af[q][i][e]),
+                                                                                 __uint_as_float(bfr[q][j][e]), acc[i][j],
+                                                                                 0, 0, 0);
+                }
             }
+            if (KB < 4) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -807,15 +820,17 @@ __device__ __forceinline__ void mma_stage_pre(const uint8_t* a_s, const uint8_t*
 // a SIMD the one with operands in registers goes first instead of both reading
 // LDS and then both multiplying.  Same per-element MFMA sequence and epilogue
 // as the other tiles: bitwise equal results.
-template <int PREC, int OUTT, int NW, int NS, bool TC = false>
+template <int PREC, int OUTT, int NW, int NS, bool TC = false, int BNT = 128>
 __global__ __launch_bounds__(NW * 64) void gemm_wide_kernel(GemmArgs g) {
-    constexpr int BM = 256, BN = 128, NT = NW * 64;
+    constexpr int BM = 256, BN = BNT, NT = NW * 64;
     constexpr int EB = Ty<PREC>::EB;
     constexpr int A_BYTES = BM * 128, B_BYTES = BN * 128, STAGE = A_BYTES + B_BYTES;
     constexpr int NA = A_BYTES / 1024, LD = STAGE / 1024 / NW;  // 1 KiB load instructions per wave per stage
-    constexpr int TI = 2, TJ = NW == 8 ? 2 : 1;
+    constexpr int TI = 2, TJ = BN / (8 * NW);  // waves in a 4 x (NW / 4) grid, 64 x (TJ 32) each
     static_assert(NW == 8 || NW == 16, "wave count");
     static_assert(NS >= 2 && NS <= 3, "ring depth");
+    static_assert(BN == 128 || (BN == 256 && NW == 8), "tile width");
+    static_assert(!TC || BN == 128, "the transposed copy is staged for 128-column tiles");
     static_assert((STAGE / 1024) % NW == 0, "loads per wave");
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
 
@@ -1553,7 +1568,7 @@ static void launch_gemm_w8(const GemmLaunch& L, hipStream_t s) {
     launch_k(gemm_w8_kernel<PREC, OUTT>, dim3(grid), dim3(512), (size_t)2 * (256 + 128) * 128, s, L, g);
 }
 
-template <int PREC, int OUTT, int NW, int NS, bool TC = false>
+template <int PREC, int OUTT, int NW, int NS, bool TC = false, int BN = 128>
 static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     GemmArgs g;
     g.A = (const uint8_t*)L.A; g.Bt = (const uint8_t*)L.Bt; g.C = (uint8_t*)L.C; g.R = (const uint8_t*)L.R;
@@ -1566,7 +1581,7 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
     g.split = L.split > 1 ? L.split : 1;
     g.c_split = L.c_split;
     const int m_tiles = (L.m_cap + 255) / 256;
-    const int tiles = m_tiles * (L.N / 128) * g.split;
+    const int tiles = m_tiles * (L.N / BN) * g.split;
     g.m_tiles_cap = m_tiles;
     int grid = tiles;
     g.persistent = 0;
@@ -1576,8 +1591,8 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
         g.tile_ctr = L.tile_ctr;
     }
     if (L.m_dev) g.persistent = 1;
-    launch_k(gemm_wide_kernel<PREC, OUTT, NW, NS, TC>, dim3(grid), dim3(NW * 64), (size_t)NS * (256 + 128) * 128, s, L,
-             g);
+    launch_k(gemm_wide_kernel<PREC, OUTT, NW, NS, TC, BN>, dim3(grid), dim3(NW * 64), (size_t)NS * (256 + BN) * 128, s,
+             L, g);
 }
 
 // Tile ids: 0-3 LDS double buffer fed through registers (4 waves), 4 the
@@ -1588,13 +1603,16 @@ static void launch_gemm_wide(const GemmLaunch& L, hipStream_t s) {
 // 14-16 the wide-block ring kernels (8 waves with a 2- or 3-stage ring, 16
 // waves with a 2-stage ring); 17 and 18 persistent grids (one 8-wave wide
 // block per compute unit, two 128x128 blocks per compute unit) taking tiles
-// off an atomic counter when the caller supplies one.
-int gemm_tile_count() { return 19; }
+// off an atomic counter when the caller supplies one; 19 the wide ring kernel
+// on 256 x 256 tiles (8 waves of 64 x 128, a third fewer operand bytes per
+// MFMA than 256 x 128: for large batches, where every compute unit gets
+// several tiles).
+int gemm_tile_count() { return 20; }
 void gemm_tile_shape(int id, int* bm, int* bn) {
-    static const int T[19][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
+    static const int T[20][2] = {{128, 128}, {128, 256}, {64, 128}, {256, 128}, {32, 32},
                                  {256, 128}, {128, 128}, {128, 256}, {64, 128}, {256, 128},
                                  {32, 32}, {32, 32}, {32, 32}, {32, 32},
-                                 {256, 128}, {256, 128}, {256, 128}, {256, 128}, {128, 128}};
+                                 {256, 128}, {256, 128}, {256, 128}, {256, 128}, {128, 128}, {256, 256}};
     *bm = T[id][0];
     *bn = T[id][1];
 }
@@ -1646,6 +1664,10 @@ static bool launch_gemm_p(const GemmLaunch& L, hipStream_t s) {
             launch_gemm_t<PREC, OUTT, 128, 128>(P, s);
             return true;
         }
+        case 19:
+            if (L.N % 256) return false;
+            launch_gemm_wide<PREC, OUTT, 8, 2, false, 256>(L, s);
+            return true;
     }
     return false;
 }
@@ -1797,6 +1819,9 @@ static hipError_t set_lds_attr_p() {
     if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 8, 2>();
     if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 8, 3>();
     if (e == hipSuccess) e = set_wide_attr<PREC, OUTT, 16, 2>();
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_wide_kernel<PREC, OUTT, 8, 2, false, 256>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * (256 + 256) * 128);
     return e;
 }
 
