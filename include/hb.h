@@ -32,7 +32,7 @@ typedef enum {
     HB_E_INVAL = -1,        /* bad argument or invalid state */
     HB_E_NOMEM = -2,        /* host or device allocation failed */
     HB_E_DEVICE = -3,       /* a HIP call or kernel launch failed */
-    HB_E_UNSUPPORTED = -4,  /* valid request that this build does not support */
+    HB_E_UNSUPPORTED = -4,  /* valid request that the library does not support */
     HB_E_BUDGET = -5,       /* node or time limit reached; statistics are valid */
     HB_E_NOSOLUTION = -6    /* the search space holds no solution */
 } hb_status;
@@ -254,7 +254,7 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
  * 6 256x128, 7 128x128, 8 128x256 (3-stage LDS ring), 9 64x128 (4-stage ring):
  *   LDS ring filled by direct global-to-LDS loads, 4 waves;
  * 10 256x128: LDS double buffer filled through registers, 8 waves (4 x 2);
- * 11-14: the fused one-launch forward kernel, switched off in this build
+ * 11-14: the fused one-launch forward kernel, switched off in the library
  *   (HB_E_UNSUPPORTED);
  * 15 256x128 (2-stage ring), 16 256x128 (3-stage ring): LDS ring filled by
  *   direct loads, each stage's operands read whole before its MFMAs, 8 waves;

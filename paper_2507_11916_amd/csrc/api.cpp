@@ -280,7 +280,7 @@ hb_status hb_eval_batch_dev_n(hb_model* m, const uint8_t* d_packed, const int32_
 hb_status hb_model_set_tile(hb_model* m, int tile_id) {
     if (!m || tile_id < 0 || tile_id > gemm_tile_count()) return fail(HB_E_INVAL, "tile id out of range");
     if (tile_id > 0 && fused_tile(tile_id - 1) && !fused_enabled())
-        return fail(HB_E_UNSUPPORTED, "tile %d (the fused persistent forward kernel) is switched off in this build", tile_id);
+        return fail(HB_E_UNSUPPORTED, "tile %d (the fused persistent forward kernel) is switched off", tile_id);
     m->tile = tile_id;
     return HB_OK;
 }
