@@ -35,7 +35,7 @@ __global__ void fill_kernel(float* p, int64_t n, float v) {
 }
 
 // ------------------------------------------------------------------ head
-// One wave per row, 8 rows per wave, 4 waves per block.  y = w.x + b;
+// Rows in turn, 2 rows per wave, 4 waves per block.  y = w.x + b;
 // loss += w_b (y - t)^2 / n; dy = 2 w_b (y - t) / n; delta_k = dy * w_k where
 // x_k > 0 (gradient at the pre-activation of the last hidden layer).  Rows >= n
 // get delta = 0.  dWo, dbo and the loss are reduced over the block's rows in
@@ -43,8 +43,9 @@ __global__ void fill_kernel(float* p, int64_t n, float v) {
 // block order.  A wave loads all of its rows (4 consecutive values per lane
 // and group, one vector access) before it reduces the first, so the rows'
 // loads are in flight together; the per-row arithmetic and the row order of
-// the accumulations are fixed.
-constexpr int kHeadRowsPerWave = 8;
+// the accumulations are fixed.  Few rows per wave make many blocks: 8 rows per
+// wave (a quarter of the blocks) took 1.5x as long, with the partial sums.
+constexpr int kHeadRowsPerWave = 2;
 constexpr int kHeadMaxGroups = 4;  // K <= 1024
 
 // four consecutive elements (float32 or bfloat16) starting at element i
@@ -96,6 +97,11 @@ __global__ __launch_bounds__(256) void head_train_kernel(HeadTrainArgs a) {
         _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
             ld4_t<T>(a.X, (size_t)r * a.ldx + min(gi * 256 + lane * 4, a.K - 4), x[rr][gi]);
     }
+    // the rows' labels and the output bias, loaded with the rows (a label read
+    // after each row's reduction would put one memory latency per row in series)
+    float lab[RW];
+    _Pragma("unroll") for (int rr = 0; rr < RW; rr++) lab[rr] = a.labels[max(0, min(row0 + rr, a.n - 1))];
+    const float bias_o = a.b[0];
     _Pragma("unroll") for (int rr = 0; rr < RW; rr++)
         _Pragma("unroll") for (int gi = 0; gi < kHeadMaxGroups; gi++)
             if (gi * 256 + lane * 4 >= a.K) _Pragma("unroll") for (int e = 0; e < 4; e++) x[rr][gi][e] = 0.f;
@@ -112,8 +118,8 @@ __global__ __launch_bounds__(256) void head_train_kernel(HeadTrainArgs a) {
         for (int s = 32; s >= 1; s >>= 1) part += __shfl_xor(part, s, 64);
         float dy = 0.f;
         if (r < a.n) {
-            const float y = part + a.b[0];
-            const float d = y - a.labels[r];
+            const float y = part + bias_o;
+            const float d = y - lab[rr];
             const float wgt = (a.asym && d > 0.f) ? a.alpha : 1.f;
             dy = 2.f * wgt * d * a.inv_n;
             accl += wgt * d * d * a.inv_n;
@@ -451,45 +457,64 @@ __global__ void cube_fold_kernel(const float* master, const float* bias, int N1,
 // master[k][n] (float32, K x N) updated from grad[k*gk + n*gn]; the working
 // copies out1 (type T) at k*s1k + n*s1n and out2 at k*s2k + n*s2n are rewritten.
 // One grid row per tensor, so every tensor's step is one launch.
-// Blocks take 64 x 64 tiles (k, n) of one tensor: the master, moments and
+// Blocks take 32 x 64 tiles (k, n) of one tensor: the master, moments and
 // gradient are read and written along n, and a working copy that is stored
 // transposed (element stride along n > 1, as the forward operand W^T) is
 // written from an LDS tile along k, so every global access is coalesced.
+// Small tiles and a grid of 512 blocks per tensor keep many blocks in flight
+// (one 64 x 64 tile per block left the kernel 13% slower, two 45%).
 template <int T>
 __global__ __launch_bounds__(256) void multi_adam_kernel(const AdamTensor* ts, float lr, float b1, float b2, float eps,
                                                         float c1, float c2) {
-    __shared__ float tile[64][65];
+    constexpr int TK = 32;  // tile rows (k); 64 columns (n)
+    __shared__ float tile[TK][65];
     const AdamTensor d = ts[blockIdx.y];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int tk = (d.K + 63) / 64, tn = (d.N + 63) / 64;
+    const int tk = (d.K + TK - 1) / TK, tn = (d.N + 63) / 64;
+    constexpr int U = 4;  // k rows whose loads are issued together (clamped in range, results masked)
     for (int t = blockIdx.x; t < tk * tn; t += gridDim.x) {
-        const int k0 = (t / tn) * 64, n0 = (t % tn) * 64;
+        const int k0 = (t / tn) * TK, n0 = (t % tn) * 64;
         const int n = n0 + tx;
-        for (int kk = ty; kk < 64; kk += 4) {
-            const int k = k0 + kk;
-            float w = 0.f;
-            if (k < d.K && n < d.N) {
-                const size_t i = (size_t)k * d.N + n;
-                const float g = d.grad[(size_t)k * d.gk + (size_t)n * d.gn];
-                const float m = b1 * d.m[i] + (1.f - b1) * g;
-                const float v = b2 * d.v[i] + (1.f - b2) * g * g;
-                d.m[i] = m;
-                d.v[i] = v;
-                w = d.master[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
-                d.master[i] = w;
-                if (d.out1 && d.s1n == 1) st_t<T>(d.out1, (size_t)k * d.s1k + n, w);
-                if (d.out2 && d.s2n == 1) st_t<T>(d.out2, (size_t)k * d.s2k + n, w);
+        for (int kb = ty; kb < TK; kb += 4 * U) {
+            float g[U], m0[U], v0[U], w0[U];
+            bool ok[U];
+            size_t idx[U];
+            _Pragma("unroll") for (int u = 0; u < U; u++) {
+                const int k = k0 + kb + 4 * u;
+                ok[u] = k < d.K && n < d.N;
+                idx[u] = ok[u] ? (size_t)k * d.N + n : 0;
+                g[u] = d.grad[ok[u] ? (size_t)k * d.gk + (size_t)n * d.gn : 0];
+                m0[u] = d.m[idx[u]];
+                v0[u] = d.v[idx[u]];
+                w0[u] = d.master[idx[u]];
             }
-            tile[kk][tx] = w;
+            _Pragma("unroll") for (int u = 0; u < U; u++) {
+                const int k = k0 + kb + 4 * u;
+                float w = 0.f;
+                if (ok[u]) {
+                    const size_t i = idx[u];
+                    const float m = b1 * m0[u] + (1.f - b1) * g[u];
+                    const float v = b2 * v0[u] + (1.f - b2) * g[u] * g[u];
+                    d.m[i] = m;
+                    d.v[i] = v;
+                    w = w0[u] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+                    d.master[i] = w;
+                    if (d.out1 && d.s1n == 1) st_t<T>(d.out1, (size_t)k * d.s1k + n, w);
+                    if (d.out2 && d.s2n == 1) st_t<T>(d.out2, (size_t)k * d.s2k + n, w);
+                }
+                tile[kb + 4 * u][tx] = w;
+            }
         }
         const bool t1 = d.out1 && d.s1n != 1, t2 = d.out2 && d.s2n != 1;
         if (t1 || t2) {
             __syncthreads();
-            for (int nn = ty; nn < 64; nn += 4) {
-                const int k = k0 + tx, n2 = n0 + nn;
+            // a wave writes 64 / TK columns per pass, TK consecutive k each
+            const int kl = tx % TK, k = k0 + kl;
+            for (int nn = ty * (64 / TK) + tx / TK; nn < 64; nn += 256 / TK) {
+                const int n2 = n0 + nn;
                 if (k < d.K && n2 < d.N) {
-                    if (t1) st_t<T>(d.out1, (size_t)k * d.s1k + (size_t)n2 * d.s1n, tile[tx][nn]);
-                    if (t2) st_t<T>(d.out2, (size_t)k * d.s2k + (size_t)n2 * d.s2n, tile[tx][nn]);
+                    if (t1) st_t<T>(d.out1, (size_t)k * d.s1k + (size_t)n2 * d.s1n, tile[kl][nn]);
+                    if (t2) st_t<T>(d.out2, (size_t)k * d.s2k + (size_t)n2 * d.s2n, tile[kl][nn]);
                 }
             }
         }
@@ -634,7 +659,7 @@ bool launch_scatter_l1(const ScatterArgs& a, int t, int domain, int chunks, hipS
 
 void launch_multi_adam(const AdamTensor* d_tensors, int count, float lr, float b1, float b2, float eps, float c1,
                        float c2, int t, hipStream_t s) {
-    const dim3 grid(256, count);
+    const dim3 grid(512, count);
     if (t == 0) hipLaunchKernelGGL(multi_adam_kernel<0>, grid, dim3(256), 0, s, d_tensors, lr, b1, b2, eps, c1, c2);
     else hipLaunchKernelGGL(multi_adam_kernel<1>, grid, dim3(256), 0, s, d_tensors, lr, b1, b2, eps, c1, c2);
 }
