@@ -168,8 +168,8 @@ def main():
         return e0.elapsed_time(e1) / steps  # ms per step
 
     def median_step(model, reps=20):
-        """Median of `reps` individually event-timed steps (the survey's timing
-        protocol; `value` keeps the driver's mean over the timed steps)."""
+        """Median of `reps` individually event-timed steps (a second view of the
+        step time; `value` keeps the mean over the timed steps)."""
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in ev:
             a.record(stream)

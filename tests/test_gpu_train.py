@@ -193,7 +193,7 @@ def test_learned_15puzzle_residual_over_manhattan(tmp_path):
     """The paper's sliding-tile heuristic construction: a network trained on the
     difference between a PDB and Manhattan distance, served as MD + floor(y -
     delta).  The label is the 6-6-3 additive PDB (admissible, so it is the
-    over-estimate judge); delta is set on one held-out set so that h exceeds the
+    reference for over-estimates); delta is set on one held-out set so that h exceeds the
     label on at most 0.1% of it, and checked on another."""
     groups = [range(1, 7), range(7, 13), range(13, 16)]
     pdb = hb.Pdb(groups=groups)
